@@ -1,0 +1,217 @@
+/*
+ * anova.h -- C ABI of the ANOVA-kernel fast summation library (gfx950 / HIP).
+ *
+ * The library applies the shifted kernel matrix (K + beta I) of kernel ridge
+ * regression, where K is the extended Gaussian ANOVA kernel
+ *
+ *     K_ij = sum_{l=1}^{P} eta_l exp(-||x_i^{W_l} - x_j^{W_l}||^2 / ell^2)
+ *
+ * (Sec. 3, eq. extended_Gaussian_ANOVA_kernel; Sec. 5, combined kernel
+ * K = eta_1 K_1 + ... + eta_P K_P), each feature window W_l holding one, two
+ * or three features (Sec. 4.1: every NFFT acts in dimension at most 3).  Each
+ * window's product is computed by NFFT-based fast summation (Sec. 4.2, eq.
+ * fastsum; K alpha ~ Phi D Phi^* alpha, Sec. 4.3): window-function spreading
+ * onto an oversampled grid, a d_A-dimensional FFT, multiplication by the
+ * regularised kernel's Fourier coefficients, an inverse FFT and gathering
+ * back to the points.  The product runs inside conjugate gradients for the
+ * system (K + beta I) alpha = y (Sec. 2, normal equation and CG).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Device pointers are plain HIP device addresses (hipMalloc'd or any
+ *   allocator's, e.g. a torch CUDA tensor's data_ptr()).  Host pointers are
+ *   marked "host".
+ * - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ * - Vectors of several right-hand sides are column-major N x nrhs arrays
+ *   with leading dimension ld >= N (element (i, c) at [c*ld + i]), float64.
+ * - X is N x d row-major float64 with leading dimension ldx >= d
+ *   (feature t of point i at [i*ldx + t]).
+ * - Every call returns an anova_status; nothing aborts and no exception
+ *   crosses the ABI.  On any status other than ANOVA_OK or
+ *   ANOVA_E_NOT_CONVERGED the contents of output arrays are unspecified, and
+ *   anova_last_error() returns a message (thread-local).
+ * - A plan is used by one stream at a time; calls on one plan from several
+ *   host threads or streams concurrently race.
+ */
+#ifndef ANOVA_H
+#define ANOVA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct anova_plan_s *anova_plan_t;
+typedef struct anova_cg_s *anova_cg_t;
+
+typedef enum {
+    ANOVA_OK = 0,
+    ANOVA_E_INVALID = 1,        /* bad argument (see each call) */
+    ANOVA_E_NOMEM = 2,          /* device or host allocation failed */
+    ANOVA_E_HIP = 3,            /* a HIP runtime call failed */
+    ANOVA_E_NOT_CONVERGED = 4,  /* CG reached maxit; the iterate is returned */
+    ANOVA_E_BREAKDOWN = 5,      /* CG: p^T A p <= 0 or a non-finite value */
+    ANOVA_E_ACCURACY = 6        /* fixed (M, m, n) cannot meet target_err */
+} anova_status;
+
+typedef enum {
+    ANOVA_FP64 = 0,        /* spreading, FFT and gathering in float64 */
+    ANOVA_FP32_NFFT = 1    /* spreading, FFT and gathering in float32;
+                              output accumulation and CG stay float64 */
+} anova_precision;
+
+/* One feature window W_l (Sec. 3, eq. index_window): d_A in {1,2,3},
+ * 0-based feature indices feat[0..d_A-1] (distinct, < d), weight eta_l
+ * (Sec. 5; equal weights 1/P in the paper, any finite weights here). */
+typedef struct {
+    int32_t d_A;
+    int32_t feat[3];
+    double eta;
+} anova_window;
+
+/* Plan parameters.  Zero in M, m, n or h means "choose": the plan then picks
+ * the cheapest (M, m, n) whose per-entry error estimate (images + truncation
+ * + window aliasing + rounding, weighted by eta) is at most target_err. */
+typedef struct {
+    double ell;          /* Gaussian width: exp(-||r||^2 / ell^2), ell > 0 */
+    int32_t precision;   /* anova_precision */
+    int32_t M;           /* bandwidth: frequencies -M/2..M/2-1 per dimension
+                            (Sec. 4.1 index set), even, 4..256 */
+    int32_t m;           /* window half-width in grid points, 2..8 */
+    int32_t n;           /* oversampled FFT length per dimension: a power of
+                            two, 8..256, n >= M */
+    double h;            /* period of the regularised kernel (Sec. 4.2) */
+    double target_err;   /* 0 -> 1e-4 (FP32_NFFT) or 1e-9 (FP64) */
+    int32_t center;      /* 0: centre each window's bounding box before
+                            scaling by 1/h; 1: scale only, x~ = x/h (Sec. 4.2) */
+    int32_t reserved;    /* must be 0 */
+} anova_params;
+
+/* What a plan chose for window l (host struct filled by anova_plan_query). */
+typedef struct {
+    int32_t d_A, M, n, m;
+    double h;
+    double center[3];       /* the point mapped to the torus origin */
+    double extent;          /* largest coordinate range over the window's features */
+    double err_images;      /* per-entry error estimates, already times eta_l */
+    double err_trunc;
+    double err_window;
+    double err_round;
+    double err_total;
+    int64_t n_tiles;        /* grid tiles holding at least one point */
+    int64_t n_subproblems;  /* work items of the spreading / gathering launches */
+} anova_window_info;
+
+typedef struct {
+    int32_t iters;          /* CG iterations taken */
+    int32_t converged;      /* 1 if ||r|| <= tol ||y|| */
+    double relres;          /* recursive residual norm / ||y|| */
+    double true_relres;     /* ||y - (K~ + beta I) alpha|| / ||y|| recomputed at exit */
+} krr_cg_info;
+
+/*
+ * Build a plan for the points X (device, N x d row-major float64, ldx >= d)
+ * and the windows win[0..P-1] (host).  The plan copies what it needs (sorted
+ * grid coordinates, permutations, Fourier multipliers) and does not keep X.
+ * It owns all its device memory until anova_plan_destroy.
+ * Steps (Sec. 4.2): period h with h >= 2 * extent, scaled nodes x~ = (x-c)/h
+ * on the torus [-1/2, 1/2)^d_A, Fourier coefficients of the periodised
+ * kernel from the FFT of M equidistant samples per dimension, divided by the
+ * squared window transform; points binned and sorted by grid tile.
+ * Synchronises `stream`.
+ * Errors: ANOVA_E_INVALID for out == NULL, X == NULL, N < 1, N > 2^31-1,
+ * d < 1, ldx < d, P < 1, P > 64, d_A not in {1,2,3}, a feature index out of
+ * range or repeated inside one window, a non-finite eta or X, ell <= 0,
+ * odd M, n not a power of two or n < M, m out of range, reserved != 0.
+ * ANOVA_E_ACCURACY when fixed parameters miss target_err.
+ */
+anova_status anova_fastsum_plan(anova_plan_t *out, const double *X, int64_t N, int32_t d,
+                                int64_t ldx, const anova_window *win, int32_t P,
+                                const anova_params *prm, void *stream);
+
+/*
+ * out = (K~ + beta I) alpha for nrhs columns (device arrays, column-major,
+ * leading dimension ld >= N; alpha and out must not overlap).  K~ is the
+ * fast-summation approximation of K (Sec. 4.3, K alpha ~ Phi D Phi^* alpha,
+ * summed over windows with weights eta_l, Sec. 5); the shift beta alpha is
+ * added exactly.  Asynchronous on `stream`.
+ * Errors: ANOVA_E_INVALID for a NULL plan/pointer, nrhs < 1, ld < N.
+ */
+anova_status anova_matvec(anova_plan_t plan, const double *alpha, double *out, int32_t nrhs,
+                          int64_t ld, double beta, void *stream);
+
+/*
+ * Solve (K~ + beta I) alpha = y by conjugate gradients (Sec. 2), one
+ * independent recurrence per column, no preconditioner.  x0 = 0; a column
+ * stops when ||r||_2 <= tol ||y||_2; every 50 iterations, and at exit, the
+ * residual is recomputed as y - (K~ + beta I) alpha (residual replacement).
+ * Dot products, vector updates and the residual recomputation are float64.
+ * y, alpha: device, column-major N x nrhs, leading dimension ld.
+ * info: host array of nrhs entries (may be NULL).  Synchronises `stream`.
+ * Returns ANOVA_E_NOT_CONVERGED if some column reached maxit (alpha then
+ * holds the last iterate), ANOVA_E_BREAKDOWN on p^T A p <= 0 or NaN.
+ * Errors: ANOVA_E_INVALID for beta <= 0, tol < 0, maxit < 1, nrhs < 1, ld < N.
+ */
+anova_status krr_cg_solve(anova_plan_t plan, const double *y, double *alpha, int32_t nrhs,
+                          int64_t ld, double beta, double tol, int32_t maxit,
+                          krr_cg_info *info, void *stream);
+
+/* Free every resource of the plan (synchronises the device).  NULL is a no-op. */
+anova_status anova_plan_destroy(anova_plan_t plan);
+
+/* Message for the last non-OK status on the calling thread ("" if none).
+ * The pointer stays valid until the next call on this thread. */
+const char *anova_last_error(void);
+
+/* Parameters and error estimates chosen for window l (0 <= l < P).  Host. */
+anova_status anova_plan_query(anova_plan_t plan, int32_t l, anova_window_info *info);
+
+/* Number of points and windows of a plan (host outputs, may be NULL). */
+anova_status anova_plan_shape(anova_plan_t plan, int64_t *N, int32_t *P, int32_t *precision);
+
+/*
+ * Stage entry points for window l (Sec. 4.1 and 4.2), exposing the three
+ * steps of one window's fast summation separately.  The grid is the
+ * oversampled n^d_A real grid of the window, float32 for ANOVA_FP32_NFFT
+ * plans and float64 for ANOVA_FP64 plans, laid out with the first feature of
+ * the window fastest: element (u_1, .., u_dA) at u_1 + n u_2 + n^2 u_3.  Grid
+ * point u sits at torus position u/n - 1/2 per dimension.
+ *
+ * anova_stage_spread:   grid = sum_j alpha_j prod_t phi(n x~_j^t - u_t)
+ *     (first step of the adjoint NFFT, eq. adjnfft), alpha a device float64
+ *     vector of N entries in the caller's point order.  Overwrites grid.
+ * anova_stage_convolve: grid <- inverse DFT of (b~_k * DFT(grid)_k) with
+ *     b~_k = b_k / prod_t phihat(k_t/n)^2 for k in the index set, 0 outside
+ *     (FFT + multiplication by the kernel coefficients + inverse FFT, eq.
+ *     fastsum).  In place.  eta_l is not applied here.
+ * anova_stage_gather:   out_i += eta_l sum_u grid_u prod_t phi(n x~_i^t - u_t)
+ *     (last step of the NFFT, eq. nfft), out a device float64 vector of N
+ *     entries in the caller's point order.
+ * All three are asynchronous on `stream`.
+ */
+anova_status anova_stage_spread(anova_plan_t plan, int32_t l, const double *alpha, void *grid,
+                                void *stream);
+anova_status anova_stage_convolve(anova_plan_t plan, int32_t l, void *grid, void *stream);
+anova_status anova_stage_gather(anova_plan_t plan, int32_t l, const void *grid, double *out,
+                                void *stream);
+
+/*
+ * Per-stage device-time accounting, for benchmarks.  While enabled, every
+ * anova_matvec and krr_cg_solve matvec records HIP events on the caller's
+ * stream around each launch of the four stage kinds, in this order:
+ * 0 fold (adding the spread tile regions into the grid), 1 spread into tile
+ * regions, 2 convolve (FFT, multiply, inverse FFT; one launch per axis),
+ * 3 gather.  anova_plan_stage_times synchronises,
+ * writes the accumulated milliseconds and launch counts per kind (host
+ * arrays of 4) and resets the counters.  Enabling adds a few microseconds of
+ * event overhead per launch; disabled by default.
+ */
+anova_status anova_plan_set_timing(anova_plan_t plan, int32_t enable);
+anova_status anova_plan_stage_times(anova_plan_t plan, double *ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ANOVA_H */

@@ -1,0 +1,277 @@
+"""Thin ctypes binding over ``libanova.so`` (the C ABI in ``include/anova.h``).
+
+Argument marshalling only: every step of the fast summation and of CG runs
+in the library's HIP kernels.  Device arrays are torch CUDA tensors (used for
+device memory and streams only).  There is no CPU fallback: if the library is
+missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libanova.so")
+
+ANOVA_OK = 0
+ANOVA_E_INVALID = 1
+ANOVA_E_NOMEM = 2
+ANOVA_E_HIP = 3
+ANOVA_E_NOT_CONVERGED = 4
+ANOVA_E_BREAKDOWN = 5
+ANOVA_E_ACCURACY = 6
+STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_HIP", 4: "E_NOT_CONVERGED",
+                5: "E_BREAKDOWN", 6: "E_ACCURACY"}
+
+ANOVA_FP64 = 0
+ANOVA_FP32_NFFT = 1
+
+
+class anova_window(ctypes.Structure):
+    _fields_ = [("d_A", ctypes.c_int32), ("feat", ctypes.c_int32 * 3), ("eta", ctypes.c_double)]
+
+
+class anova_params(ctypes.Structure):
+    _fields_ = [("ell", ctypes.c_double), ("precision", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("h", ctypes.c_double),
+                ("target_err", ctypes.c_double), ("center", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class anova_window_info(ctypes.Structure):
+    _fields_ = [("d_A", ctypes.c_int32), ("M", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("h", ctypes.c_double), ("center", ctypes.c_double * 3),
+                ("extent", ctypes.c_double), ("err_images", ctypes.c_double),
+                ("err_trunc", ctypes.c_double), ("err_window", ctypes.c_double),
+                ("err_round", ctypes.c_double), ("err_total", ctypes.c_double),
+                ("n_tiles", ctypes.c_int64), ("n_subproblems", ctypes.c_int64)]
+
+
+class krr_cg_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("relres", ctypes.c_double), ("true_relres", ctypes.c_double)]
+
+
+class AnovaError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+VP = ctypes.c_void_p
+
+
+def load():
+    """Load the in-tree library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2111_10140_amd/build.py "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sigs = {
+        "anova_fastsum_plan": [ctypes.POINTER(VP), VP, i64, i32, i64, ctypes.POINTER(anova_window),
+                               i32, ctypes.POINTER(anova_params), VP],
+        "anova_matvec": [VP, VP, VP, i32, i64, dbl, VP],
+        "krr_cg_solve": [VP, VP, VP, i32, i64, dbl, dbl, i32, ctypes.POINTER(krr_cg_info), VP],
+        "anova_plan_destroy": [VP],
+        "anova_plan_query": [VP, i32, ctypes.POINTER(anova_window_info)],
+        "anova_plan_shape": [VP, ctypes.POINTER(i64), ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "anova_stage_spread": [VP, i32, VP, VP, VP],
+        "anova_stage_convolve": [VP, i32, VP, VP],
+        "anova_stage_gather": [VP, i32, VP, VP, VP],
+        "anova_plan_set_timing": [VP, i32],
+        "anova_plan_stage_times": [VP, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
+    }
+    for name, args in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.anova_last_error.argtypes = []
+    lib.anova_last_error.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def anova_last_error() -> str:
+    return load().anova_last_error().decode()
+
+
+def _check(st: int, allow=(ANOVA_OK,)) -> int:
+    if st not in allow:
+        raise AnovaError(st, anova_last_error())
+    return st
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _dev_f64(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64):
+        raise TypeError(f"{name} must be a CUDA float64 tensor")
+    return t
+
+
+def _colmajor(t, name, N):
+    """(N,) or (N, nrhs) tensor stored column-major: returns (ptr, nrhs, ld)."""
+    _dev_f64(t, name)
+    if t.dim() == 1:
+        if t.stride(0) != 1 or t.shape[0] != N:
+            raise ValueError(f"{name} must be a contiguous vector of N entries")
+        return t.data_ptr(), 1, N
+    if t.dim() != 2 or t.shape[0] != N or t.stride(0) != 1:
+        raise ValueError(f"{name} must be (N, nrhs) column-major (stride(0) == 1)")
+    return t.data_ptr(), t.shape[1], max(t.stride(1), N)
+
+
+def make_windows(windows) -> "ctypes.Array":
+    P = len(windows)
+    arr = (anova_window * P)()
+    for l, w in enumerate(windows):
+        feat = tuple(w.feat) if hasattr(w, "feat") else tuple(w[0])
+        eta = w.eta if hasattr(w, "eta") else w[1]
+        arr[l].d_A = len(feat)
+        for t, f in enumerate(feat):
+            arr[l].feat[t] = int(f)
+        arr[l].eta = float(eta)
+    return arr
+
+
+def make_params(ell: float, precision: int = ANOVA_FP32_NFFT, M: int = 0, m: int = 0, n: int = 0,
+                h: float = 0.0, target_err: float = 0.0, center: int = 0) -> anova_params:
+    p = anova_params()
+    p.ell, p.precision, p.M, p.m, p.n = float(ell), int(precision), int(M), int(m), int(n)
+    p.h, p.target_err, p.center, p.reserved = float(h), float(target_err), int(center), 0
+    return p
+
+
+@dataclass
+class WindowInfo:
+    d_A: int
+    M: int
+    n: int
+    m: int
+    h: float
+    center: tuple
+    extent: float
+    err_images: float
+    err_trunc: float
+    err_window: float
+    err_round: float
+    err_total: float
+    n_tiles: int
+    n_subproblems: int
+
+
+class Plan:
+    """Owning wrapper over an anova_plan_t."""
+
+    def __init__(self, handle: int, N: int, P: int, precision: int):
+        self.handle = handle
+        self.N, self.P, self.precision = N, P, precision
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    def destroy(self):
+        if self.handle:
+            _check(load().anova_plan_destroy(self.handle))
+            self.handle = None
+
+    def info(self, l: int) -> WindowInfo:
+        r = anova_window_info()
+        _check(load().anova_plan_query(self.handle, l, ctypes.byref(r)))
+        return WindowInfo(r.d_A, r.M, r.n, r.m, r.h, tuple(r.center), r.extent, r.err_images,
+                          r.err_trunc, r.err_window, r.err_round, r.err_total, r.n_tiles,
+                          r.n_subproblems)
+
+    def set_timing(self, enable: bool) -> None:
+        _check(load().anova_plan_set_timing(self.handle, 1 if enable else 0))
+
+    def stage_times(self):
+        """{kind: (total_ms, launches)} for fold/spread/convolve/gather; resets."""
+        ms = (ctypes.c_double * 4)()
+        cnt = (ctypes.c_int64 * 4)()
+        _check(load().anova_plan_stage_times(self.handle, ms, cnt))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(["fold", "spread", "convolve", "gather"])}
+
+    def err_estimate(self) -> float:
+        return sum(self.info(l).err_total for l in range(self.P))
+
+
+def anova_fastsum_plan(X, windows, params: anova_params, stream=None) -> Plan:
+    """Plan for device points X ((N, d) row-major CUDA float64)."""
+    _dev_f64(X, "X")
+    if X.dim() != 2 or X.stride(1) != 1:
+        raise ValueError("X must be (N, d) row-major")
+    N, d = X.shape
+    wins = make_windows(windows)
+    h = VP()
+    st = load().anova_fastsum_plan(ctypes.byref(h), X.data_ptr(), N, d, X.stride(0), wins,
+                                   len(windows), ctypes.byref(params), _stream(stream))
+    _check(st)
+    return Plan(h.value, N, len(windows), params.precision)
+
+
+def anova_matvec(plan: Plan, alpha, out, beta: float, stream=None) -> None:
+    """out = (K~ + beta I) alpha (asynchronous on the stream)."""
+    pa, nrhs, lda = _colmajor(alpha, "alpha", plan.N)
+    po, nrhs2, ldo = _colmajor(out, "out", plan.N)
+    if nrhs != nrhs2 or lda != ldo:
+        raise ValueError("alpha and out must have the same shape and leading dimension")
+    _check(load().anova_matvec(plan.handle, pa, po, nrhs, lda, float(beta), _stream(stream)))
+
+
+def krr_cg_solve(plan: Plan, y, alpha, beta: float, tol: float, maxit: int, stream=None,
+                 allow_not_converged: bool = False):
+    """Solve (K~ + beta I) alpha = y; returns a list of krr_cg_info per column."""
+    py, nrhs, ldy = _colmajor(y, "y", plan.N)
+    pa, nrhs2, lda = _colmajor(alpha, "alpha", plan.N)
+    if nrhs != nrhs2 or ldy != lda:
+        raise ValueError("y and alpha must have the same shape and leading dimension")
+    info = (krr_cg_info * nrhs)()
+    st = load().krr_cg_solve(plan.handle, py, pa, nrhs, lda, float(beta), float(tol), int(maxit),
+                             info, _stream(stream))
+    allow = (ANOVA_OK, ANOVA_E_NOT_CONVERGED) if allow_not_converged else (ANOVA_OK,)
+    _check(st, allow)
+    return [dict(iters=i.iters, converged=bool(i.converged), relres=i.relres,
+                 true_relres=i.true_relres, status=STATUS_NAMES[st]) for i in info]
+
+
+def anova_plan_destroy(plan: Plan) -> None:
+    plan.destroy()
+
+
+def grid_tensor(plan: Plan, l: int):
+    """A zeroed device tensor with the grid shape of window l (x fastest)."""
+    import torch
+    inf = plan.info(l)
+    dt = torch.float64 if plan.precision == ANOVA_FP64 else torch.float32
+    return torch.zeros((inf.n,) * inf.d_A, dtype=dt, device="cuda")
+
+
+def anova_stage_spread(plan: Plan, l: int, alpha, grid, stream=None) -> None:
+    pa, _, _ = _colmajor(alpha, "alpha", plan.N)
+    _check(load().anova_stage_spread(plan.handle, l, pa, grid.data_ptr(), _stream(stream)))
+
+
+def anova_stage_convolve(plan: Plan, l: int, grid, stream=None) -> None:
+    _check(load().anova_stage_convolve(plan.handle, l, grid.data_ptr(), _stream(stream)))
+
+
+def anova_stage_gather(plan: Plan, l: int, grid, out, stream=None) -> None:
+    po, _, _ = _colmajor(out, "out", plan.N)
+    _check(load().anova_stage_gather(plan.handle, l, grid.data_ptr(), po, _stream(stream)))

@@ -1,0 +1,756 @@
+// Plan construction and the C ABI around one matvec (host side).
+//
+// For each feature window the plan fixes the fast-summation parameters of
+// Sec. 4.2: the period h (h >= 2 * extent, so differences of scaled nodes stay
+// inside one period), the bandwidth M of the index set I_M (Sec. 4.1), the
+// oversampled FFT length n and the window half-width m.  The kernel's Fourier
+// coefficients b_k are the DFT of M equidistant samples of the h-periodised
+// Gaussian (Sec. 4.2); they are divided by the squared window transform so
+// that one multiplication performs both deconvolutions.  Points are binned
+// into grid cells and sorted by grid tile for the spreading and gathering
+// kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <limits>
+#include <numeric>
+
+#include "anova_internal.h"
+
+namespace anova {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+const char *get_error() { return g_last_error.c_str(); }
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+
+// ------------------------------------------------------------- special functions
+// Modified Bessel function I0 by its power series sum ((x/2)^2k / (k!)^2):
+// all terms positive, so the sum is accurate to rounding for the arguments
+// used here (0 <= x <= 60).
+double bessel_i0(double x) {
+    const double q = 0.25 * x * x;
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k < 500; ++k) {
+        term *= q / ((double)k * (double)k);
+        sum += term;
+        if (term < 1e-17 * sum) break;
+    }
+    return sum;
+}
+
+// Kaiser-Bessel window in grid units, phi0(t) = I0(b sqrt(1-(t/m)^2)) for
+// |t| <= m, 0 outside, and its continuous Fourier transform
+// 2m sinh(s)/s with s = sqrt(b^2 - (2 pi m xi)^2) (sin(s)/s past the root).
+double kb_phi(double t, int m, double b) {
+    if (std::fabs(t) > m) return 0.0;
+    const double u = 1.0 - (t / m) * (t / m);
+    return bessel_i0(b * std::sqrt(std::max(u, 0.0)));
+}
+double kb_phihat(double xi, int m, double b) {
+    const double q = b * b - (2.0 * kPi * m * xi) * (2.0 * kPi * m * xi);
+    if (q > 1e-12) {
+        const double s = std::sqrt(q);
+        return 2.0 * m * std::sinh(s) / s;
+    }
+    if (q < -1e-12) {
+        const double s = std::sqrt(-q);
+        return 2.0 * m * std::sin(s) / s;
+    }
+    return 2.0 * m;
+}
+
+// ------------------------------------------------------------- kernel coefficients
+// 1-D Fourier coefficients of the h-periodised Gaussian exp(-r^2/ell^2)
+// (Poisson summation); used only for the plan's error estimates.
+double gauss_coeff(double k, double ell, double h) {
+    const double a = kPi * ell * k / h;
+    return std::sqrt(kPi) * ell / h * std::exp(-a * a);
+}
+
+// h-periodised 1-D Gaussian: sum over images r + j h.
+double periodized_gauss(double r, double ell, double h) {
+    double s = 0.0;
+    const int J = 2 + (int)std::ceil(8.0 * ell / h);
+    for (int j = -J; j <= J; ++j) {
+        const double z = (r + j * h) / ell;
+        s += std::exp(-z * z);
+    }
+    return s;
+}
+
+// b1[k + M/2], k = -M/2..M/2-1: DFT of the M equidistant samples
+// kappa~(j h / M), j = -M/2..M/2-1, divided by M.  The periodised Gaussian is
+// a product over dimensions, and so is its sampled DFT: b_k = prod_t b1[k_t].
+// The samples are even in j, so the coefficients are real.
+std::vector<double> sampled_coeffs_1d(int M, double ell, double h) {
+    std::vector<double> samp(M), b(M);
+    for (int j = -M / 2; j < M / 2; ++j) samp[j + M / 2] = periodized_gauss(j * h / M, ell, h);
+    for (int k = -M / 2; k < M / 2; ++k) {
+        long double acc = 0.0L;
+        for (int j = -M / 2; j < M / 2; ++j) {
+            const long long kj = ((long long)k * j) % M;
+            acc += (long double)samp[j + M / 2] *
+                   std::cos(2.0L * (long double)kPi * (long double)kj / (long double)M);
+        }
+        b[k + M / 2] = (double)(acc / M);
+    }
+    return b;
+}
+
+// ------------------------------------------------------------- error model
+// Per-entry error estimates of one window's approximation K~_ij - K_ij for
+// |x_i - x_j| <= D per coordinate, before the weight eta.
+double est_images(double h, double D, double ell, int dA) {
+    const double g = h - D;
+    if (g <= 0) return std::numeric_limits<double>::infinity();
+    return 2.0 * dA * std::exp(-(g * g) / (ell * ell));
+}
+
+// (S' + T)^d - S'^d with T the tail of the coefficient sum outside
+// |k| < M/2, doubled for the aliasing of the sampled coefficients.
+double est_trunc(int M, double h, double ell, int dA) {
+    double inner = 0.0, tail = 0.0;
+    for (int k = -(M / 2 - 1); k <= M / 2 - 1; ++k) inner += gauss_coeff(k, ell, h);
+    for (int k = M / 2; k < M / 2 + 100000; ++k) {
+        const double c = gauss_coeff(k, ell, h);
+        tail += 2.0 * c;
+        if (c < 1e-300 || c < 1e-18 * tail) break;
+    }
+    double d = 0.0;  // binomial expansion without cancellation
+    double binom = 1.0;
+    for (int j = 1; j <= dA; ++j) {
+        binom = binom * (dA - j + 1) / j;
+        d += binom * std::pow(inner, dA - j) * std::pow(tail, j);
+    }
+    return 2.0 * d;
+}
+
+// Window aliasing: for each kept frequency the relative weight of its
+// aliases k + r n in the window transform, plus the jump of the truncated
+// window at |t| = m; combined over dimensions and over the adjoint and the
+// forward transform, weighted by the kernel coefficients.
+double est_window(int M, int n, int m, double ell, double h, int dA) {
+    const double b = kPi * m * (2.0 - (double)M / n);
+    const double i0b = bessel_i0(b);
+    const double jump = 1.0 / i0b;
+    const std::vector<double> b1 = sampled_coeffs_1d(M, ell, h);
+    double B = 0.0, BA = 0.0;
+    for (int k = -(M / 2 - 1); k <= M / 2 - 1; ++k) {
+        const double c = std::fabs(b1[k + M / 2]);
+        const double ph0 = kb_phihat((double)k / n, m, b) / i0b;
+        double alias = 0.0;
+        for (int r = 1; r <= 8; ++r) {
+            alias += std::fabs(kb_phihat((double)(k + r * n) / n, m, b)) / i0b;
+            alias += std::fabs(kb_phihat((double)(k - r * n) / n, m, b)) / i0b;
+        }
+        alias += 2.0 * jump;
+        B += c;
+        BA += c * alias / ph0;
+    }
+    double d = 0.0, binom = 1.0;
+    for (int j = 1; j <= dA; ++j) {
+        binom = binom * (dA - j + 1) / j;
+        d += binom * std::pow(B, dA - j) * std::pow(BA, j);
+    }
+    return 2.0 * d;
+}
+
+double est_round(int precision, int n, int m, int dA) {
+    const double eps = precision == ANOVA_FP64 ? 1.1e-16 : 6.0e-8;
+    return eps * 8.0 * (dA * std::log2((double)n) + 2.0 * m);
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// ------------------------------------------------------------- window polynomials
+// Fit phi0(f + m - 1 - a) / I0(b), f in [0,1), for a = 0..2m-1, by
+// interpolation at Chebyshev points in z = 2f-1; returns monomial
+// coefficients in z ([a][deg+1]) with the smallest degree whose maximum
+// error on a fine sample is below tol.
+std::vector<double> fit_window_polys(int m, double b, double tol, int &deg_out) {
+    const int W = 2 * m;
+    const double i0b = bessel_i0(b);
+    for (int deg = 4; deg <= kMaxPolyDeg; ++deg) {
+        const int npts = deg + 1;
+        std::vector<double> coef((size_t)W * npts);
+        double worst = 0.0;
+        for (int a = 0; a < W; ++a) {
+            // Chebyshev coefficients by the discrete cosine sum at Chebyshev nodes
+            std::vector<double> fz(npts), cheb(npts, 0.0);
+            for (int i = 0; i < npts; ++i) {
+                const double z = std::cos(kPi * (i + 0.5) / npts);
+                const double f = 0.5 * (z + 1.0);
+                fz[i] = kb_phi(f + m - 1 - a, m, b) / i0b;
+            }
+            for (int j = 0; j < npts; ++j) {
+                double s = 0.0;
+                for (int i = 0; i < npts; ++i) s += fz[i] * std::cos(kPi * j * (i + 0.5) / npts);
+                cheb[j] = (j == 0 ? 1.0 : 2.0) * s / npts;
+            }
+            // convert sum_j cheb_j T_j(z) to monomials with T_{j+1} = 2z T_j - T_{j-1}
+            std::vector<double> Tm1(npts, 0.0), T0(npts, 0.0), T1(npts, 0.0), mono(npts, 0.0);
+            T0[0] = 1.0;
+            for (int i = 0; i < npts; ++i) mono[i] += cheb[0] * T0[i];
+            if (npts > 1) {
+                T1[1] = 1.0;
+                for (int i = 0; i < npts; ++i) mono[i] += cheb[1] * T1[i];
+            }
+            for (int j = 2; j < npts; ++j) {
+                std::vector<double> T2(npts, 0.0);
+                for (int i = 0; i < npts; ++i) {
+                    if (i > 0) T2[i] += 2.0 * T1[i - 1];
+                    T2[i] -= T0[i];
+                }
+                for (int i = 0; i < npts; ++i) mono[i] += cheb[j] * T2[i];
+                T0 = T1;
+                T1 = T2;
+            }
+            for (int i = 0; i < npts; ++i) coef[(size_t)a * npts + i] = mono[i];
+            // check
+            for (int s = 0; s <= 64; ++s) {
+                const double f = s / 64.0 * (1.0 - 1e-12);
+                const double z = 2.0 * f - 1.0;
+                double v = 0.0;
+                for (int i = deg; i >= 0; --i) v = v * z + mono[i];
+                const double ref = kb_phi(f + m - 1 - a, m, b) / i0b;
+                worst = std::max(worst, std::fabs(v - ref));
+            }
+        }
+        if (worst <= tol || deg == kMaxPolyDeg) {
+            deg_out = deg;
+            return coef;
+        }
+    }
+    deg_out = kMaxPolyDeg;
+    return {};
+}
+
+// ------------------------------------------------------------- parameter choice
+struct Choice {
+    double h;
+    int M, n, m;
+    double e_img, e_trunc, e_win, e_round;
+};
+
+Choice choose(const anova_params &prm, double D, int dA, double budget, int64_t N) {
+    Choice c{};
+    const int prec = prm.precision;
+    // period
+    if (prm.h > 0) {
+        c.h = prm.h;
+    } else {
+        const double r = std::max(budget * 0.1, 1e-300);
+        c.h = std::max(2.0 * D, D + prm.ell * std::sqrt(std::log(std::max(2.0 * dA / r, 1.0001))));
+        if (c.h <= 0) c.h = 1.0;
+    }
+    c.e_img = est_images(c.h, D, prm.ell, dA);
+    const bool fixed = prm.M > 0 && prm.m > 0 && prm.n > 0;
+    if (fixed) {
+        c.M = prm.M; c.n = prm.n; c.m = prm.m;
+    } else {
+        // search: cheapest (n, M, m) meeting the budget; unspecified fields free
+        double best = std::numeric_limits<double>::infinity();
+        const double rest = std::max(budget - c.e_img, budget * 0.5);
+        for (int n = 8; n <= 256; n *= 2) {
+            if (prm.n > 0 && n != prm.n) continue;
+            const double er = est_round(prec, n, 8, dA);
+            const double avail = rest - er;
+            if (avail <= 0) continue;
+            int M = prm.M;
+            if (M <= 0) {
+                for (M = 4; M <= n; M += 2)
+                    if (est_trunc(M, c.h, prm.ell, dA) <= 0.35 * avail) break;
+                if (M > n) continue;
+            }
+            if (M > n) continue;
+            if (prm.M <= 0 && M * 5 > n * 4) continue;  // keep sigma = n/M >= 1.25
+            for (int m = 2; m <= 8; ++m) {
+                if (prm.m > 0 && m != prm.m) continue;
+                if (2 * m > n) break;
+                const double ew = est_window(M, n, m, prm.ell, c.h, dA);
+                if (ew > 0.65 * avail) continue;
+                double cost = (double)N * std::pow(2.0 * m, dA) +
+                              4.0 * std::pow((double)n, dA) * std::log2((double)n) * dA;
+                if (cost < best) {
+                    best = cost;
+                    c.M = M; c.n = n; c.m = m;
+                }
+                break;
+            }
+        }
+        if (!std::isfinite(best))
+            throw Error{ANOVA_E_ACCURACY,
+                        "no (M, n, m) with n <= 256 and m <= 8 meets target_err for this window"};
+    }
+    c.e_trunc = est_trunc(c.M, c.h, prm.ell, dA);
+    c.e_win = est_window(c.M, c.n, c.m, prm.ell, c.h, dA);
+    c.e_round = est_round(prec, c.n, c.m, dA);
+    return c;
+}
+
+template <typename T>
+void upload(DevBuf &buf, const std::vector<T> &v) {
+    size_t bytes = v.size() * sizeof(T);
+    bytes = (bytes + 255) & ~(size_t)255;
+    buf.alloc(bytes);
+    if (!v.empty()) ANOVA_HIP_CHECK(hipMemcpy(buf.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// For every tile of the n^dA grid (tile edge `tile`, tpd = n/tile per
+// dimension), the source regions (one per non-empty tile, src_tiles[k] its
+// tile id) that overlap it, in increasing k.  A region starts at its tile's
+// origin - m + 1
+// and spans L = tile + 2m - 1 points per dimension, periodically.  Each pair
+// stores the destination tile origin's offset b in the region (mod n) per
+// dimension, packed as 10-bit fields.
+void build_fold_lists(const std::vector<int32_t> &src_tiles, int dA, int n, int tile, int m,
+                      std::vector<int32_t> &fstart, std::vector<int2> &pairs) {
+    const int L = tile + 2 * m - 1;
+    const int tpd = n / tile;
+    int64_t ntiles = 1;
+    for (int t = 0; t < dA; ++t) ntiles *= tpd;
+    std::vector<std::vector<int2>> per_tile(ntiles);
+    for (size_t si = 0; si < src_tiles.size(); ++si) {
+        const int tl = src_tiles[si];
+        const int tc[3] = {tl % tpd, (tl / tpd) % tpd, tl / (tpd * tpd)};
+        std::vector<int> dest[3];
+        int r0[3] = {0, 0, 0};
+        for (int t = 0; t < 3; ++t) {
+            if (t >= dA) {
+                dest[t].push_back(0);
+                continue;
+            }
+            r0[t] = tc[t] * tile - m + 1;
+            std::vector<char> hit(tpd, 0);
+            for (int e = 0; e < L; ++e) hit[(((r0[t] + e) % n + n) % n) / tile] = 1;
+            for (int q = 0; q < tpd; ++q)
+                if (hit[q]) dest[t].push_back(q);
+        }
+        for (int dz : dest[2])
+            for (int dy : dest[1])
+                for (int dx : dest[0]) {
+                    const int dc[3] = {dx, dy, dz};
+                    int packed = 0;
+                    for (int t = 0; t < dA; ++t) packed |= (((dc[t] * tile - r0[t]) % n + n) % n) << (10 * t);
+                    per_tile[(size_t)dx + (size_t)tpd * (dy + (size_t)tpd * dz)].push_back(
+                        int2{(int)si, packed});
+                }
+    }
+    fstart.assign(ntiles + 1, 0);
+    pairs.clear();
+    for (int64_t t = 0; t < ntiles; ++t) {
+        fstart[t] = (int32_t)pairs.size();
+        pairs.insert(pairs.end(), per_tile[t].begin(), per_tile[t].end());
+    }
+    fstart[ntiles] = (int32_t)pairs.size();
+}
+
+template <typename T, typename Node>
+void build_window(WindowPlan &w, const std::vector<double> &Xh, int64_t N, int64_t ldx, int prec) {
+    const int dA = w.dA, n = w.n, m = w.m;
+    // tile edge: power of two dividing n whose region (tile + 2m - 1)^dA of
+    // 64-bit spreading accumulators fits in 64 KB of LDS
+    int tile = dA == 3 ? 8 : (dA == 2 ? 32 : 256);
+    tile = std::min(tile, n);
+    auto region = [&](int t) {
+        double L = t + 2.0 * m - 1.0;
+        return std::pow(L, dA) * 8.0;
+    };
+    while (tile > 2 && region(tile) > 65536.0) tile /= 2;
+    w.tile = tile;
+    w.tiles_per_dim = n / tile;
+    int64_t ntiles = 1;
+    for (int t = 0; t < dA; ++t) ntiles *= w.tiles_per_dim;
+    w.n_tiles = ntiles;
+    // binning
+    std::vector<uint32_t> cellw(N);
+    std::vector<T> frac((size_t)N * 3, T(0));
+    std::vector<int32_t> key(N);
+    const double scale = (double)n / w.h;
+    for (int64_t i = 0; i < N; ++i) {
+        uint32_t packed = 0;
+        int64_t tk = 0, mul = 1;
+        for (int t = 0; t < dA; ++t) {
+            double tt = (Xh[(size_t)i * ldx + w.feat[t]] - w.center[t]) * scale + 0.5 * n;
+            tt -= n * std::floor(tt / n);
+            double cf = std::floor(tt);
+            int cell = (int)cf;
+            double f = tt - cf;
+            if (cell >= n) { cell -= n; }
+            if (cell < 0) { cell += n; }
+            frac[(size_t)i * 3 + t] = static_cast<T>(f);
+            packed |= (uint32_t)cell << (10 * t);
+            tk += (int64_t)(cell / tile) * mul;
+            mul *= w.tiles_per_dim;
+        }
+        cellw[i] = packed;
+        key[i] = (int32_t)tk;
+    }
+    // stable counting sort by tile
+    std::vector<int64_t> start(ntiles + 1, 0);
+    for (int64_t i = 0; i < N; ++i) start[key[i] + 1]++;
+    for (int64_t t = 0; t < ntiles; ++t) start[t + 1] += start[t];
+    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    std::vector<int32_t> perm(N);
+    for (int64_t i = 0; i < N; ++i) perm[fill[key[i]]++] = (int32_t)i;
+    std::vector<Node> nodes(N);
+    for (int64_t j = 0; j < N; ++j) {
+        const int32_t i = perm[j];
+        Node nd{};
+        for (int t = 0; t < 3; ++t) nd.f[t] = frac[(size_t)i * 3 + t];
+        nd.cell = cellw[i];
+        nodes[j] = nd;
+    }
+    // sub-problems
+    const int64_t maxsub = 1024;
+    std::vector<SubProblem> subs;
+    int64_t nonempty = 0;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        const int64_t s0 = start[t], s1 = start[t + 1];
+        if (s1 == s0) continue;
+        ++nonempty;
+        for (int64_t s = s0; s < s1; s += maxsub)
+            subs.push_back(SubProblem{(int32_t)t, (int32_t)s, (int32_t)std::min(maxsub, s1 - s), 0});
+    }
+    w.n_nonempty = nonempty;
+    w.n_sub = (int64_t)subs.size();
+    upload(w.nodes, nodes);
+    upload(w.perm, perm);
+    upload(w.subs, subs);
+    // per non-empty tile: its sub-problems, and the fold lists over tiles
+    {
+        std::vector<int32_t> src_tiles, src_sub;
+        for (size_t q = 0; q < subs.size(); ++q)
+            if (q == 0 || subs[q].tile != subs[q - 1].tile) {
+                src_tiles.push_back(subs[q].tile);
+                src_sub.push_back((int32_t)q);
+            }
+        src_sub.push_back((int32_t)subs.size());
+        upload(w.src_sub, src_sub);
+        std::vector<int32_t> fstart;
+        std::vector<int2> pairs;
+        build_fold_lists(src_tiles, dA, n, tile, m, fstart, pairs);
+        w.n_pairs = (int64_t)pairs.size();
+        upload(w.fold_pairs, pairs);
+        upload(w.fold_start, fstart);
+    }
+    // window polynomial table
+    const double tol = prec == ANOVA_FP64 ? 1e-14 : 2e-8;
+    int deg = 0;
+    std::vector<double> coef = fit_window_polys(m, w.kb_b, tol, deg);
+    w.poly_deg = deg;
+    std::vector<T> coefT(coef.begin(), coef.end());
+    upload(w.poly, coefT);
+    // per-axis multiplier: b1_k / phihat(k/n)^2 for |k| < M/2, else 0
+    std::vector<T> bconv(n, T(0));
+    const double i0b = bessel_i0(w.kb_b);
+    const std::vector<double> bk = sampled_coeffs_1d(w.M, w.ell, w.h);
+    for (int k = 0; k < n; ++k) {
+        const int ks = k < n / 2 ? k : k - n;
+        if (std::abs(ks) >= w.M / 2) continue;
+        const double ph = kb_phihat((double)ks / n, m, w.kb_b) / i0b;
+        bconv[k] = static_cast<T>(bk[ks + w.M / 2] / (ph * ph));
+    }
+    upload(w.bconv, bconv);
+    // twiddles exp(-2 pi i j / n), j < n/2
+    std::vector<T> tw(n);
+    for (int j = 0; j < n / 2; ++j) {
+        const long double ang = -2.0L * (long double)kPi * j / n;
+        tw[2 * j] = static_cast<T>(std::cos(ang));
+        tw[2 * j + 1] = static_cast<T>(std::sin(ang));
+    }
+    upload(w.twiddle, tw);
+}
+
+void validate(const double *X, int64_t N, int32_t d, int64_t ldx, const anova_window *win,
+              int32_t P, const anova_params *prm) {
+    ANOVA_REQUIRE(X != nullptr, "X is NULL");
+    ANOVA_REQUIRE(win != nullptr, "win is NULL");
+    ANOVA_REQUIRE(prm != nullptr, "prm is NULL");
+    ANOVA_REQUIRE(N >= 1 && N <= 2147483647LL, "N must be in [1, 2^31-1]");
+    ANOVA_REQUIRE(d >= 1, "d must be >= 1");
+    ANOVA_REQUIRE(ldx >= d, "ldx must be >= d");
+    ANOVA_REQUIRE(P >= 1 && P <= 64, "P must be in [1, 64]");
+    ANOVA_REQUIRE(std::isfinite(prm->ell) && prm->ell > 0, "ell must be finite and > 0");
+    ANOVA_REQUIRE(prm->precision == ANOVA_FP64 || prm->precision == ANOVA_FP32_NFFT,
+                  "precision must be ANOVA_FP64 or ANOVA_FP32_NFFT");
+    ANOVA_REQUIRE(prm->M >= 0 && prm->M % 2 == 0 && prm->M <= 256, "M must be even, 0 or 4..256");
+    ANOVA_REQUIRE(prm->M == 0 || prm->M >= 4, "M must be >= 4");
+    ANOVA_REQUIRE(prm->n == 0 || (is_pow2(prm->n) && prm->n >= 8 && prm->n <= 256),
+                  "n must be 0 or a power of two in [8, 256]");
+    ANOVA_REQUIRE(prm->n == 0 || prm->M == 0 || prm->n >= prm->M, "n must be >= M");
+    ANOVA_REQUIRE(prm->m == 0 || (prm->m >= 2 && prm->m <= 8), "m must be 0 or in [2, 8]");
+    ANOVA_REQUIRE(prm->n == 0 || prm->m == 0 || 2 * prm->m <= prm->n, "2m must be <= n");
+    ANOVA_REQUIRE(std::isfinite(prm->h) && prm->h >= 0, "h must be finite and >= 0");
+    ANOVA_REQUIRE(std::isfinite(prm->target_err) && prm->target_err >= 0, "target_err must be >= 0");
+    ANOVA_REQUIRE(prm->center == 0 || prm->center == 1, "center must be 0 or 1");
+    ANOVA_REQUIRE(prm->reserved == 0, "reserved must be 0");
+    for (int l = 0; l < P; ++l) {
+        const anova_window &w = win[l];
+        ANOVA_REQUIRE(w.d_A >= 1 && w.d_A <= 3, "window d_A must be 1, 2 or 3");
+        ANOVA_REQUIRE(std::isfinite(w.eta), "window weight eta must be finite");
+        for (int t = 0; t < w.d_A; ++t) {
+            ANOVA_REQUIRE(w.feat[t] >= 0 && w.feat[t] < d, "feature index out of range");
+            for (int u = 0; u < t; ++u)
+                ANOVA_REQUIRE(w.feat[u] != w.feat[t], "repeated feature inside a window");
+        }
+    }
+}
+
+}  // namespace
+
+void ensure_grid(anova_plan_s *p, int slots) {
+    size_t maxg = 0, maxp = 0;
+    for (auto &w : p->win) {
+        maxg = std::max(maxg, w.grid_elems());
+        maxp = std::max(maxp, (size_t)w.n_sub * w.region_elems());
+    }
+    const size_t es = p->precision == ANOVA_FP64 ? 8 : 4;
+    if (!p->priv.ptr || p->priv.bytes < maxp * es) p->priv.alloc(maxp * es);
+    size_t maxt = 0;
+    for (auto &w : p->win)
+        if (w.n_sub != w.n_nonempty) maxt = std::max(maxt, (size_t)w.n_nonempty * w.region_elems());
+    if (maxt && (!p->treg.ptr || p->treg.bytes < maxt * es)) p->treg.alloc(maxt * es);
+    size_t slot = ((maxg * es + 255) / 256) * 256 / es;
+    if (p->grid.ptr && p->grid_slot_elems >= slot && p->grid_slots >= slots) return;
+    p->grid.alloc(slot * es * slots);
+    p->grid_slot_elems = slot;
+    p->grid_slots = slots;
+}
+
+hipEvent_t pool_event(anova_plan_s *p) {
+    if (!p->event_pool.empty()) {
+        hipEvent_t e = p->event_pool.back();
+        p->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    ANOVA_HIP_CHECK(hipEventCreate(&e));
+    return e;
+}
+
+void plan_matvec(anova_plan_s *p, const double *alpha, double *out, double beta, hipStream_t s) {
+    ensure_grid(p, 1);
+    for (int l = 0; l < p->P; ++l) {
+        const WindowPlan &w = p->win[l];
+        void *g = p->grid.ptr;
+        void *pv = p->priv.ptr;
+        timed_launch(p, kStageSpread, s,
+                     [&] { launch_spread_regions(w, p->precision, alpha, pv, s); });
+        void *tr = p->treg.ptr;
+        timed_launch(p, kStageFold, s, [&] { launch_fold(w, p->precision, pv, tr, g, s); });
+        timed_launch(p, kStageConvolve, s, [&] { launch_convolve(w, p->precision, g, s); });
+        timed_launch(p, kStageGather, s,
+                     [&] { launch_gather(w, p->precision, g, alpha, out, beta, l == 0, s); });
+    }
+}
+
+}  // namespace anova
+
+using namespace anova;
+
+template <typename F>
+static anova_status guarded(F &&f) {
+    try {
+        f();
+        return ANOVA_OK;
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return ANOVA_E_NOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return ANOVA_E_HIP;
+    }
+}
+
+extern "C" anova_status anova_fastsum_plan(anova_plan_t *out, const double *X, int64_t N,
+                                           int32_t d, int64_t ldx, const anova_window *win,
+                                           int32_t P, const anova_params *prm, void *stream) {
+    if (!out) {
+        set_error("out is NULL");
+        return ANOVA_E_INVALID;
+    }
+    *out = nullptr;
+    anova_plan_s *p = nullptr;
+    anova_status st = guarded([&] {
+        validate(X, N, d, ldx, win, P, prm);
+        hipStream_t s = (hipStream_t)stream;
+        std::vector<double> Xh((size_t)N * ldx);
+        ANOVA_HIP_CHECK(hipStreamSynchronize(s));
+        ANOVA_HIP_CHECK(hipMemcpy(Xh.data(), X, Xh.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < (size_t)N; ++i)
+            for (int t = 0; t < d; ++t)
+                ANOVA_REQUIRE(std::isfinite(Xh[i * ldx + t]), "X holds a non-finite value");
+        p = new anova_plan_s();
+        ANOVA_HIP_CHECK(hipGetDevice(&p->device));
+        p->N = N; p->d = d; p->P = P; p->precision = prm->precision; p->ell = prm->ell;
+        p->win.resize(P);
+        double eta_abs = 0.0;
+        for (int l = 0; l < P; ++l) eta_abs += std::fabs(win[l].eta);
+        if (eta_abs == 0.0) eta_abs = 1.0;
+        const double target = prm->target_err > 0 ? prm->target_err
+                              : (prm->precision == ANOVA_FP64 ? 1e-9 : 1e-4);
+        const double budget = target / eta_abs;
+        for (int l = 0; l < P; ++l) {
+            WindowPlan &w = p->win[l];
+            w.dA = win[l].d_A;
+            w.eta = win[l].eta;
+            double D = 0.0;
+            for (int t = 0; t < w.dA; ++t) {
+                w.feat[t] = win[l].feat[t];
+                double lo = Xh[w.feat[t]], hi = lo;
+                for (int64_t i = 1; i < N; ++i) {
+                    const double v = Xh[(size_t)i * ldx + w.feat[t]];
+                    lo = std::min(lo, v);
+                    hi = std::max(hi, v);
+                }
+                w.center[t] = prm->center == 1 ? 0.0 : 0.5 * (lo + hi);
+                D = std::max(D, hi - lo);
+            }
+            w.extent = D;
+            const Choice c = choose(*prm, D, w.dA, budget, N);
+            ANOVA_REQUIRE(c.h > D || (D == 0 && c.h > 0), "h must exceed the extent of the points");
+            w.h = c.h; w.M = c.M; w.n = c.n; w.m = c.m;
+            w.kb_b = kPi * w.m * (2.0 - (double)w.M / w.n);
+            const double ae = std::fabs(w.eta);
+            w.err_images = ae * c.e_img;
+            w.err_trunc = ae * c.e_trunc;
+            w.err_window = ae * c.e_win;
+            w.err_round = ae * c.e_round;
+            w.err_total = w.err_images + w.err_trunc + w.err_window + w.err_round;
+            w.ell = prm->ell;
+            if (prm->precision == ANOVA_FP64)
+                build_window<double, NodeF64>(w, Xh, N, ldx, prm->precision);
+            else
+                build_window<float, NodeF32>(w, Xh, N, ldx, prm->precision);
+        }
+        if (prm->target_err > 0) {
+            double tot = 0.0;
+            for (auto &w : p->win) tot += w.err_total;
+            if (tot > prm->target_err)
+                throw Error{ANOVA_E_ACCURACY, "estimated per-entry error " + std::to_string(tot) +
+                                                  " exceeds target_err"};
+        }
+        ensure_grid(p, 1);
+        ANOVA_HIP_CHECK(hipDeviceSynchronize());
+    });
+    if (st != ANOVA_OK) {
+        delete p;
+        return st;
+    }
+    *out = p;
+    return ANOVA_OK;
+}
+
+extern "C" anova_status anova_plan_destroy(anova_plan_t p) {
+    if (!p) return ANOVA_OK;
+    return guarded([&] {
+        (void)hipDeviceSynchronize();
+        for (auto &t : p->timed) {
+            (void)hipEventDestroy(t.start);
+            (void)hipEventDestroy(t.stop);
+        }
+        for (auto e : p->event_pool) (void)hipEventDestroy(e);
+        delete p;
+    });
+}
+
+extern "C" anova_status anova_plan_set_timing(anova_plan_t p, int32_t enable) {
+    return guarded([&] {
+        ANOVA_REQUIRE(p != nullptr, "NULL plan");
+        p->timing = enable != 0;
+    });
+}
+
+extern "C" anova_status anova_plan_stage_times(anova_plan_t p, double *ms, int64_t *launches) {
+    return guarded([&] {
+        ANOVA_REQUIRE(p != nullptr && ms != nullptr && launches != nullptr, "NULL argument");
+        for (int k = 0; k < 4; ++k) { ms[k] = 0.0; launches[k] = 0; }
+        ANOVA_HIP_CHECK(hipDeviceSynchronize());
+        for (auto &t : p->timed) {
+            float e = 0.0f;
+            ANOVA_HIP_CHECK(hipEventElapsedTime(&e, t.start, t.stop));
+            ms[t.kind] += e;
+            launches[t.kind] += 1;
+            p->event_pool.push_back(t.start);
+            p->event_pool.push_back(t.stop);
+        }
+        p->timed.clear();
+    });
+}
+
+extern "C" const char *anova_last_error(void) { return get_error(); }
+
+extern "C" anova_status anova_plan_query(anova_plan_t p, int32_t l, anova_window_info *info) {
+    return guarded([&] {
+        ANOVA_REQUIRE(p != nullptr && info != nullptr, "NULL argument");
+        ANOVA_REQUIRE(l >= 0 && l < p->P, "window index out of range");
+        const WindowPlan &w = p->win[l];
+        anova_window_info r{};
+        r.d_A = w.dA; r.M = w.M; r.n = w.n; r.m = w.m; r.h = w.h;
+        for (int t = 0; t < 3; ++t) r.center[t] = w.center[t];
+        r.extent = w.extent;
+        r.err_images = w.err_images; r.err_trunc = w.err_trunc; r.err_window = w.err_window;
+        r.err_round = w.err_round; r.err_total = w.err_total;
+        r.n_tiles = w.n_nonempty; r.n_subproblems = w.n_sub;
+        *info = r;
+    });
+}
+
+extern "C" anova_status anova_plan_shape(anova_plan_t p, int64_t *N, int32_t *P, int32_t *precision) {
+    return guarded([&] {
+        ANOVA_REQUIRE(p != nullptr, "NULL plan");
+        if (N) *N = p->N;
+        if (P) *P = p->P;
+        if (precision) *precision = p->precision;
+    });
+}
+
+extern "C" anova_status anova_matvec(anova_plan_t p, const double *alpha, double *out,
+                                     int32_t nrhs, int64_t ld, double beta, void *stream) {
+    return guarded([&] {
+        ANOVA_REQUIRE(p != nullptr, "NULL plan");
+        ANOVA_REQUIRE(alpha != nullptr && out != nullptr, "NULL vector");
+        ANOVA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+        ANOVA_REQUIRE(ld >= p->N, "ld must be >= N");
+        ANOVA_REQUIRE(std::isfinite(beta), "beta must be finite");
+        hipStream_t s = (hipStream_t)stream;
+        for (int c = 0; c < nrhs; ++c)
+            plan_matvec(p, alpha + (size_t)c * ld, out + (size_t)c * ld, beta, s);
+    });
+}
+
+extern "C" anova_status anova_stage_spread(anova_plan_t p, int32_t l, const double *alpha,
+                                           void *grid, void *stream) {
+    return guarded([&] {
+        ANOVA_REQUIRE(p != nullptr && alpha != nullptr && grid != nullptr, "NULL argument");
+        ANOVA_REQUIRE(l >= 0 && l < p->P, "window index out of range");
+        ensure_grid(p, 1);
+        launch_spread(p->win[l], p->precision, alpha, grid, p->priv.ptr, p->treg.ptr,
+                      (hipStream_t)stream);
+    });
+}
+
+extern "C" anova_status anova_stage_convolve(anova_plan_t p, int32_t l, void *grid, void *stream) {
+    return guarded([&] {
+        ANOVA_REQUIRE(p != nullptr && grid != nullptr, "NULL argument");
+        ANOVA_REQUIRE(l >= 0 && l < p->P, "window index out of range");
+        launch_convolve(p->win[l], p->precision, grid, (hipStream_t)stream);
+    });
+}
+
+extern "C" anova_status anova_stage_gather(anova_plan_t p, int32_t l, const void *grid,
+                                           double *out, void *stream) {
+    return guarded([&] {
+        ANOVA_REQUIRE(p != nullptr && grid != nullptr && out != nullptr, "NULL argument");
+        ANOVA_REQUIRE(l >= 0 && l < p->P, "window index out of range");
+        launch_gather(p->win[l], p->precision, grid, nullptr, out, 0.0, false, (hipStream_t)stream);
+    });
+}

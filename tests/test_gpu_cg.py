@@ -1,0 +1,100 @@
+"""Parity of the HIP conjugate-gradient solver with the oracle.
+
+The plain float64 case is solved to a relative residual of 1e-6 and checked
+by the oracle's own direct product (the true residual of the GPU solution
+against the exact K) and against the oracle's CG solution; float32-NFFT
+solves report their residuals and are checked on the oracle's matvec within
+the matvec tolerance.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_util import dev_cols, dev_rows, empty_cols, to_np
+
+pytestmark = pytest.mark.gpu
+
+F32, F64 = 1, 0
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2111_10140_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def solve(A, plan, y, beta, tol, maxit, **kw):
+    import torch
+    yd = dev_cols(y)
+    x = empty_cols(y.shape[0], 1 if y.ndim == 1 else y.shape[1])
+    info = A.krr_cg_solve(plan, yd, x, beta, tol, maxit, **kw)
+    torch.cuda.synchronize()
+    return to_np(x), info
+
+
+def test_plain_fp64_cg(A):
+    p = workloads.plain_fp64()
+    plan = A.anova_fastsum_plan(dev_rows(p.X), p.windows,
+                                A.make_params(p.ell, F64, M=32, m=4, n=64, h=1.0))
+    y = p.y[:, 0]
+    x, info = solve(A, plan, y, p.beta, 1e-6, 2000)
+    print(info)
+    assert info[0]["converged"] and info[0]["true_relres"] <= 1e-6
+    # the oracle's exact operator: residual of the GPU solution
+    apply = lambda v: oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, v)
+    rr = np.linalg.norm(y - apply(x)) / np.linalg.norm(y)
+    print(f"oracle relres of GPU solution {rr:.3e}")
+    assert rr <= 1.0e-6 + 1e-7
+    ref = oracle.cg.cg_solve(apply, y, 1e-10, 5000)
+    dx = np.linalg.norm(x - ref.x) / np.linalg.norm(ref.x)
+    print(f"||x_gpu - x_oracle|| / ||x_oracle|| = {dx:.3e} (oracle iters {ref.iters}, gpu {info[0]['iters']})")
+    assert dx <= 1e-5
+
+
+def test_fp32_nfft_cg_feature_grouped(A):
+    p = workloads.feature_grouped(20000, seed=21)
+    plan = A.anova_fastsum_plan(dev_rows(p.X), p.windows, A.make_params(p.ell, F32))
+    y = p.y[:, 0]
+    x, info = solve(A, plan, y, p.beta, 1e-6, 3000)
+    print(info)
+    assert info[0]["converged"]
+    assert info[0]["true_relres"] <= 1e-5
+    rows = np.random.default_rng(0).choice(p.N, 200, replace=False)
+    Ax = oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, x, rows=rows)
+    # sampled rows of the exact residual, relative to the matvec tolerance
+    res = np.max(np.abs(y[rows] - Ax)) / np.abs(x).sum()
+    print(f"sampled exact residual / ||x||_1 = {res:.3e}")
+    assert res <= 1e-4
+
+
+def test_multi_rhs_columns_independent(A):
+    p = workloads.random_problem(3000, 6, [(0, 1, 2), (3, 4), (5,)], 0.2, nrhs=3, seed=22)
+    plan = A.anova_fastsum_plan(dev_rows(p.X), p.windows, A.make_params(p.ell, F64))
+    X3, info3 = solve(A, plan, p.y, 1.0, 1e-8, 2000)
+    # floating-point atomics make the summation order (not the result beyond
+    # rounding) vary from run to run, so columns agree to the solve's
+    # accuracy rather than bitwise
+    for c in range(3):
+        x1, info1 = solve(A, plan, np.ascontiguousarray(p.y[:, c]), 1.0, 1e-8, 2000)
+        assert abs(info1[0]["iters"] - info3[c]["iters"]) <= 2
+        assert info1[0]["converged"] and info3[c]["converged"]
+        np.testing.assert_allclose(X3[:, c], x1, rtol=0, atol=1e-8 * np.abs(x1).max())
+
+
+def test_not_converged_and_invalid(A):
+    p = workloads.random_problem(500, 3, [(0, 1, 2)], 0.2, seed=23, eta=[1.0])
+    plan = A.anova_fastsum_plan(dev_rows(p.X), p.windows, A.make_params(p.ell, F64))
+    y = p.y[:, 0]
+    x, info = solve(A, plan, y, 1.0, 1e-12, 1, allow_not_converged=True)
+    assert info[0]["status"] == "E_NOT_CONVERGED" and info[0]["iters"] == 1
+    assert not info[0]["converged"]
+    with pytest.raises(A.AnovaError) as ei:
+        solve(A, plan, y, 0.0, 1e-6, 10)
+    assert ei.value.status == A.ANOVA_E_INVALID
+    # zero right-hand side: converged at once with alpha = 0
+    x, info = solve(A, plan, np.zeros(500), 1.0, 1e-6, 10)
+    assert info[0]["converged"] and info[0]["iters"] == 0 and not x.any()

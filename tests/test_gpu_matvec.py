@@ -1,0 +1,205 @@
+"""Parity of the HIP fast-summation matvec with the oracle's direct sum.
+
+Gate (per column): E = ||K~ a - K a||_inf / ||a||_1 <= 1e-4 for the float32
+NFFT path and <= 1e-8 for the float64 path at the small plain-double case's
+parameters; auto-chosen parameters must also stay within the plan's own
+per-entry error estimate.  Inputs are seeded synthetic stand-ins for the
+paper's data (uniform points in [-1/4, 1/4)^d, windows of at most three
+features, equal weights), at sizes the oracle finishes in seconds; the full
+sizes are checked on sampled rows.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_util import dev_cols, dev_rows, empty_cols, rel_err, to_np
+
+pytestmark = pytest.mark.gpu
+
+F32, F64 = 1, 0
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2111_10140_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def gpu_matvec(A, plan, alpha, beta):
+    a = dev_cols(alpha)
+    out = empty_cols(alpha.shape[0], 1 if alpha.ndim == 1 else alpha.shape[1])
+    A.anova_matvec(plan, a, out, beta)
+    import torch
+    torch.cuda.synchronize()
+    return to_np(out)
+
+
+def make_plan(A, p, precision, **kw):
+    return A.anova_fastsum_plan(dev_rows(p.X), p.windows, A.make_params(p.ell, precision, **kw))
+
+
+def test_plain_fp64_config(A):
+    # N = 2000 uniform in [-1/4,1/4)^3, ell = 0.1, bandwidth M = 32, m = 4,
+    # n = 64, period h = 1; gate 1e-8
+    p = workloads.plain_fp64()
+    plan = make_plan(A, p, F64, M=32, m=4, n=64, h=1.0)
+    a = p.alpha[:, 0]
+    out = gpu_matvec(A, plan, a, p.beta)
+    ref = oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a)
+    e = rel_err(out, ref, a)
+    print(f"plain fp64 E = {e:.3e}; estimate {plan.err_estimate():.3e}")
+    assert e <= 1e-8
+
+
+def test_fp32_feature_grouped_auto(A):
+    p = workloads.feature_grouped(20000, seed=11)
+    plan = make_plan(A, p, F32, target_err=1e-4)
+    a = p.alpha[:, 0]
+    out = gpu_matvec(A, plan, a, p.beta)
+    ref = oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a)
+    e = rel_err(out, ref, a)
+    infos = [plan.info(l) for l in range(plan.P)]
+    print("auto params", [(i.M, i.n, i.m, round(i.h, 3)) for i in infos], f"E = {e:.3e}",
+          f"estimate {plan.err_estimate():.3e}")
+    assert e <= 1e-4
+    assert e <= plan.err_estimate()
+
+
+def test_fp32_fixed_feature_grouped_params(A):
+    # the feature-grouped configuration's fixed parameters: M = 64, m = 6, n = 128
+    p = workloads.feature_grouped(6000, seed=12)
+    plan = make_plan(A, p, F32, M=64, m=6, n=128)
+    a = p.alpha[:, 0]
+    out = gpu_matvec(A, plan, a, p.beta)
+    ref = oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a)
+    e = rel_err(out, ref, a)
+    print(f"fixed (64, 6, 128) fp32 E = {e:.3e}")
+    assert e <= 1e-4
+
+
+@pytest.mark.parametrize("precision,gate", [(F32, 1e-4), (F64, 1e-9)])
+def test_mixed_window_dimensions(A, precision, gate):
+    p = workloads.random_problem(3001, 6, [(0, 1, 2), (3, 4), (5,)], 0.2, beta=0.5, seed=13)
+    plan = make_plan(A, p, precision, target_err=gate)
+    a = p.alpha[:, 0]
+    out = gpu_matvec(A, plan, a, p.beta)
+    ref = oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a)
+    e = rel_err(out, ref, a)
+    print("mixed", precision, [(plan.info(l).M, plan.info(l).n, plan.info(l).m) for l in range(3)],
+          f"E = {e:.3e}")
+    assert e <= gate
+
+
+@pytest.mark.parametrize("ell", [0.1, 0.4])
+def test_other_widths_and_weights(A, ell):
+    p = workloads.random_problem(2500, 5, [(4, 0, 2), (1, 3)], ell, beta=2.0, seed=14,
+                                 eta=[0.7, 0.3])
+    plan = make_plan(A, p, F32)
+    a = p.alpha[:, 0]
+    e = rel_err(gpu_matvec(A, plan, a, p.beta),
+                oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a), a)
+    print(f"ell {ell}: E = {e:.3e}")
+    assert e <= 1e-4
+
+
+def test_multi_rhs_equals_single_columns(A):
+    p = workloads.random_problem(4097, 6, [(0, 1, 2), (3, 4, 5)], 0.2, nrhs=3, seed=15)
+    plan = make_plan(A, p, F32)
+    out = gpu_matvec(A, plan, p.alpha, 1.0)
+    ref = oracle.direct.anova_matvec(p.X, p.windows, p.ell, 1.0, p.alpha)
+    assert rel_err(out, ref, p.alpha) <= 1e-4
+    for c in range(3):
+        single = gpu_matvec(A, plan, np.ascontiguousarray(p.alpha[:, c]), 1.0)
+        np.testing.assert_allclose(single, out[:, c], rtol=0, atol=1e-6 * np.abs(p.alpha[:, c]).sum())
+
+
+@pytest.mark.parametrize("N", [1, 2, 3, 255, 1023, 1025])
+def test_small_and_ragged_sizes(A, N):
+    p = workloads.random_problem(N, 3, [(0, 1, 2)], 0.15, seed=100 + N, eta=[1.0])
+    for precision, gate in [(F32, 1e-4), (F64, 1e-9)]:
+        plan = make_plan(A, p, precision)
+        a = p.alpha[:, 0]
+        e = rel_err(gpu_matvec(A, plan, a, p.beta),
+                    oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a), a)
+        assert e <= gate, (N, precision, e)
+
+
+def test_degenerate_identical_points(A):
+    # all points equal: every kernel entry is sum(eta) = 1
+    X = np.tile(np.array([[0.1, -0.2, 0.05]]), (500, 1))
+    wins = [workloads.Window((0, 1), 0.5), workloads.Window((2,), 0.5)]
+    a = np.random.default_rng(3).standard_normal(500)
+    for precision, gate in [(F32, 1e-4), (F64, 1e-9)]:
+        plan = A.anova_fastsum_plan(dev_rows(X), wins, A.make_params(0.2, precision))
+        out = gpu_matvec(A, plan, a, 0.0)
+        assert np.max(np.abs(out - a.sum())) / np.abs(a).sum() <= gate
+
+
+def test_column_entries_within_estimate(A):
+    # K~ e_j against the dense kernel column: the maximum entry error must
+    # stay below the plan's per-entry error estimate
+    p = workloads.feature_grouped(3000, seed=16)
+    plan = make_plan(A, p, F32)
+    est = plan.err_estimate()
+    js = np.random.default_rng(0).choice(p.N, 8, replace=False)
+    E = np.zeros((p.N, len(js)))
+    E[js, np.arange(len(js))] = 1.0
+    out = gpu_matvec(A, plan, E, 0.0)
+    ref = oracle.direct.kernel_block(p.X, p.windows, p.ell, np.arange(p.N), js)
+    worst = np.max(np.abs(out - ref))
+    print(f"max entry error {worst:.3e}, estimate {est:.3e}")
+    assert worst <= est
+
+
+def test_operator_symmetry(A):
+    p = workloads.feature_grouped(5000, seed=17)
+    plan = make_plan(A, p, F32)
+    rng = np.random.default_rng(1)
+    u, v = rng.standard_normal(p.N), rng.standard_normal(p.N)
+    Ku, Kv = gpu_matvec(A, plan, u, 0.0), gpu_matvec(A, plan, v, 0.0)
+    assert abs(v @ Ku - u @ Kv) <= 1e-5 * np.abs(u).sum() * np.abs(v).sum() / p.N
+
+
+def test_stage_spread_matches_adjoint_ndft(A):
+    # the spread grid, transformed by numpy's FFT and divided by the window
+    # transform, reproduces the adjoint NDFT (eq. adjnfft) at x~ = x/h
+    import torch
+    p = workloads.random_problem(700, 3, [(0, 1, 2)], 0.1, seed=18, eta=[1.0])
+    M, n, m, h = 16, 32, 6, 1.0
+    plan = A.anova_fastsum_plan(dev_rows(p.X), p.windows,
+                                A.make_params(p.ell, F64, M=M, n=n, m=m, h=h, center=1))
+    g = A.grid_tensor(plan, 0)
+    a = p.alpha[:, 0]
+    A.anova_stage_spread(plan, 0, dev_cols(a), g)
+    torch.cuda.synchronize()
+    grid = to_np(g)  # index [u3, u2, u1]: x fastest
+    Y = np.fft.fftn(grid.transpose(2, 1, 0))  # axes (u1, u2, u3)
+    k = np.arange(-M // 2, M // 2)
+    b = oracle.fastsum.kb_beta(m, n / M)
+    ph = oracle.fastsum.kb_window_hat(k / n, m, b) / oracle.fastsum.kb_window(np.array([0.0]), m, b)[0]
+    # grid point u sits at u/n - 1/2: phase (-1)^k per dimension
+    sgn = (-1.0) ** k
+    Yk = Y[np.ix_(k % n, k % n, k % n)]
+    Yk = Yk * np.einsum("a,b,c->abc", sgn / ph, sgn / ph, sgn / ph)
+    ref = oracle.fastsum.adjoint_ndft(a, p.X / h, M)
+    err = np.max(np.abs(Yk - ref)) / np.abs(a).sum()
+    print(f"adjoint NDFT stage error {err:.3e}")
+    assert err <= 1e-9
+
+
+def test_feature_grouped_full_size_sampled_rows(A):
+    p = workloads.feature_grouped(100_000, seed=1)
+    plan = make_plan(A, p, F32, M=64, m=6, n=128)
+    a = p.alpha[:, 0]
+    out = gpu_matvec(A, plan, a, p.beta)
+    rows = np.random.default_rng(7).choice(p.N, 256, replace=False)
+    ref = oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a, rows=rows)
+    e = float(np.max(np.abs(out[rows] - ref)) / np.abs(a).sum())
+    print(f"N=1e5 fixed (64,6,128) sampled-row E = {e:.3e}")
+    assert e <= 1e-4
