@@ -44,12 +44,15 @@ def parse():
     return ap.parse_args()
 
 
-def alg_bytes(stage: str, N: int, G: int, elem: int) -> float:
+def alg_bytes(stage: str, N: int, G: int, elem: int, P: int = 3) -> float:
     """Algorithmic HBM bytes of one launch of a stage for one window.
     spread : node record (16 B f32 / 32 B f64) + permutation 4 B + alpha 8 B
              per point, one write of each grid value;
-    gather : node record + permutation + output read-modify-write 16 B per
-             point, one read of each grid value;
+    gather : node record + one value written per point (4 B f32 / 8 B f64),
+             one read of each grid value;
+    combine (all windows): alpha read and output write 16 B per point, plus
+             the inverse permutation and the window's value per point and
+             window;
     convolve (one axis pass): one read and one write of the grid;
     fold   : one write of each grid value (the tile regions it reads are
              traffic of this implementation, not of the method)."""
@@ -57,7 +60,9 @@ def alg_bytes(stage: str, N: int, G: int, elem: int) -> float:
     if stage == "spread":
         return N * (node + 4 + 8) + G * elem
     if stage == "gather":
-        return N * (node + 4 + 16) + G * elem
+        return N * (node + elem) + G * elem
+    if stage == "combine":
+        return N * (16 + P * (4 + elem))
     if stage == "convolve":
         return 2.0 * G * elem
     return float(G * elem)  # fold

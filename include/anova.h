@@ -101,6 +101,9 @@ typedef struct {
     double err_total;
     int64_t n_tiles;        /* grid tiles holding at least one point */
     int64_t n_subproblems;  /* work items of the spreading / gathering launches */
+    int32_t per_cell;       /* 1: points are accumulated per grid cell in
+                               registers (many points per cell); 0: per point */
+    int32_t tile;           /* tile edge in grid points */
 } anova_window_info;
 
 typedef struct {
@@ -199,12 +202,14 @@ anova_status anova_stage_gather(anova_plan_t plan, int32_t l, const void *grid, 
 /*
  * Per-stage device-time accounting, for benchmarks.  While enabled, every
  * anova_matvec and krr_cg_solve matvec records HIP events on the caller's
- * stream around each launch of the four stage kinds, in this order:
+ * stream around each launch group of the five stage kinds, in this order:
  * 0 fold (adding the spread tile regions into the grid), 1 spread into tile
- * regions, 2 convolve (FFT, multiply, inverse FFT; one launch per axis),
- * 3 gather.  anova_plan_stage_times synchronises,
- * writes the accumulated milliseconds and launch counts per kind (host
- * arrays of 4) and resets the counters.  Enabling adds a few microseconds of
+ * regions (with the permutation of the coefficients into sorted order),
+ * 2 convolve (FFT, multiply, inverse FFT; one launch per axis), 3 gather
+ * (interpolation at the points, sorted order), 4 combine (weighted sum over
+ * windows plus the shift, in the caller's order).  anova_plan_stage_times
+ * synchronises, writes the accumulated milliseconds and launch counts per
+ * kind (host arrays of 5) and resets the counters.  Enabling adds a few microseconds of
  * event overhead per launch; disabled by default.
  */
 anova_status anova_plan_set_timing(anova_plan_t plan, int32_t enable);

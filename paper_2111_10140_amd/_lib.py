@@ -46,7 +46,8 @@ class anova_window_info(ctypes.Structure):
                 ("extent", ctypes.c_double), ("err_images", ctypes.c_double),
                 ("err_trunc", ctypes.c_double), ("err_window", ctypes.c_double),
                 ("err_round", ctypes.c_double), ("err_total", ctypes.c_double),
-                ("n_tiles", ctypes.c_int64), ("n_subproblems", ctypes.c_int64)]
+                ("n_tiles", ctypes.c_int64), ("n_subproblems", ctypes.c_int64),
+                ("per_cell", ctypes.c_int32), ("tile", ctypes.c_int32)]
 
 
 class krr_cg_info(ctypes.Structure):
@@ -171,6 +172,8 @@ class WindowInfo:
     err_total: float
     n_tiles: int
     n_subproblems: int
+    per_cell: int
+    tile: int
 
 
 class Plan:
@@ -196,17 +199,17 @@ class Plan:
         _check(load().anova_plan_query(self.handle, l, ctypes.byref(r)))
         return WindowInfo(r.d_A, r.M, r.n, r.m, r.h, tuple(r.center), r.extent, r.err_images,
                           r.err_trunc, r.err_window, r.err_round, r.err_total, r.n_tiles,
-                          r.n_subproblems)
+                          r.n_subproblems, r.per_cell, r.tile)
 
     def set_timing(self, enable: bool) -> None:
         _check(load().anova_plan_set_timing(self.handle, 1 if enable else 0))
 
     def stage_times(self):
-        """{kind: (total_ms, launches)} for fold/spread/convolve/gather; resets."""
-        ms = (ctypes.c_double * 4)()
-        cnt = (ctypes.c_int64 * 4)()
+        """{kind: (total_ms, launches)} for fold/spread/convolve/gather/combine; resets."""
+        ms = (ctypes.c_double * 5)()
+        cnt = (ctypes.c_int64 * 5)()
         _check(load().anova_plan_stage_times(self.handle, ms, cnt))
-        return {k: (ms[i], cnt[i]) for i, k in enumerate(["fold", "spread", "convolve", "gather"])}
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(["fold", "spread", "convolve", "gather", "combine"])}
 
     def err_estimate(self) -> float:
         return sum(self.info(l).err_total for l in range(self.P))

@@ -83,7 +83,19 @@ struct alignas(16) SubProblem {
     int32_t pad;
 };
 
-constexpr int kMaxPolyDeg = 23;   // polynomial degree bound for the window tables
+// Per-window operand of the combine kernel (device array, one per window).
+struct CombineWin {
+    const void *tmp;         // window's interpolated values, sorted order (float/double)
+    const int32_t *iperm;    // caller's point index -> sorted position
+    double eta;
+};
+
+// Degree of the per-offset window polynomials: the fit error of the
+// Kaiser-Bessel window stays below 2e-7 (float32) and 1.2e-14 (float64) of
+// its maximum for m = 2..8 and oversampling 1.25..4.
+template <typename T> struct PolyDeg;
+template <> struct PolyDeg<float> { static constexpr int value = 8; };
+template <> struct PolyDeg<double> { static constexpr int value = 15; };
 
 // ---------------------------------------------------------------- window plan
 struct WindowPlan {
@@ -93,19 +105,27 @@ struct WindowPlan {
     double eta = 0, ell = 0, h = 0, extent = 0, kb_b = 0;
     double center[3] = {0, 0, 0};
     double err_images = 0, err_trunc = 0, err_window = 0, err_round = 0, err_total = 0;
+    double fit_err = 0;          // max error of the window polynomials
     // tiling
     int tile = 0;                // tile edge in grid points (same in every dimension)
     int tiles_per_dim = 0;
     int64_t n_tiles = 0, n_nonempty = 0, n_sub = 0;
     int poly_deg = 0;
+    bool dense = false;          // per-cell register accumulation (see kernels.hip)
+    int chunks = 1;              // dense regime: workgroups per tile
+    int64_t n_points = 0;
+    int64_t n_regions = 0;       // spread regions per launch (sub-problems, or tiles x chunks)
     // device data
     DevBuf nodes;    // NodeF32 or NodeF64, sorted by tile (N entries)
     DevBuf perm;     // int32: sorted position -> caller's point index
+    DevBuf iperm;    // int32: caller's point index -> sorted position
     DevBuf subs;     // SubProblem[n_sub]
     DevBuf poly;     // window polynomial table [2m][poly_deg+1] (float or double)
     DevBuf bconv;    // per-axis multiplier, n entries (float or double)
     DevBuf twiddle;  // n/2 complex exp(-2 pi i j / n) (float2 or double2)
-    DevBuf src_sub;     // int32 [n_nonempty + 1]: sub-problems of the k-th non-empty tile
+    DevBuf src_sub;     // int32 [n_nonempty + 1]: spread regions of the k-th non-empty tile
+    DevBuf cell_start;  // dense regime: int32 [cells + 1] sorted-point offsets per (tile, cell)
+    DevBuf tiles_ne;    // dense regime: int32 ids of the non-empty tiles
     DevBuf fold_pairs;  // int2 {non-empty tile k, packed region offsets}, grouped by tile
     DevBuf fold_start;  // int32 [n_tiles + 1] offsets into fold_pairs
     int64_t n_pairs = 0;
@@ -135,6 +155,9 @@ struct anova_plan_s {
     anova::DevBuf grid;      // largest window grid (float or double) x grid_slots
     anova::DevBuf priv;      // spread regions: max over windows of n_sub x region (float/double)
     anova::DevBuf treg;      // per-tile sums of the regions (windows whose tiles have several)
+    anova::DevBuf asort;     // coefficients in a window's sorted order (float or double), N
+    anova::DevBuf tmp;       // per-window interpolated values, P x N (float or double)
+    anova::DevBuf combine;   // CombineWin[P]
     size_t grid_slot_elems = 0;
     int grid_slots = 0;
     int device = 0;
@@ -151,15 +174,17 @@ struct anova_plan_s {
 namespace anova {
 
 // kernel launchers (kernels.hip)
-void launch_spread(const WindowPlan &w, int precision, const double *alpha, void *grid, void *priv,
-                   void *treg, hipStream_t s);
-void launch_spread_regions(const WindowPlan &w, int precision, const double *alpha, void *priv,
-                           hipStream_t s);
+void launch_spread(const WindowPlan &w, int precision, const double *alpha, void *grid, void *as,
+                   void *priv, void *treg, hipStream_t s);
+void launch_spread_regions(const WindowPlan &w, int precision, const double *alpha, void *as,
+                           void *priv, hipStream_t s);
 void launch_fold(const WindowPlan &w, int precision, const void *priv, void *treg, void *grid,
                  hipStream_t s);
 void launch_convolve(const WindowPlan &w, int precision, void *grid, hipStream_t s);
-void launch_gather(const WindowPlan &w, int precision, const void *grid, const double *alpha,
-                   double *out, double beta, bool first, hipStream_t s);
+void launch_gather(const WindowPlan &w, int precision, const void *grid, void *tmp,
+                   hipStream_t s);
+void launch_combine(const void *wins, int P, int precision, const double *alpha, double *out,
+                    double beta, int64_t N, bool accumulate, hipStream_t s);
 void launch_zero(void *p, size_t bytes, hipStream_t s);
 
 // one matvec of a plan for a single column (plan.hip)
@@ -167,7 +192,14 @@ void plan_matvec(anova_plan_s *p, const double *alpha, double *out, double beta,
 void ensure_grid(anova_plan_s *p, int slots);
 
 // stage kinds for the optional timing
-enum StageKind { kStageFold = 0, kStageSpread = 1, kStageConvolve = 2, kStageGather = 3 };
+enum StageKind {
+    kStageFold = 0,
+    kStageSpread = 1,
+    kStageConvolve = 2,
+    kStageGather = 3,
+    kStageCombine = 4,
+    kStageKinds = 5
+};
 // records an event pair around `launch` when the plan's timing is enabled
 template <typename F>
 void timed_launch(anova_plan_s *p, int kind, hipStream_t s, F &&launch);

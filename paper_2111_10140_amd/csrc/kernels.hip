@@ -32,15 +32,19 @@ constexpr int kBlock = 256;
 
 // Weights phi0(f + m - 1 - a), a = 0..W-1, of a point with fractional cell
 // offset f in [0,1): one polynomial per support offset, Horner in z = 2f-1.
+// The degree is fixed per precision (kPolyDeg), so the loops unroll and the
+// coefficients, uniform across the wave, stay in scalar registers.
 template <typename T, int W>
-__device__ __forceinline__ void window_weights(const T *__restrict__ poly, int deg, T f,
+__device__ __forceinline__ void window_weights(const T *__restrict__ poly, int /*deg*/, T f,
                                                T (&w)[W]) {
+    constexpr int D = PolyDeg<T>::value;
     const T z = T(2) * f - T(1);
 #pragma unroll
-    for (int a = 0; a < W; ++a) w[a] = poly[a * (deg + 1) + deg];
-    for (int k = deg - 1; k >= 0; --k) {
+    for (int a = 0; a < W; ++a) w[a] = poly[a * (D + 1) + D];
 #pragma unroll
-        for (int a = 0; a < W; ++a) w[a] = w[a] * z + poly[a * (deg + 1) + k];
+    for (int k = D - 1; k >= 0; --k) {
+#pragma unroll
+        for (int a = 0; a < W; ++a) w[a] = w[a] * z + poly[a * (D + 1) + k];
     }
 }
 
@@ -86,9 +90,9 @@ __device__ __forceinline__ float block_max(float v, float *sh) {
 // `priv`; the fold kernel adds the regions into the grid.
 template <typename T, int DA, int W>
 __global__ __launch_bounds__(kBlock) void spread_kernel(
-    const typename NodeOf<T>::type *__restrict__ nodes, const int32_t *__restrict__ perm,
-    const SubProblem *__restrict__ subs, const double *__restrict__ alpha, T *__restrict__ priv,
-    const T *__restrict__ poly, int deg, int tile, int tpd) {
+    const typename NodeOf<T>::type *__restrict__ nodes, const T *__restrict__ as,
+    const SubProblem *__restrict__ subs, T *__restrict__ priv, const T *__restrict__ poly,
+    int deg, int tile, int tpd) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem_raw);
     __shared__ float red[kBlock / 64];
@@ -100,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(
     const int end = sp.start + sp.count;
     float amax = 0.0f;
     for (int j = sp.start + threadIdx.x; j < end; j += kBlock) {
-        float va = (float)fabs(alpha[perm[j]]);
+        float va = (float)fabs(as[j]);
         if (!(va <= 3.0e38f)) va = INFINITY;  // NaN or out of range: propagate as NaN below
         amax = fmaxf(amax, va);
     }
@@ -121,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(
     const int oz = (sp.tile / (tpd * tpd)) * tile;
     for (int j = sp.start + threadIdx.x; j < end; j += kBlock) {
         const auto rec = nodes[j];
-        const T a = static_cast<T>(alpha[perm[j]]) * sc;
+        const T a = as[j] * sc;
         const int lx = int(rec.cell & 1023u) - ox;
         T wx[W];
         window_weights<T, W>(poly, deg, rec.f[0], wx);
@@ -164,6 +168,200 @@ __global__ __launch_bounds__(kBlock) void spread_kernel(
     const double inv = ldexp(1.0, -S);
     for (int e = threadIdx.x; e < vol; e += kBlock)
         out[e] = static_cast<T>((double)(long long)acc[e] * inv);
+}
+
+// ------------------------------------------------------------------ dense regime
+// With many points per grid cell (float32, small support), points are sorted
+// by cell inside each tile and thread (cell, s) handles points s, s+S, ... of
+// its cell.  Spreading accumulates the cell's W^d_A support values in
+// registers and adds them to the tile region once per thread; gathering reads
+// the cell's support values from LDS once and interpolates every point of the
+// thread.  One workgroup per non-empty tile (TILE^d_A cells, S threads each).
+template <int DA, int TILE>
+struct DenseShape {
+    static constexpr int cells = DA == 3 ? TILE * TILE * TILE : (DA == 2 ? TILE * TILE : TILE);
+};
+
+template <int DA, int W, int TILE, int S>
+__global__ __launch_bounds__(kBlock) void spread_dense_kernel(
+    const NodeF32 *__restrict__ nodes, const float *__restrict__ as,
+    const int32_t *__restrict__ tiles, const int32_t *__restrict__ cell_start,
+    float *__restrict__ priv, const float *__restrict__ poly, int deg, int K) {
+    constexpr int L = TILE + W - 1;
+    constexpr int L2 = DA >= 2 ? L * L : L;
+    constexpr int VOL = DA == 3 ? L2 * L : L2;
+    constexpr int CELLS = DenseShape<DA, TILE>::cells;
+    static_assert(CELLS * S == kBlock, "one thread per (cell, split)");
+    constexpr int WY = DA >= 2 ? W : 1, WZ = DA == 3 ? W : 1;
+    __shared__ unsigned long long acc_lds[VOL];
+    __shared__ float red[kBlock / 64];
+    const int tk = blockIdx.x / K, chunk = blockIdx.x % K;
+    const int key0 = tiles[tk] * CELLS;
+    for (int e = threadIdx.x; e < VOL; e += kBlock) acc_lds[e] = 0ull;
+    const int cell = threadIdx.x / S;
+    const int q = chunk * S + (int)(threadIdx.x % S), QS = K * S;
+    const int lx = cell % TILE;
+    const int ly = DA >= 2 ? (cell / TILE) % TILE : 0;
+    const int lz = DA == 3 ? cell / (TILE * TILE) : 0;
+    float acc[WZ][WY][W];
+#pragma unroll
+    for (int c = 0; c < WZ; ++c)
+#pragma unroll
+        for (int b = 0; b < WY; ++b)
+#pragma unroll
+            for (int i = 0; i < W; ++i) acc[c][b][i] = 0.0f;
+    // the fixed-point scale is needed only for the final flush, so the
+    // largest |coefficient| of the workgroup is tracked along the way
+    float amax = 0.0f;
+    const int c1 = cell_start[key0 + cell + 1];
+    int j = cell_start[key0 + cell] + q;
+    // software pipeline: the next point's record and coefficient load while
+    // the current one is accumulated
+    NodeF32 rec_n{};
+    float a_n = 0.0f;
+    if (j < c1) { rec_n = nodes[j]; a_n = as[j]; }
+    for (; j < c1; j += QS) {
+        const NodeF32 rec = rec_n;
+        const float a = a_n;
+        if (j + QS < c1) { rec_n = nodes[j + QS]; a_n = as[j + QS]; }
+        float va = fabsf(a);
+        if (!(va <= 3.0e38f)) va = INFINITY;
+        amax = fmaxf(amax, va);
+        float wx[W], wy[W], wz[W];
+        window_weights<float, W>(poly, deg, rec.f[0], wx);
+        if constexpr (DA >= 2) window_weights<float, W>(poly, deg, rec.f[1], wy);
+        if constexpr (DA == 3) window_weights<float, W>(poly, deg, rec.f[2], wz);
+#pragma unroll
+        for (int c = 0; c < WZ; ++c) {
+            const float wc = DA == 3 ? a * wz[c] : a;
+#pragma unroll
+            for (int b = 0; b < WY; ++b) {
+                const float wbc = DA >= 2 ? wc * wy[b] : wc;
+#pragma unroll
+                for (int i = 0; i < W; ++i) acc[c][b][i] = fmaf(wbc, wx[i], acc[c][b][i]);
+            }
+        }
+    }
+    amax = block_max(amax, red);  // also orders the zero fill before the adds
+    float *out = priv + (size_t)blockIdx.x * VOL;
+    if (!(amax > 0.0f) || !isfinite(amax)) {
+        const float fill = amax > 0.0f ? NAN : 0.0f;
+        for (int e = threadIdx.x; e < VOL; e += kBlock) out[e] = fill;
+        return;
+    }
+    int ex2;
+    (void)frexpf(amax * 1.0000002f, &ex2);
+    const int Sx = 30 - ex2;
+    const double sc = ldexp(1.0, Sx);
+#pragma unroll
+    for (int c = 0; c < WZ; ++c)
+#pragma unroll
+        for (int b = 0; b < WY; ++b)
+#pragma unroll
+            for (int i = 0; i < W; ++i) {
+                const float v = acc[c][b][i];
+                if (v != 0.0f)
+                    atomicAdd(&acc_lds[((lz + c) * L + ly + b) * L + lx + i],
+                              (unsigned long long)round_to_ll((double)v * sc));
+            }
+    __syncthreads();
+    const double inv = ldexp(1.0, -Sx);
+    for (int e = threadIdx.x; e < VOL; e += kBlock)
+        out[e] = (float)((double)(long long)acc_lds[e] * inv);
+}
+
+template <int DA, int W, int TILE, int S>
+__global__ __launch_bounds__(kBlock) void gather_dense_kernel(
+    const NodeF32 *__restrict__ nodes, const int32_t *__restrict__ tiles,
+    const int32_t *__restrict__ cell_start, const float *__restrict__ grid,
+    float *__restrict__ tmp, const float *__restrict__ poly, int deg, int n, int tpd, int K) {
+    constexpr int m = W / 2;
+    constexpr int L = TILE + W - 1;
+    constexpr int L2 = DA >= 2 ? L * L : L;
+    constexpr int VOL = DA == 3 ? L2 * L : L2;
+    constexpr int CELLS = DenseShape<DA, TILE>::cells;
+    static_assert(CELLS * S == kBlock, "one thread per (cell, split)");
+    constexpr int WY = DA >= 2 ? W : 1, WZ = DA == 3 ? W : 1;
+    __shared__ float g_lds[VOL];
+    const int chunk = blockIdx.x % K;
+    const int tile_id = tiles[blockIdx.x / K];
+    const int key0 = tile_id * CELLS;
+    const int ox = (tile_id % tpd) * TILE;
+    const int oy = ((tile_id / tpd) % tpd) * TILE;
+    const int oz = (tile_id / (tpd * tpd)) * TILE;
+    for (int e = threadIdx.x; e < VOL; e += kBlock) {
+        const int ex = e % L;
+        size_t g = (size_t)wrap_index(ox - m + 1 + ex, n);
+        if constexpr (DA >= 2) g += (size_t)n * (size_t)wrap_index(oy - m + 1 + (e / L) % L, n);
+        if constexpr (DA == 3) g += (size_t)n * (size_t)n * (size_t)wrap_index(oz - m + 1 + e / L2, n);
+        g_lds[e] = grid[g];
+    }
+    __syncthreads();
+    const int cell = threadIdx.x / S;
+    const int q = chunk * S + (int)(threadIdx.x % S), QS = K * S;
+    const int lx = cell % TILE;
+    const int ly = DA >= 2 ? (cell / TILE) % TILE : 0;
+    const int lz = DA == 3 ? cell / (TILE * TILE) : 0;
+    const int c0 = cell_start[key0 + cell] + q, c1 = cell_start[key0 + cell + 1];
+    if (c0 >= c1) return;
+    float g[WZ][WY][W];
+#pragma unroll
+    for (int c = 0; c < WZ; ++c)
+#pragma unroll
+        for (int b = 0; b < WY; ++b)
+#pragma unroll
+            for (int i = 0; i < W; ++i) g[c][b][i] = g_lds[((lz + c) * L + ly + b) * L + lx + i];
+    for (int j = c0; j < c1; j += QS) {
+        const NodeF32 rec = nodes[j];
+        float wx[W], wy[W], wz[W];
+        window_weights<float, W>(poly, deg, rec.f[0], wx);
+        if constexpr (DA >= 2) window_weights<float, W>(poly, deg, rec.f[1], wy);
+        if constexpr (DA == 3) window_weights<float, W>(poly, deg, rec.f[2], wz);
+        float acc = 0.0f;
+#pragma unroll
+        for (int c = 0; c < WZ; ++c) {
+            float sc = 0.0f;
+#pragma unroll
+            for (int b = 0; b < WY; ++b) {
+                float s = 0.0f;
+#pragma unroll
+                for (int i = 0; i < W; ++i) s = fmaf(g[c][b][i], wx[i], s);
+                sc = DA >= 2 ? fmaf(s, wy[b], sc) : s;
+            }
+            acc = DA == 3 ? fmaf(sc, wz[c], acc) : sc;
+        }
+        tmp[j] = acc;
+    }
+}
+
+// ------------------------------------------------------------------ permute
+// Coefficients in the window's sorted point order: as[j] = alpha[perm[j]].
+template <typename T>
+__global__ __launch_bounds__(kBlock) void permute_kernel(const double *__restrict__ alpha,
+                                                         const int32_t *__restrict__ perm,
+                                                         T *__restrict__ as, int N) {
+    for (int j = blockIdx.x * kBlock + threadIdx.x; j < N; j += gridDim.x * kBlock)
+        as[j] = static_cast<T>(alpha[perm[j]]);
+}
+
+// ------------------------------------------------------------------ combine
+// out_i = beta alpha_i + sum_l eta_l tmp_l[iperm_l[i]] in float64, windows
+// in order (accumulate: out_i += ... instead).  tmp_l holds window l's
+// interpolated values in its sorted point order, iperm_l maps the caller's
+// point index to that order.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void combine_kernel(const CombineWin *__restrict__ wins,
+                                                         int P, const double *__restrict__ alpha,
+                                                         double *__restrict__ out, double beta,
+                                                         int N, int accumulate) {
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < N; i += gridDim.x * kBlock) {
+        double s = accumulate ? out[i] : beta * alpha[i];
+        for (int l = 0; l < P; ++l) {
+            const CombineWin cw = wins[l];
+            s += cw.eta * (double)static_cast<const T *>(cw.tmp)[cw.iperm[i]];
+        }
+        out[i] = s;
+    }
 }
 
 // ------------------------------------------------------------------ tile sum
@@ -233,12 +431,11 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(
 }
 
 // ------------------------------------------------------------------ gather
-template <typename T, int DA, int W, bool FIRST>
+template <typename T, int DA, int W>
 __global__ __launch_bounds__(kBlock) void gather_kernel(
-    const typename NodeOf<T>::type *__restrict__ nodes, const int32_t *__restrict__ perm,
-    const SubProblem *__restrict__ subs, const T *__restrict__ grid,
-    const double *__restrict__ alpha, double *__restrict__ out, double eta, double beta,
-    const T *__restrict__ poly, int deg, int n, int tile, int tpd) {
+    const typename NodeOf<T>::type *__restrict__ nodes, const SubProblem *__restrict__ subs,
+    const T *__restrict__ grid, T *__restrict__ tmp, const T *__restrict__ poly, int deg, int n,
+    int tile, int tpd) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
     constexpr int m = W / 2;
@@ -304,12 +501,7 @@ __global__ __launch_bounds__(kBlock) void gather_kernel(
                 }
             }
         }
-        const int i = perm[j];
-        const double v = eta * static_cast<double>(acc);
-        if constexpr (FIRST)
-            out[i] = beta * alpha[i] + v;
-        else
-            out[i] += v;
+        tmp[j] = acc;
     }
 }
 
@@ -425,13 +617,13 @@ static size_t region_bytes(const WindowPlan &w, size_t elem) {
 }
 
 template <typename T, int DA, int W>
-static void spread_t(const WindowPlan &w, const double *alpha, void *priv, hipStream_t s) {
+static void spread_t(const WindowPlan &w, const void *as, void *priv, hipStream_t s) {
     if (w.n_sub == 0) return;
     const size_t shm = region_bytes(w, sizeof(unsigned long long));
     hipLaunchKernelGGL((spread_kernel<T, DA, W>), dim3((unsigned)w.n_sub), dim3(kBlock), shm, s,
-                       w.nodes.as<typename NodeOf<T>::type>(), w.perm.as<int32_t>(),
-                       w.subs.as<SubProblem>(), alpha, (T *)priv, w.poly.as<T>(), w.poly_deg,
-                       w.tile, w.tiles_per_dim);
+                       w.nodes.as<typename NodeOf<T>::type>(), (const T *)as,
+                       w.subs.as<SubProblem>(), (T *)priv, w.poly.as<T>(), w.poly_deg, w.tile,
+                       w.tiles_per_dim);
     ANOVA_HIP_CHECK(hipGetLastError());
 }
 
@@ -439,7 +631,7 @@ template <typename T, int DA>
 static void fold_t(const WindowPlan &w, const void *priv, void *treg, void *grid, hipStream_t s) {
     const int vol = (int)w.region_elems();
     const void *src = priv;
-    if (w.n_sub != w.n_nonempty) {
+    if (w.n_regions != w.n_nonempty) {
         hipLaunchKernelGGL((tile_sum_kernel<T>), dim3((vol + kBlock - 1) / kBlock, (unsigned)w.n_nonempty),
                            dim3(kBlock), 0, s, (const T *)priv, w.src_sub.as<int32_t>(), (T *)treg,
                            vol);
@@ -453,20 +645,13 @@ static void fold_t(const WindowPlan &w, const void *priv, void *treg, void *grid
 }
 
 template <typename T, int DA, int W>
-static void gather_t(const WindowPlan &w, const void *grid, const double *alpha, double *out,
-                     double beta, bool first, hipStream_t s) {
+static void gather_t(const WindowPlan &w, const void *grid, void *tmp, hipStream_t s) {
     if (w.n_sub == 0) return;
     const size_t shm = region_bytes(w, sizeof(T));
-    if (first)
-        hipLaunchKernelGGL((gather_kernel<T, DA, W, true>), dim3((unsigned)w.n_sub), dim3(kBlock),
-                           shm, s, w.nodes.as<typename NodeOf<T>::type>(), w.perm.as<int32_t>(),
-                           w.subs.as<SubProblem>(), (const T *)grid, alpha, out, w.eta, beta,
-                           w.poly.as<T>(), w.poly_deg, w.n, w.tile, w.tiles_per_dim);
-    else
-        hipLaunchKernelGGL((gather_kernel<T, DA, W, false>), dim3((unsigned)w.n_sub), dim3(kBlock),
-                           shm, s, w.nodes.as<typename NodeOf<T>::type>(), w.perm.as<int32_t>(),
-                           w.subs.as<SubProblem>(), (const T *)grid, alpha, out, w.eta, beta,
-                           w.poly.as<T>(), w.poly_deg, w.n, w.tile, w.tiles_per_dim);
+    hipLaunchKernelGGL((gather_kernel<T, DA, W>), dim3((unsigned)w.n_sub), dim3(kBlock), shm, s,
+                       w.nodes.as<typename NodeOf<T>::type>(), w.subs.as<SubProblem>(),
+                       (const T *)grid, (T *)tmp, w.poly.as<T>(), w.poly_deg, w.n, w.tile,
+                       w.tiles_per_dim);
     ANOVA_HIP_CHECK(hipGetLastError());
 }
 
@@ -482,12 +667,87 @@ static void gather_t(const WindowPlan &w, const void *grid, const double *alpha,
         default: throw Error{ANOVA_E_INVALID, "window half-width m out of range"}; \
     }
 
-template <typename T>
-static void spread_typed(const WindowPlan &w, const double *alpha, void *priv, hipStream_t s) {
+// dense-regime launches: tile edge 4 / 16 / 64 for d_A = 3 / 2 / 1 and
+// 256 / cells threads per cell; supports up to W = 6 / 8 / 16
+template <int DA>
+struct DenseTile {
+    static constexpr int value = DA == 3 ? 4 : (DA == 2 ? 16 : 64);
+};
+template <int DA, int W>
+static constexpr bool dense_supported() {
+    return DA == 3 ? W <= 6 : (DA == 2 ? W <= 8 : W <= 16);
+}
+
+template <int DA, int W>
+static void spread_dense_t(const WindowPlan &w, const void *as, void *priv, hipStream_t s) {
+    if constexpr (dense_supported<DA, W>()) {
+        constexpr int TILE = DenseTile<DA>::value;
+        constexpr int S = kBlock / DenseShape<DA, TILE>::cells;
+        if (w.n_nonempty == 0) return;
+        hipLaunchKernelGGL((spread_dense_kernel<DA, W, TILE, S>),
+                           dim3((unsigned)(w.n_nonempty * w.chunks)), dim3(kBlock), 0, s,
+                           w.nodes.as<NodeF32>(), (const float *)as, w.tiles_ne.as<int32_t>(),
+                           w.cell_start.as<int32_t>(), (float *)priv, w.poly.as<float>(),
+                           w.poly_deg, w.chunks);
+        ANOVA_HIP_CHECK(hipGetLastError());
+    } else {
+        throw Error{ANOVA_E_INVALID, "dense spreading does not support this window width"};
+    }
+}
+
+template <int DA, int W>
+static void gather_dense_t(const WindowPlan &w, const void *grid, void *tmp, hipStream_t s) {
+    if constexpr (dense_supported<DA, W>()) {
+        constexpr int TILE = DenseTile<DA>::value;
+        constexpr int S = kBlock / DenseShape<DA, TILE>::cells;
+        if (w.n_nonempty == 0) return;
+        hipLaunchKernelGGL((gather_dense_kernel<DA, W, TILE, S>),
+                           dim3((unsigned)(w.n_nonempty * w.chunks)), dim3(kBlock), 0, s,
+                           w.nodes.as<NodeF32>(), w.tiles_ne.as<int32_t>(),
+                           w.cell_start.as<int32_t>(), (const float *)grid, (float *)tmp,
+                           w.poly.as<float>(), w.poly_deg, w.n, w.tiles_per_dim, w.chunks);
+        ANOVA_HIP_CHECK(hipGetLastError());
+    } else {
+        throw Error{ANOVA_E_INVALID, "dense gathering does not support this window width"};
+    }
+}
+
+#define ANOVA_DISPATCH_DENSE(DA, FN, ...)                                 \
+    switch (w.m) {                                                        \
+        case 2: FN<DA, 4>(__VA_ARGS__); break;                            \
+        case 3: FN<DA, 6>(__VA_ARGS__); break;                            \
+        case 4: FN<DA, 8>(__VA_ARGS__); break;                            \
+        case 5: FN<DA, 10>(__VA_ARGS__); break;                           \
+        case 6: FN<DA, 12>(__VA_ARGS__); break;                           \
+        case 7: FN<DA, 14>(__VA_ARGS__); break;                           \
+        case 8: FN<DA, 16>(__VA_ARGS__); break;                           \
+        default: throw Error{ANOVA_E_INVALID, "window half-width m out of range"}; \
+    }
+
+static void spread_dense(const WindowPlan &w, const void *as, void *priv, hipStream_t s) {
     switch (w.dA) {
-        case 1: ANOVA_DISPATCH_W(1, spread_t, w, alpha, priv, s); break;
-        case 2: ANOVA_DISPATCH_W(2, spread_t, w, alpha, priv, s); break;
-        case 3: ANOVA_DISPATCH_W(3, spread_t, w, alpha, priv, s); break;
+        case 1: ANOVA_DISPATCH_DENSE(1, spread_dense_t, w, as, priv, s); break;
+        case 2: ANOVA_DISPATCH_DENSE(2, spread_dense_t, w, as, priv, s); break;
+        case 3: ANOVA_DISPATCH_DENSE(3, spread_dense_t, w, as, priv, s); break;
+        default: throw Error{ANOVA_E_INVALID, "d_A out of range"};
+    }
+}
+
+static void gather_dense(const WindowPlan &w, const void *grid, void *tmp, hipStream_t s) {
+    switch (w.dA) {
+        case 1: ANOVA_DISPATCH_DENSE(1, gather_dense_t, w, grid, tmp, s); break;
+        case 2: ANOVA_DISPATCH_DENSE(2, gather_dense_t, w, grid, tmp, s); break;
+        case 3: ANOVA_DISPATCH_DENSE(3, gather_dense_t, w, grid, tmp, s); break;
+        default: throw Error{ANOVA_E_INVALID, "d_A out of range"};
+    }
+}
+
+template <typename T>
+static void spread_typed(const WindowPlan &w, const void *as, void *priv, hipStream_t s) {
+    switch (w.dA) {
+        case 1: ANOVA_DISPATCH_W(1, spread_t, w, as, priv, s); break;
+        case 2: ANOVA_DISPATCH_W(2, spread_t, w, as, priv, s); break;
+        case 3: ANOVA_DISPATCH_W(3, spread_t, w, as, priv, s); break;
         default: throw Error{ANOVA_E_INVALID, "d_A out of range"};
     }
 }
@@ -504,22 +764,32 @@ static void fold_typed(const WindowPlan &w, const void *priv, void *treg, void *
 }
 
 template <typename T>
-static void gather_typed(const WindowPlan &w, const void *grid, const double *alpha, double *out,
-                         double beta, bool first, hipStream_t s) {
+static void gather_typed(const WindowPlan &w, const void *grid, void *tmp, hipStream_t s) {
     switch (w.dA) {
-        case 1: ANOVA_DISPATCH_W(1, gather_t, w, grid, alpha, out, beta, first, s); break;
-        case 2: ANOVA_DISPATCH_W(2, gather_t, w, grid, alpha, out, beta, first, s); break;
-        case 3: ANOVA_DISPATCH_W(3, gather_t, w, grid, alpha, out, beta, first, s); break;
+        case 1: ANOVA_DISPATCH_W(1, gather_t, w, grid, tmp, s); break;
+        case 2: ANOVA_DISPATCH_W(2, gather_t, w, grid, tmp, s); break;
+        case 3: ANOVA_DISPATCH_W(3, gather_t, w, grid, tmp, s); break;
         default: throw Error{ANOVA_E_INVALID, "d_A out of range"};
     }
 }
 
-void launch_spread_regions(const WindowPlan &w, int precision, const double *alpha, void *priv,
-                           hipStream_t s) {
+void launch_spread_regions(const WindowPlan &w, int precision, const double *alpha, void *as,
+                           void *priv, hipStream_t s) {
+    const int N = (int)w.n_points;
+    const int blocks = std::max(1, std::min((N + kBlock - 1) / kBlock, 4096));
     if (precision == ANOVA_FP64)
-        spread_typed<double>(w, alpha, priv, s);
+        hipLaunchKernelGGL(permute_kernel<double>, dim3(blocks), dim3(kBlock), 0, s, alpha,
+                           w.perm.as<int32_t>(), (double *)as, N);
     else
-        spread_typed<float>(w, alpha, priv, s);
+        hipLaunchKernelGGL(permute_kernel<float>, dim3(blocks), dim3(kBlock), 0, s, alpha,
+                           w.perm.as<int32_t>(), (float *)as, N);
+    ANOVA_HIP_CHECK(hipGetLastError());
+    if (w.dense)
+        spread_dense(w, as, priv, s);
+    else if (precision == ANOVA_FP64)
+        spread_typed<double>(w, as, priv, s);
+    else
+        spread_typed<float>(w, as, priv, s);
 }
 
 void launch_fold(const WindowPlan &w, int precision, const void *priv, void *treg, void *grid,
@@ -530,18 +800,34 @@ void launch_fold(const WindowPlan &w, int precision, const void *priv, void *tre
         fold_typed<float>(w, priv, treg, grid, s);
 }
 
-void launch_spread(const WindowPlan &w, int precision, const double *alpha, void *grid, void *priv,
-                   void *treg, hipStream_t s) {
-    launch_spread_regions(w, precision, alpha, priv, s);
+void launch_spread(const WindowPlan &w, int precision, const double *alpha, void *grid, void *as,
+                   void *priv, void *treg, hipStream_t s) {
+    launch_spread_regions(w, precision, alpha, as, priv, s);
     launch_fold(w, precision, priv, treg, grid, s);
 }
 
-void launch_gather(const WindowPlan &w, int precision, const void *grid, const double *alpha,
-                   double *out, double beta, bool first, hipStream_t s) {
-    if (precision == ANOVA_FP64)
-        gather_typed<double>(w, grid, alpha, out, beta, first, s);
+void launch_gather(const WindowPlan &w, int precision, const void *grid, void *tmp,
+                   hipStream_t s) {
+    if (w.dense)
+        gather_dense(w, grid, tmp, s);
+    else if (precision == ANOVA_FP64)
+        gather_typed<double>(w, grid, tmp, s);
     else
-        gather_typed<float>(w, grid, alpha, out, beta, first, s);
+        gather_typed<float>(w, grid, tmp, s);
+}
+
+void launch_combine(const void *wins, int P, int precision, const double *alpha, double *out,
+                    double beta, int64_t N, bool accumulate, hipStream_t s) {
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((N + kBlock - 1) / kBlock, 8192));
+    if (precision == ANOVA_FP64)
+        hipLaunchKernelGGL(combine_kernel<double>, dim3(blocks), dim3(kBlock), 0, s,
+                           (const CombineWin *)wins, P, alpha, out, beta, (int)N,
+                           accumulate ? 1 : 0);
+    else
+        hipLaunchKernelGGL(combine_kernel<float>, dim3(blocks), dim3(kBlock), 0, s,
+                           (const CombineWin *)wins, P, alpha, out, beta, (int)N,
+                           accumulate ? 1 : 0);
+    ANOVA_HIP_CHECK(hipGetLastError());
 }
 
 template <typename T, int LOGN>

@@ -168,65 +168,54 @@ bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
 // ------------------------------------------------------------- window polynomials
 // Fit phi0(f + m - 1 - a) / I0(b), f in [0,1), for a = 0..2m-1, by
-// interpolation at Chebyshev points in z = 2f-1; returns monomial
-// coefficients in z ([a][deg+1]) with the smallest degree whose maximum
-// error on a fine sample is below tol.
-std::vector<double> fit_window_polys(int m, double b, double tol, int &deg_out) {
+// interpolation at the deg+1 Chebyshev points in z = 2f-1; returns monomial
+// coefficients in z ([a][deg+1]) and the largest error on a fine sample.
+std::vector<double> fit_window_polys(int m, double b, int deg, double &err_out) {
     const int W = 2 * m;
     const double i0b = bessel_i0(b);
-    for (int deg = 4; deg <= kMaxPolyDeg; ++deg) {
-        const int npts = deg + 1;
-        std::vector<double> coef((size_t)W * npts);
-        double worst = 0.0;
-        for (int a = 0; a < W; ++a) {
-            // Chebyshev coefficients by the discrete cosine sum at Chebyshev nodes
-            std::vector<double> fz(npts), cheb(npts, 0.0);
-            for (int i = 0; i < npts; ++i) {
-                const double z = std::cos(kPi * (i + 0.5) / npts);
-                const double f = 0.5 * (z + 1.0);
-                fz[i] = kb_phi(f + m - 1 - a, m, b) / i0b;
-            }
-            for (int j = 0; j < npts; ++j) {
-                double s = 0.0;
-                for (int i = 0; i < npts; ++i) s += fz[i] * std::cos(kPi * j * (i + 0.5) / npts);
-                cheb[j] = (j == 0 ? 1.0 : 2.0) * s / npts;
-            }
-            // convert sum_j cheb_j T_j(z) to monomials with T_{j+1} = 2z T_j - T_{j-1}
-            std::vector<double> Tm1(npts, 0.0), T0(npts, 0.0), T1(npts, 0.0), mono(npts, 0.0);
-            T0[0] = 1.0;
-            for (int i = 0; i < npts; ++i) mono[i] += cheb[0] * T0[i];
-            if (npts > 1) {
-                T1[1] = 1.0;
-                for (int i = 0; i < npts; ++i) mono[i] += cheb[1] * T1[i];
-            }
-            for (int j = 2; j < npts; ++j) {
-                std::vector<double> T2(npts, 0.0);
-                for (int i = 0; i < npts; ++i) {
-                    if (i > 0) T2[i] += 2.0 * T1[i - 1];
-                    T2[i] -= T0[i];
-                }
-                for (int i = 0; i < npts; ++i) mono[i] += cheb[j] * T2[i];
-                T0 = T1;
-                T1 = T2;
-            }
-            for (int i = 0; i < npts; ++i) coef[(size_t)a * npts + i] = mono[i];
-            // check
-            for (int s = 0; s <= 64; ++s) {
-                const double f = s / 64.0 * (1.0 - 1e-12);
-                const double z = 2.0 * f - 1.0;
-                double v = 0.0;
-                for (int i = deg; i >= 0; --i) v = v * z + mono[i];
-                const double ref = kb_phi(f + m - 1 - a, m, b) / i0b;
-                worst = std::max(worst, std::fabs(v - ref));
-            }
+    const int npts = deg + 1;
+    std::vector<double> coef((size_t)W * npts);
+    double worst = 0.0;
+    for (int a = 0; a < W; ++a) {
+        std::vector<double> fz(npts), cheb(npts, 0.0);
+        for (int i = 0; i < npts; ++i) {
+            const double z = std::cos(kPi * (i + 0.5) / npts);
+            fz[i] = kb_phi(0.5 * (z + 1.0) + m - 1 - a, m, b) / i0b;
         }
-        if (worst <= tol || deg == kMaxPolyDeg) {
-            deg_out = deg;
-            return coef;
+        for (int j = 0; j < npts; ++j) {
+            double s = 0.0;
+            for (int i = 0; i < npts; ++i) s += fz[i] * std::cos(kPi * j * (i + 0.5) / npts);
+            cheb[j] = (j == 0 ? 1.0 : 2.0) * s / npts;
+        }
+        // sum_j cheb_j T_j(z) in monomials, with T_{j+1} = 2z T_j - T_{j-1}
+        std::vector<double> T0(npts, 0.0), T1(npts, 0.0), mono(npts, 0.0);
+        T0[0] = 1.0;
+        for (int i = 0; i < npts; ++i) mono[i] += cheb[0] * T0[i];
+        if (npts > 1) {
+            T1[1] = 1.0;
+            for (int i = 0; i < npts; ++i) mono[i] += cheb[1] * T1[i];
+        }
+        for (int j = 2; j < npts; ++j) {
+            std::vector<double> T2(npts, 0.0);
+            for (int i = 0; i < npts; ++i) {
+                if (i > 0) T2[i] += 2.0 * T1[i - 1];
+                T2[i] -= T0[i];
+            }
+            for (int i = 0; i < npts; ++i) mono[i] += cheb[j] * T2[i];
+            T0 = T1;
+            T1 = T2;
+        }
+        for (int i = 0; i < npts; ++i) coef[(size_t)a * npts + i] = mono[i];
+        for (int s = 0; s <= 256; ++s) {
+            const double f = s / 256.0 * (1.0 - 1e-12);
+            const double z = 2.0 * f - 1.0;
+            double v = 0.0;
+            for (int i = deg; i >= 0; --i) v = v * z + mono[i];
+            worst = std::max(worst, std::fabs(v - kb_phi(f + m - 1 - a, m, b) / i0b));
         }
     }
-    deg_out = kMaxPolyDeg;
-    return {};
+    err_out = worst;
+    return coef;
 }
 
 // ------------------------------------------------------------- parameter choice
@@ -352,6 +341,40 @@ void build_fold_lists(const std::vector<int32_t> &src_tiles, int dA, int n, int 
 template <typename T, typename Node>
 void build_window(WindowPlan &w, const std::vector<double> &Xh, int64_t N, int64_t ldx, int prec) {
     const int dA = w.dA, n = w.n, m = w.m;
+    // binning: cell index and fractional offset per point and dimension, from
+    // t = n (x - c) / h + n/2 in float64 (periodic on [0, n))
+    std::vector<int32_t> cellc((size_t)N * 3, 0);
+    std::vector<T> frac((size_t)N * 3, T(0));
+    const double scale = (double)n / w.h;
+    size_t ncells = 1;
+    for (int t = 0; t < dA; ++t) ncells *= (size_t)n;
+    std::vector<char> occupied(ncells, 0);
+    for (int64_t i = 0; i < N; ++i) {
+        size_t lin = 0, mul = 1;
+        for (int t = 0; t < dA; ++t) {
+            double tt = (Xh[(size_t)i * ldx + w.feat[t]] - w.center[t]) * scale + 0.5 * n;
+            tt -= n * std::floor(tt / n);
+            const double cf = std::floor(tt);
+            int cell = (int)cf;
+            const double f = tt - cf;
+            if (cell >= n) cell -= n;
+            if (cell < 0) cell += n;
+            frac[(size_t)i * 3 + t] = static_cast<T>(f);
+            cellc[(size_t)i * 3 + t] = cell;
+            lin += (size_t)cell * mul;
+            mul *= (size_t)n;
+        }
+        occupied[lin] = 1;
+    }
+    size_t nocc = 0;
+    for (char o : occupied) nocc += o;
+    // dense regime: float32, small support and several points per occupied
+    // cell -> per-cell register accumulation with a fixed small tile
+    const int W = 2 * m;
+    const int dense_tile = dA == 3 ? 4 : (dA == 2 ? 16 : 64);
+    const bool dense_ok = prec == ANOVA_FP32_NFFT && n >= dense_tile &&
+                          (dA == 3 ? W <= 6 : (dA == 2 ? W <= 8 : W <= 16));
+    w.dense = dense_ok && (double)N >= 3.0 * (double)std::max<size_t>(nocc, 1);
     // tile edge: power of two dividing n whose region (tile + 2m - 1)^dA of
     // 64-bit spreading accumulators fits in 64 KB of LDS
     int tile = dA == 3 ? 8 : (dA == 2 ? 32 : 256);
@@ -361,40 +384,39 @@ void build_window(WindowPlan &w, const std::vector<double> &Xh, int64_t N, int64
         return std::pow(L, dA) * 8.0;
     };
     while (tile > 2 && region(tile) > 65536.0) tile /= 2;
+    if (w.dense) tile = dense_tile;
     w.tile = tile;
     w.tiles_per_dim = n / tile;
     int64_t ntiles = 1;
     for (int t = 0; t < dA; ++t) ntiles *= w.tiles_per_dim;
     w.n_tiles = ntiles;
-    // binning
+    int64_t cells_per_tile = 1;
+    for (int t = 0; t < dA; ++t) cells_per_tile *= tile;
+    // sort key: tile, then cell inside the tile (x fastest)
     std::vector<uint32_t> cellw(N);
-    std::vector<T> frac((size_t)N * 3, T(0));
     std::vector<int32_t> key(N);
-    const double scale = (double)n / w.h;
     for (int64_t i = 0; i < N; ++i) {
         uint32_t packed = 0;
-        int64_t tk = 0, mul = 1;
+        int64_t tk = 0, lk = 0, mul = 1, lmul = 1;
         for (int t = 0; t < dA; ++t) {
-            double tt = (Xh[(size_t)i * ldx + w.feat[t]] - w.center[t]) * scale + 0.5 * n;
-            tt -= n * std::floor(tt / n);
-            double cf = std::floor(tt);
-            int cell = (int)cf;
-            double f = tt - cf;
-            if (cell >= n) { cell -= n; }
-            if (cell < 0) { cell += n; }
-            frac[(size_t)i * 3 + t] = static_cast<T>(f);
+            const int cell = cellc[(size_t)i * 3 + t];
             packed |= (uint32_t)cell << (10 * t);
             tk += (int64_t)(cell / tile) * mul;
+            lk += (int64_t)(cell % tile) * lmul;
             mul *= w.tiles_per_dim;
+            lmul *= tile;
         }
         cellw[i] = packed;
-        key[i] = (int32_t)tk;
+        // per-point kernels keep the caller's order inside a tile (points of
+        // one cell in one wave collide on the same LDS addresses)
+        key[i] = (int32_t)(w.dense ? tk * cells_per_tile + lk : tk * cells_per_tile);
     }
-    // stable counting sort by tile
-    std::vector<int64_t> start(ntiles + 1, 0);
-    for (int64_t i = 0; i < N; ++i) start[key[i] + 1]++;
-    for (int64_t t = 0; t < ntiles; ++t) start[t + 1] += start[t];
-    std::vector<int64_t> fill(start.begin(), start.end() - 1);
+    // stable counting sort by key
+    const int64_t nkeys = ntiles * cells_per_tile;
+    std::vector<int64_t> kstart(nkeys + 1, 0);
+    for (int64_t i = 0; i < N; ++i) kstart[key[i] + 1]++;
+    for (int64_t k = 0; k < nkeys; ++k) kstart[k + 1] += kstart[k];
+    std::vector<int64_t> fill(kstart.begin(), kstart.end() - 1);
     std::vector<int32_t> perm(N);
     for (int64_t i = 0; i < N; ++i) perm[fill[key[i]]++] = (int32_t)i;
     std::vector<Node> nodes(N);
@@ -404,6 +426,26 @@ void build_window(WindowPlan &w, const std::vector<double> &Xh, int64_t N, int64
         for (int t = 0; t < 3; ++t) nd.f[t] = frac[(size_t)i * 3 + t];
         nd.cell = cellw[i];
         nodes[j] = nd;
+    }
+    std::vector<int64_t> start(ntiles + 1);
+    for (int64_t t = 0; t <= ntiles; ++t) start[t] = kstart[t * cells_per_tile];
+    w.n_points = N;
+    if (w.dense) {
+        std::vector<int32_t> cs(nkeys + 1);
+        for (int64_t k = 0; k <= nkeys; ++k) cs[k] = (int32_t)kstart[k];
+        upload(w.cell_start, cs);
+        std::vector<int32_t> ne;
+        for (int64_t t = 0; t < ntiles; ++t)
+            if (start[t + 1] > start[t]) ne.push_back((int32_t)t);
+        upload(w.tiles_ne, ne);
+        // workgroups per tile: about 12 points per thread (4 threads per
+        // cell in 3-D), and at least ~512 workgroups when the points allow
+        const double per_cell = (double)N / (double)std::max<size_t>(nocc, 1);
+        const int S = dA == 3 ? 4 : (dA == 2 ? 1 : 4);
+        int K = (int)std::lround(per_cell / (12.0 * S));
+        K = std::max(K, (int)((512 + ne.size() - 1) / std::max<size_t>(ne.size(), 1)));
+        K = std::min(K, std::max(1, (int)(per_cell / S)));
+        w.chunks = std::max(1, std::min(K, 256));
     }
     // sub-problems
     const int64_t maxsub = 1024;
@@ -418,8 +460,14 @@ void build_window(WindowPlan &w, const std::vector<double> &Xh, int64_t N, int64
     }
     w.n_nonempty = nonempty;
     w.n_sub = (int64_t)subs.size();
+    w.n_regions = w.dense ? w.n_nonempty * w.chunks : w.n_sub;
     upload(w.nodes, nodes);
     upload(w.perm, perm);
+    {
+        std::vector<int32_t> iperm(N);
+        for (int64_t j = 0; j < N; ++j) iperm[perm[j]] = (int32_t)j;
+        upload(w.iperm, iperm);
+    }
     upload(w.subs, subs);
     // per non-empty tile: its sub-problems, and the fold lists over tiles
     {
@@ -430,6 +478,8 @@ void build_window(WindowPlan &w, const std::vector<double> &Xh, int64_t N, int64
                 src_sub.push_back((int32_t)q);
             }
         src_sub.push_back((int32_t)subs.size());
+        if (w.dense)  // chunk regions of tile k: k*chunks .. (k+1)*chunks - 1
+            for (size_t k = 0; k < src_sub.size(); ++k) src_sub[k] = (int32_t)(k * w.chunks);
         upload(w.src_sub, src_sub);
         std::vector<int32_t> fstart;
         std::vector<int2> pairs;
@@ -438,11 +488,20 @@ void build_window(WindowPlan &w, const std::vector<double> &Xh, int64_t N, int64
         upload(w.fold_pairs, pairs);
         upload(w.fold_start, fstart);
     }
-    // window polynomial table
-    const double tol = prec == ANOVA_FP64 ? 1e-14 : 2e-8;
-    int deg = 0;
-    std::vector<double> coef = fit_window_polys(m, w.kb_b, tol, deg);
+    // window polynomial table at the precision's fixed degree; its error
+    // perturbs every weight, counted (per dimension, spread and gather) in
+    // the window error relative to the window's integral
+    const int deg = prec == ANOVA_FP64 ? PolyDeg<double>::value : PolyDeg<float>::value;
+    double fit_err = 0.0;
+    std::vector<double> coef = fit_window_polys(m, w.kb_b, deg, fit_err);
     w.poly_deg = deg;
+    w.fit_err = fit_err;
+    {
+        const double phi0_int = kb_phihat(0.0, m, w.kb_b) / bessel_i0(w.kb_b);
+        const double e_fit = std::fabs(w.eta) * 2.0 * dA * (2.0 * m) * fit_err / phi0_int;
+        w.err_window += e_fit;
+        w.err_total += e_fit;
+    }
     std::vector<T> coefT(coef.begin(), coef.end());
     upload(w.poly, coefT);
     // per-axis multiplier: b1_k / phihat(k/n)^2 for |k| < M/2, else 0
@@ -507,14 +566,25 @@ void ensure_grid(anova_plan_s *p, int slots) {
     size_t maxg = 0, maxp = 0;
     for (auto &w : p->win) {
         maxg = std::max(maxg, w.grid_elems());
-        maxp = std::max(maxp, (size_t)w.n_sub * w.region_elems());
+        maxp = std::max(maxp, (size_t)w.n_regions * w.region_elems());
     }
     const size_t es = p->precision == ANOVA_FP64 ? 8 : 4;
     if (!p->priv.ptr || p->priv.bytes < maxp * es) p->priv.alloc(maxp * es);
     size_t maxt = 0;
     for (auto &w : p->win)
-        if (w.n_sub != w.n_nonempty) maxt = std::max(maxt, (size_t)w.n_nonempty * w.region_elems());
+        if (w.n_regions != w.n_nonempty)
+            maxt = std::max(maxt, (size_t)w.n_nonempty * w.region_elems());
     if (maxt && (!p->treg.ptr || p->treg.bytes < maxt * es)) p->treg.alloc(maxt * es);
+    if (!p->asort.ptr || p->asort.bytes < (size_t)p->N * es) p->asort.alloc((size_t)p->N * es);
+    const size_t tmp_bytes = (size_t)p->P * (size_t)p->N * es;
+    if (!p->tmp.ptr || p->tmp.bytes < tmp_bytes) {
+        p->tmp.alloc(tmp_bytes);
+        std::vector<CombineWin> cw(p->P);
+        for (int l = 0; l < p->P; ++l)
+            cw[l] = CombineWin{(const char *)p->tmp.ptr + (size_t)l * p->N * es,
+                               p->win[l].iperm.as<int32_t>(), p->win[l].eta};
+        upload(p->combine, cw);
+    }
     size_t slot = ((maxg * es + 255) / 256) * 256 / es;
     if (p->grid.ptr && p->grid_slot_elems >= slot && p->grid_slots >= slots) return;
     p->grid.alloc(slot * es * slots);
@@ -539,14 +609,18 @@ void plan_matvec(anova_plan_s *p, const double *alpha, double *out, double beta,
         const WindowPlan &w = p->win[l];
         void *g = p->grid.ptr;
         void *pv = p->priv.ptr;
+        void *as = p->asort.ptr;
         timed_launch(p, kStageSpread, s,
-                     [&] { launch_spread_regions(w, p->precision, alpha, pv, s); });
+                     [&] { launch_spread_regions(w, p->precision, alpha, as, pv, s); });
         void *tr = p->treg.ptr;
         timed_launch(p, kStageFold, s, [&] { launch_fold(w, p->precision, pv, tr, g, s); });
         timed_launch(p, kStageConvolve, s, [&] { launch_convolve(w, p->precision, g, s); });
-        timed_launch(p, kStageGather, s,
-                     [&] { launch_gather(w, p->precision, g, alpha, out, beta, l == 0, s); });
+        void *tl = (char *)p->tmp.ptr + (size_t)l * p->N * (p->precision == ANOVA_FP64 ? 8 : 4);
+        timed_launch(p, kStageGather, s, [&] { launch_gather(w, p->precision, g, tl, s); });
     }
+    timed_launch(p, kStageCombine, s, [&] {
+        launch_combine(p->combine.ptr, p->P, p->precision, alpha, out, beta, p->N, false, s);
+    });
 }
 
 }  // namespace anova
@@ -672,7 +746,7 @@ extern "C" anova_status anova_plan_set_timing(anova_plan_t p, int32_t enable) {
 extern "C" anova_status anova_plan_stage_times(anova_plan_t p, double *ms, int64_t *launches) {
     return guarded([&] {
         ANOVA_REQUIRE(p != nullptr && ms != nullptr && launches != nullptr, "NULL argument");
-        for (int k = 0; k < 4; ++k) { ms[k] = 0.0; launches[k] = 0; }
+        for (int k = 0; k < kStageKinds; ++k) { ms[k] = 0.0; launches[k] = 0; }
         ANOVA_HIP_CHECK(hipDeviceSynchronize());
         for (auto &t : p->timed) {
             float e = 0.0f;
@@ -699,7 +773,10 @@ extern "C" anova_status anova_plan_query(anova_plan_t p, int32_t l, anova_window
         r.extent = w.extent;
         r.err_images = w.err_images; r.err_trunc = w.err_trunc; r.err_window = w.err_window;
         r.err_round = w.err_round; r.err_total = w.err_total;
-        r.n_tiles = w.n_nonempty; r.n_subproblems = w.n_sub;
+        r.n_tiles = w.n_nonempty;
+        r.n_subproblems = w.n_regions;
+        r.per_cell = w.dense ? 1 : 0;
+        r.tile = w.tile;
         *info = r;
     });
 }
@@ -733,8 +810,8 @@ extern "C" anova_status anova_stage_spread(anova_plan_t p, int32_t l, const doub
         ANOVA_REQUIRE(p != nullptr && alpha != nullptr && grid != nullptr, "NULL argument");
         ANOVA_REQUIRE(l >= 0 && l < p->P, "window index out of range");
         ensure_grid(p, 1);
-        launch_spread(p->win[l], p->precision, alpha, grid, p->priv.ptr, p->treg.ptr,
-                      (hipStream_t)stream);
+        launch_spread(p->win[l], p->precision, alpha, grid, p->asort.ptr, p->priv.ptr,
+                      p->treg.ptr, (hipStream_t)stream);
     });
 }
 
@@ -751,6 +828,11 @@ extern "C" anova_status anova_stage_gather(anova_plan_t p, int32_t l, const void
     return guarded([&] {
         ANOVA_REQUIRE(p != nullptr && grid != nullptr && out != nullptr, "NULL argument");
         ANOVA_REQUIRE(l >= 0 && l < p->P, "window index out of range");
-        launch_gather(p->win[l], p->precision, grid, nullptr, out, 0.0, false, (hipStream_t)stream);
+        ensure_grid(p, 1);
+        const size_t es = p->precision == ANOVA_FP64 ? 8 : 4;
+        void *tl = (char *)p->tmp.ptr + (size_t)l * p->N * es;
+        launch_gather(p->win[l], p->precision, grid, tl, (hipStream_t)stream);
+        launch_combine((const CombineWin *)p->combine.ptr + l, 1, p->precision, nullptr, out, 0.0,
+                       p->N, true, (hipStream_t)stream);
     });
 }

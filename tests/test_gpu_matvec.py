@@ -203,3 +203,48 @@ def test_feature_grouped_full_size_sampled_rows(A):
     e = float(np.max(np.abs(out[rows] - ref)) / np.abs(a).sum())
     print(f"N=1e5 fixed (64,6,128) sampled-row E = {e:.3e}")
     assert e <= 1e-4
+
+
+@pytest.mark.parametrize("windows,d,kw", [
+    ([(0, 1, 2)], 3, dict(M=12, n=16, m=3)),
+    ([(0, 1, 2)], 3, dict(M=12, n=16, m=2)),
+    ([(0, 1)], 2, dict(M=12, n=16, m=4)),
+    ([(0,)], 1, dict(M=48, n=64, m=8)),
+    ([(0, 1, 2), (3, 4), (5,)], 6, dict(M=12, n=16, m=3)),
+])
+def test_per_cell_regime(A, windows, d, kw):
+    # many points per grid cell: the per-cell register-accumulating kernels
+    p = workloads.random_problem(20000, d, windows, 0.4, beta=1.0, seed=30 + d)
+    plan = make_plan(A, p, F32, **kw)
+    modes = [plan.info(l).per_cell for l in range(plan.P)]
+    a = p.alpha[:, 0]
+    e = rel_err(gpu_matvec(A, plan, a, p.beta),
+                oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a), a)
+    print(f"per-cell modes {modes}: E = {e:.3e}, estimate {plan.err_estimate():.3e}")
+    assert modes[0] == 1
+    assert e <= max(1e-4, 0.0) and e <= plan.err_estimate()
+
+
+def test_matvec_is_deterministic(A):
+    # integer accumulation and fixed-order folds: repeated products agree bitwise
+    for kw in [dict(M=12, n=16, m=3), dict(M=64, n=128, m=6)]:
+        p = workloads.random_problem(30000, 3, [(0, 1, 2)], 0.3, seed=40, eta=[1.0])
+        plan = make_plan(A, p, F32, **kw)
+        a = p.alpha[:, 0]
+        o1 = gpu_matvec(A, plan, a, 1.0)
+        o2 = gpu_matvec(A, plan, a, 1.0)
+        assert np.array_equal(o1, o2)
+
+
+def test_headline_size_sampled_rows(A):
+    # N = 1e6, nine features in three windows, parameters chosen for 1e-4
+    p = workloads.headline(1_000_000)
+    plan = make_plan(A, p, F32, target_err=1e-4)
+    assert all(plan.info(l).per_cell == 1 for l in range(plan.P))
+    a = p.alpha[:, 0]
+    out = gpu_matvec(A, plan, a, p.beta)
+    rows = np.random.default_rng(8).choice(p.N, 128, replace=False)
+    ref = oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a, rows=rows)
+    e = float(np.max(np.abs(out[rows] - ref)) / np.abs(a).sum())
+    print(f"N=1e6 auto sampled-row E = {e:.3e}")
+    assert e <= 1e-4
