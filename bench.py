@@ -45,27 +45,32 @@ def parse():
 
 
 def alg_bytes(stage: str, N: int, G: int, elem: int, P: int = 3) -> float:
-    """Algorithmic HBM bytes of one launch of a stage for one window.
-    spread : node record (16 B f32 / 32 B f64) + permutation 4 B + alpha 8 B
-             per point, one write of each grid value;
-    gather : node record + one value written per point (4 B f32 / 8 B f64),
-             one read of each grid value;
-    combine (all windows): alpha read and output write 16 B per point, plus
-             the inverse permutation and the window's value per point and
-             window;
+    """Algorithmic HBM bytes of a stage for one window (the combine: for the
+    whole product).  elem = 4 B (float32 NFFT) or 8 B (float64):
+    permute : permutation index 4 B, the gathered float64 coefficient 8 B and
+              the sorted coefficient written (elem) per point;
+    spread  : node record (16 B f32 / 32 B f64) + sorted coefficient per
+              point, one write of each grid value;
+    tile_sum, fold : one write of each grid value (the tile regions they read
+              are traffic of this implementation, not of the method);
     convolve (one axis pass): one read and one write of the grid;
-    fold   : one write of each grid value (the tile regions it reads are
-             traffic of this implementation, not of the method)."""
+    gather  : node record + one value written per point, one read of each
+              grid value;
+    combine (all windows): alpha read and output write 16 B per point, plus
+              the inverse permutation and the window's value per point and
+              window."""
     node = 16 if elem == 4 else 32
+    if stage == "permute":
+        return N * (4 + 8 + elem)
     if stage == "spread":
-        return N * (node + 4 + 8) + G * elem
+        return N * (node + elem) + G * elem
     if stage == "gather":
         return N * (node + elem) + G * elem
     if stage == "combine":
         return N * (16 + P * (4 + elem))
     if stage == "convolve":
         return 2.0 * G * elem
-    return float(G * elem)  # fold
+    return float(G * elem)  # tile_sum, fold
 
 
 def time_matvecs(A, torch, plan, a, out, beta, steps, warmup):
@@ -125,13 +130,15 @@ def main():
     gpu_out = out.cpu().numpy()
 
     G = infos[0].n ** infos[0].d_A
+    P = plan.P
     per_launch = {}
     for k, (tot, cnt) in stages.items():
         if cnt:
+            # one launch group covers all P windows (combine: the whole product)
             avg_ms = tot / cnt
-            per_launch[k] = dict(avg_us=avg_ms * 1e3, launches=cnt,
-                                 alg_bytes=alg_bytes(k, N, G, 4),
-                                 gbs=alg_bytes(k, N, G, 4) / (avg_ms * 1e-3) / 1e9)
+            b = alg_bytes(k, N, G, 4, P) * (1 if k == "combine" else P)
+            per_launch[k] = dict(avg_us=avg_ms * 1e3, launches=cnt, alg_bytes=b,
+                                 gbs=b / (avg_ms * 1e-3) / 1e9)
     dom = max(per_launch, key=lambda k: per_launch[k]["avg_us"])
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(per_launch[dom]["gbs"], 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -160,6 +160,47 @@ anova_status krr_cg_solve(anova_plan_t plan, const double *y, double *alpha, int
                           int64_t ld, double beta, double tol, int32_t maxit,
                           krr_cg_info *info, void *stream);
 
+/*
+ * Solves that advance together.  krr_cg_start sets up one problem's CG
+ * (x0 = 0, r = p = y) for nrhs columns on `stream` (asynchronous); alpha
+ * receives the iterate and must stay valid until krr_cg_destroy.
+ * krr_cg_iterate runs `iters` CG iterations of every listed solve (each
+ * column stops at its own tolerance or maxit): one iteration is a batched
+ * product over every (solve, window, column), one launch per stage and
+ * kernel signature, plus five float64 vector kernels over all columns of
+ * all solves; it is captured once per solve list into a hipGraph and
+ * replayed (lists of up to 4 recently used combinations are cached).  At
+ * each column's iterations 50, 100, ... its residual is recomputed as
+ * y - A x, so a column iterates the same way alone and in any list.  The solves
+ * of one list must share the precision; a solve may appear in several lists
+ * over time (continuous batching).  Asynchronous on `stream`.
+ * krr_cg_poll reads the number of still-iterating columns and the current
+ * per-column info (synchronises).  krr_cg_finish recomputes the true residual
+ * of every column and returns ANOVA_OK, ANOVA_E_NOT_CONVERGED or
+ * ANOVA_E_BREAKDOWN like krr_cg_solve (synchronises).  krr_cg_destroy frees
+ * the solve (synchronises the device; NULL is a no-op).
+ * Not thread-safe across threads sharing solves.
+ */
+anova_status krr_cg_start(anova_cg_t *out, anova_plan_t plan, const double *y, double *alpha,
+                          int32_t nrhs, int64_t ld, double beta, double tol, int32_t maxit,
+                          void *stream);
+anova_status krr_cg_iterate(anova_cg_t *solves, int32_t count, int32_t iters, void *stream);
+anova_status krr_cg_poll(anova_cg_t solve, int32_t *active, krr_cg_info *info, void *stream);
+anova_status krr_cg_finish(anova_cg_t solve, krr_cg_info *info, void *stream);
+anova_status krr_cg_destroy(anova_cg_t solve);
+
+/*
+ * Solve `count` independent problems together (krr_cg_start for each,
+ * krr_cg_iterate over the list of unfinished ones until every column has
+ * stopped, krr_cg_finish, krr_cg_destroy).  Arrays of `count` entries;
+ * info receives sum(nrhs) entries, problem by problem.  Returns the worst
+ * status over the problems.  Synchronises `stream`.
+ */
+anova_status krr_cg_solve_batched(int32_t count, const anova_plan_t *plans,
+                                  const double *const *y, double *const *alpha,
+                                  const int32_t *nrhs, const int64_t *ld, const double *beta,
+                                  double tol, int32_t maxit, krr_cg_info *info, void *stream);
+
 /* Free every resource of the plan (synchronises the device).  NULL is a no-op. */
 anova_status anova_plan_destroy(anova_plan_t plan);
 
@@ -202,14 +243,16 @@ anova_status anova_stage_gather(anova_plan_t plan, int32_t l, const void *grid, 
 /*
  * Per-stage device-time accounting, for benchmarks.  While enabled, every
  * anova_matvec and krr_cg_solve matvec records HIP events on the caller's
- * stream around each launch group of the five stage kinds, in this order:
- * 0 fold (adding the spread tile regions into the grid), 1 spread into tile
- * regions (with the permutation of the coefficients into sorted order),
- * 2 convolve (FFT, multiply, inverse FFT; one launch per axis), 3 gather
- * (interpolation at the points, sorted order), 4 combine (weighted sum over
- * windows plus the shift, in the caller's order).  anova_plan_stage_times
- * synchronises, writes the accumulated milliseconds and launch counts per
- * kind (host arrays of 5) and resets the counters.  Enabling adds a few microseconds of
+ * stream around each launch group of the seven stage kinds, in execution
+ * order: 0 permute (coefficients into each window's sorted point order),
+ * 1 spread (window-weighted sums into per-tile grid regions), 2 tile sum
+ * (regions of one tile added, where a tile holds several), 3 fold (tile
+ * regions added into the grid with periodic wrap), 4 convolve (FFT, multiply,
+ * inverse FFT; one launch per axis), 5 gather (interpolation at the points,
+ * sorted order), 6 combine (weighted sum over windows plus the shift, in the
+ * caller's order).  anova_plan_stage_times synchronises, writes the
+ * accumulated milliseconds and launch counts per kind (host arrays of 7) and
+ * resets the counters.  Enabling adds a few microseconds of
  * event overhead per launch; disabled by default.
  */
 anova_status anova_plan_set_timing(anova_plan_t plan, int32_t enable);

@@ -87,6 +87,14 @@ def load():
         "anova_stage_convolve": [VP, i32, VP, VP],
         "anova_stage_gather": [VP, i32, VP, VP, VP],
         "anova_plan_set_timing": [VP, i32],
+        "krr_cg_start": [ctypes.POINTER(VP), VP, VP, VP, i32, i64, dbl, dbl, i32, VP],
+        "krr_cg_iterate": [ctypes.POINTER(VP), i32, i32, VP],
+        "krr_cg_poll": [VP, ctypes.POINTER(i32), ctypes.POINTER(krr_cg_info), VP],
+        "krr_cg_finish": [VP, ctypes.POINTER(krr_cg_info), VP],
+        "krr_cg_destroy": [VP],
+        "krr_cg_solve_batched": [i32, ctypes.POINTER(VP), ctypes.POINTER(VP), ctypes.POINTER(VP),
+                                 ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(dbl),
+                                 dbl, i32, ctypes.POINTER(krr_cg_info), VP],
         "anova_plan_stage_times": [VP, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
     }
     for name, args in sigs.items():
@@ -176,6 +184,9 @@ class WindowInfo:
     tile: int
 
 
+STAGE_KINDS = ("permute", "spread", "tile_sum", "fold", "convolve", "gather", "combine")
+
+
 class Plan:
     """Owning wrapper over an anova_plan_t."""
 
@@ -205,11 +216,11 @@ class Plan:
         _check(load().anova_plan_set_timing(self.handle, 1 if enable else 0))
 
     def stage_times(self):
-        """{kind: (total_ms, launches)} for fold/spread/convolve/gather/combine; resets."""
-        ms = (ctypes.c_double * 5)()
-        cnt = (ctypes.c_int64 * 5)()
+        """{kind: (total_ms, launches)} per stage kind, in execution order; resets."""
+        ms = (ctypes.c_double * len(STAGE_KINDS))()
+        cnt = (ctypes.c_int64 * len(STAGE_KINDS))()
         _check(load().anova_plan_stage_times(self.handle, ms, cnt))
-        return {k: (ms[i], cnt[i]) for i, k in enumerate(["fold", "spread", "convolve", "gather", "combine"])}
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(STAGE_KINDS)}
 
     def err_estimate(self) -> float:
         return sum(self.info(l).err_total for l in range(self.P))
@@ -278,3 +289,83 @@ def anova_stage_convolve(plan: Plan, l: int, grid, stream=None) -> None:
 def anova_stage_gather(plan: Plan, l: int, grid, out, stream=None) -> None:
     po, _, _ = _colmajor(out, "out", plan.N)
     _check(load().anova_stage_gather(plan.handle, l, grid.data_ptr(), po, _stream(stream)))
+
+
+def _info_dicts(info, st):
+    return [dict(iters=i.iters, converged=bool(i.converged), relres=i.relres,
+                 true_relres=i.true_relres, status=STATUS_NAMES[st]) for i in info]
+
+
+class Solve:
+    """One problem's CG state (krr_cg_start ... krr_cg_destroy).  y and alpha
+    must stay alive until destroy(); several solves advance together with
+    krr_cg_iterate."""
+
+    def __init__(self, plan: Plan, y, alpha, beta: float, tol: float, maxit: int, stream=None):
+        py, nrhs, ldy = _colmajor(y, "y", plan.N)
+        pa, nrhs2, lda = _colmajor(alpha, "alpha", plan.N)
+        if nrhs != nrhs2 or ldy != lda:
+            raise ValueError("y and alpha must have the same shape and leading dimension")
+        h = VP()
+        _check(load().krr_cg_start(ctypes.byref(h), plan.handle, py, pa, nrhs, lda, float(beta),
+                                   float(tol), int(maxit), _stream(stream)))
+        self.handle = h.value
+        self.plan, self.y, self.alpha, self.nrhs = plan, y, alpha, nrhs
+
+    def poll(self, stream=None):
+        """(number of iterating columns, per-column info)"""
+        a = ctypes.c_int32()
+        info = (krr_cg_info * self.nrhs)()
+        _check(load().krr_cg_poll(self.handle, ctypes.byref(a), info, _stream(stream)))
+        return a.value, _info_dicts(info, ANOVA_OK)
+
+    def finish(self, stream=None, allow_not_converged: bool = True):
+        info = (krr_cg_info * self.nrhs)()
+        st = load().krr_cg_finish(self.handle, info, _stream(stream))
+        allow = (ANOVA_OK, ANOVA_E_NOT_CONVERGED) if allow_not_converged else (ANOVA_OK,)
+        _check(st, allow)
+        return _info_dicts(info, st)
+
+    def destroy(self):
+        if self.handle:
+            _check(load().krr_cg_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def krr_cg_iterate(solves: Sequence["Solve"], iters: int, stream=None) -> None:
+    arr = (VP * len(solves))(*[s.handle for s in solves])
+    _check(load().krr_cg_iterate(arr, len(solves), int(iters), _stream(stream)))
+
+
+def krr_cg_solve_batched(plans, ys, alphas, betas, tol: float, maxit: int, stream=None,
+                         allow_not_converged: bool = False):
+    """Solve several problems together; returns one info list per problem."""
+    n = len(plans)
+    P = (VP * n)(*[p.handle for p in plans])
+    Y = (VP * n)()
+    A = (VP * n)()
+    R = (ctypes.c_int32 * n)()
+    L = (ctypes.c_int64 * n)()
+    B = (ctypes.c_double * n)(*[float(b) for b in betas])
+    for i, (p, y, a) in enumerate(zip(plans, ys, alphas)):
+        py, nrhs, ldy = _colmajor(y, "y", p.N)
+        pa, nrhs2, lda = _colmajor(a, "alpha", p.N)
+        if nrhs != nrhs2 or ldy != lda:
+            raise ValueError("y and alpha must have the same shape and leading dimension")
+        Y[i], A[i], R[i], L[i] = py, pa, nrhs, lda
+    info = (krr_cg_info * sum(R))()
+    st = load().krr_cg_solve_batched(n, P, Y, A, R, L, B, float(tol), int(maxit), info,
+                                     _stream(stream))
+    allow = (ANOVA_OK, ANOVA_E_NOT_CONVERGED) if allow_not_converged else (ANOVA_OK,)
+    _check(st, allow)
+    out, k = [], 0
+    for i in range(n):
+        out.append(_info_dicts(info[k:k + R[i]], st))
+        k += R[i]
+    return out

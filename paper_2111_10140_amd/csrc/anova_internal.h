@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -144,6 +145,10 @@ struct WindowPlan {
 
 }  // namespace anova
 
+namespace anova {
+class Batch;
+}
+
 struct anova_plan_s {
     int64_t N = 0;
     int32_t d = 0;
@@ -151,16 +156,10 @@ struct anova_plan_s {
     int32_t precision = 0;
     double ell = 0;
     std::vector<anova::WindowPlan> win;
-    // work space
-    anova::DevBuf grid;      // largest window grid (float or double) x grid_slots
-    anova::DevBuf priv;      // spread regions: max over windows of n_sub x region (float/double)
-    anova::DevBuf treg;      // per-tile sums of the regions (windows whose tiles have several)
-    anova::DevBuf asort;     // coefficients in a window's sorted order (float or double), N
-    anova::DevBuf tmp;       // per-window interpolated values, P x N (float or double)
-    anova::DevBuf combine;   // CombineWin[P]
-    size_t grid_slot_elems = 0;
-    int grid_slots = 0;
     int device = 0;
+    // batched launches of this plan's own products (anova_matvec), reused
+    // while the vectors and the shift stay the same
+    std::unique_ptr<anova::Batch> mv_batch;
     // optional per-stage timing (events on the launching stream)
     bool timing = false;
     struct TimedLaunch {
@@ -173,41 +172,120 @@ struct anova_plan_s {
 
 namespace anova {
 
-// kernel launchers (kernels.hip)
-void launch_spread(const WindowPlan &w, int precision, const double *alpha, void *grid, void *as,
-                   void *priv, void *treg, hipStream_t s);
-void launch_spread_regions(const WindowPlan &w, int precision, const double *alpha, void *as,
-                           void *priv, hipStream_t s);
-void launch_fold(const WindowPlan &w, int precision, const void *priv, void *treg, void *grid,
-                 hipStream_t s);
-void launch_convolve(const WindowPlan &w, int precision, void *grid, hipStream_t s);
-void launch_gather(const WindowPlan &w, int precision, const void *grid, void *tmp,
-                   hipStream_t s);
-void launch_combine(const void *wins, int P, int precision, const double *alpha, double *out,
-                    double beta, int64_t N, bool accumulate, hipStream_t s);
-void launch_zero(void *p, size_t bytes, hipStream_t s);
-
-// one matvec of a plan for a single column (plan.hip)
-void plan_matvec(anova_plan_s *p, const double *alpha, double *out, double beta, hipStream_t s);
-void ensure_grid(anova_plan_s *p, int slots);
-
-// stage kinds for the optional timing
-enum StageKind {
-    kStageFold = 0,
-    kStageSpread = 1,
-    kStageConvolve = 2,
-    kStageGather = 3,
-    kStageCombine = 4,
-    kStageKinds = 5
+// ---------------------------------------------------------------- batched launches
+// One window of one problem for one right-hand side, as seen by the kernels.
+struct WinInst {
+    const void *nodes;          // NodeF32 / NodeF64, sorted order
+    const int32_t *perm;        // sorted position -> caller's index
+    const SubProblem *subs;     // per-point mode work items
+    const int32_t *tiles_ne;    // per-cell mode: non-empty tile ids
+    const int32_t *cell_start;  // per-cell mode: point offsets per (tile, cell)
+    const int32_t *src_sub;     // regions of each non-empty tile
+    const int2 *fold_pairs;
+    const int32_t *fold_start;
+    const void *poly;
+    const void *bconv;
+    const void *twiddle;
+    const double *alpha;        // input column, caller's order
+    void *priv;                 // spread regions
+    void *treg;                 // per-tile region sums
+    void *grid;                 // n^dA grid
+    void *tmp;                  // interpolated values, sorted order
+    int32_t n, tile, tpd, chunks;
+    int32_t vol, n_sub, n_nonempty, n_tiles;
+    int32_t n_regions, N, dA, width;
 };
-// records an event pair around `launch` when the plan's timing is enabled
-template <typename F>
-void timed_launch(anova_plan_s *p, int kind, hipStream_t s, F &&launch);
-hipEvent_t pool_event(anova_plan_s *p);
 
+// One output column of the combine kernel.
+struct CombInst {
+    double *out;
+    const double *alpha;
+    double beta;
+    int32_t N, win0, P, accumulate;
+};
+
+// Stage identifiers; the first five are the reported timing kinds.
+enum StageKind {
+    kStagePermute = 0,
+    kStageSpread = 1,
+    kStageTileSum = 2,
+    kStageFold = 3,
+    kStageConvolve = 4,
+    kStageGather = 5,
+    kStageCombine = 6,
+    kStageKinds = 7
+};
+
+// A launch: all instances of one stage sharing a kernel signature.
+struct BatchGroup {
+    int stage = 0;
+    int cell = 0, dA = 0, W = 0, tile = 0, n = 0, axis = 0, np = 1;
+    int blocks = 0, cnt = 0;
+    const int32_t *members = nullptr;  // device: instance indices
+    const int32_t *prefix = nullptr;   // device: block prefix (cnt + 1)
+};
+
+// Problem handed to a batch: a plan applied to nrhs columns.
+struct BatchProblem {
+    anova_plan_s *plan = nullptr;
+    const double *alpha = nullptr;  // device, column-major, leading dimension ld
+    double *out = nullptr;
+    int nrhs = 1;
+    int64_t ld = 0;                 // column stride of alpha
+    int64_t ld_out = -1;            // column stride of out (-1: same as ld)
+    double beta = 0.0;
+    int only_window = -1;           // >= 0: stage entry points (one window)
+    void *grid_override = nullptr;  // stage entry points: the caller's grid
+};
+
+// A set of products run with one launch per stage and kernel signature.
+class Batch {
+  public:
+    int precision = 0;
+    std::vector<WinInst> insts;
+    std::vector<CombInst> combs;
+    std::vector<CombineWin> cwins;
+    std::vector<BatchGroup> groups;  // execution order
+    DevBuf d_insts, d_combs, d_cwins, d_tables, work;
+    int comb_blocks = 0, comb_cnt = 0;
+    const int32_t *comb_prefix = nullptr;
+    std::vector<BatchProblem> probs;
+
+    // (re)build for the given problems; workspace is reused when it fits
+    void build(const std::vector<BatchProblem> &problems);
+    bool same(const std::vector<BatchProblem> &problems) const;
+    // stage mask: bit k = stage kind k (combine = 4)
+    void run(hipStream_t s, anova_plan_s *timing = nullptr, unsigned mask = 0xffu) const;
+};
+
+// kernel-side entry points (kernels.hip)
+void run_group(const BatchGroup &g, int precision, const WinInst *insts, hipStream_t s);
+void run_combine(const CombInst *cis, const CombineWin *wins, const int32_t *prefix, int cnt,
+                 int blocks, int precision, hipStream_t s);
+int convolve_lines_per_block(int n, int nq);
+int cell_tile(int dA);
+int cell_threads_per_cell(int dA);
+bool cell_width_supported(int dA, int W);
+int combine_span();
+int block_threads();
+
+// plan helpers (plan.hip)
+void plan_matvec(anova_plan_s *p, const double *alpha, double *out, int nrhs, int64_t ld,
+                 double beta, hipStream_t s);
+template <typename T>
+void upload(DevBuf &buf, const std::vector<T> &v) {
+    size_t bytes = v.size() * sizeof(T);
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (!buf.ptr || buf.bytes < bytes) buf.alloc(bytes);
+    if (!v.empty())
+        ANOVA_HIP_CHECK(hipMemcpy(buf.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// optional per-stage timing
+hipEvent_t pool_event(anova_plan_s *p);
 template <typename F>
 void timed_launch(anova_plan_s *p, int kind, hipStream_t s, F &&launch) {
-    if (!p->timing) {
+    if (!p || !p->timing) {
         launch();
         return;
     }

@@ -1,0 +1,300 @@
+// Batched products: every (problem, window, right-hand side) of a set of
+// products runs in one launch per stage and kernel signature.
+//
+// build() lays out one WinInst per instance (window data of the plan, the
+// input column, and a private slice of one work-space allocation: grid,
+// spread regions, per-tile region sums, interpolated values), groups the
+// instances of each stage by kernel signature, and uploads the instance and
+// group tables.  run() issues the stages in order: permute, spread, tile
+// sum, fold, convolve (one pass per axis), gather, combine.  Nothing is allocated or
+// copied in run(), so it can be captured in a hipGraph.
+#include <algorithm>
+#include <map>
+#include <tuple>
+
+#include "anova_internal.h"
+
+namespace anova {
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+struct Sizes {
+    size_t grid, priv, treg, tmp;
+};
+
+Sizes instance_sizes(const WindowPlan &w, size_t es, bool own_grid) {
+    Sizes z{};
+    z.grid = own_grid ? align256(w.grid_elems() * es) : 0;
+    z.priv = align256((size_t)w.n_regions * w.region_elems() * es);
+    z.treg = w.n_regions != w.n_nonempty ? align256((size_t)w.n_nonempty * w.region_elems() * es) : 0;
+    z.tmp = align256((size_t)w.n_points * es);
+    return z;
+}
+
+}  // namespace
+
+bool Batch::same(const std::vector<BatchProblem> &problems) const {
+    if (problems.size() != probs.size()) return false;
+    for (size_t i = 0; i < problems.size(); ++i) {
+        const BatchProblem &a = problems[i], &b = probs[i];
+        if (a.plan != b.plan || a.alpha != b.alpha || a.out != b.out || a.nrhs != b.nrhs ||
+            a.ld != b.ld || a.ld_out != b.ld_out || a.beta != b.beta ||
+            a.only_window != b.only_window ||
+            a.grid_override != b.grid_override)
+            return false;
+    }
+    return true;
+}
+
+void Batch::build(const std::vector<BatchProblem> &problems) {
+    ANOVA_REQUIRE(!problems.empty(), "empty batch");
+    precision = problems[0].plan->precision;
+    for (const BatchProblem &bp : problems)
+        ANOVA_REQUIRE(bp.plan->precision == precision, "a batch mixes float32 and float64 plans");
+    const size_t es = precision == ANOVA_FP64 ? 8 : 4;
+    insts.clear();
+    combs.clear();
+    cwins.clear();
+    groups.clear();
+    // ---- instances and work-space layout
+    struct Slot {
+        size_t grid, priv, treg, tmp;
+    };
+    std::vector<Slot> slots;
+    size_t total = 0;
+    for (const BatchProblem &bp : problems) {
+        anova_plan_s *p = bp.plan;
+        for (int c = 0; c < bp.nrhs; ++c) {
+            CombInst ci{};
+            const int64_t ldo = bp.ld_out >= 0 ? bp.ld_out : bp.ld;
+            ci.out = bp.out ? bp.out + (size_t)c * ldo : nullptr;
+            ci.alpha = bp.alpha + (size_t)c * bp.ld;
+            ci.beta = bp.beta;
+            ci.N = (int32_t)p->N;
+            ci.win0 = (int32_t)cwins.size();
+            ci.accumulate = bp.only_window >= 0 ? 1 : 0;
+            int nw = 0;
+            for (int l = 0; l < p->P; ++l) {
+                if (bp.only_window >= 0 && l != bp.only_window) continue;
+                const WindowPlan &w = p->win[l];
+                const Sizes z = instance_sizes(w, es, bp.grid_override == nullptr);
+                Slot sl{total, total + z.grid, total + z.grid + z.priv,
+                        total + z.grid + z.priv + z.treg};
+                total += z.grid + z.priv + z.treg + z.tmp;
+                slots.push_back(sl);
+                WinInst wi{};
+                wi.nodes = w.nodes.ptr;
+                wi.perm = w.perm.as<int32_t>();
+                wi.subs = w.subs.as<SubProblem>();
+                wi.tiles_ne = w.tiles_ne.as<int32_t>();
+                wi.cell_start = w.cell_start.as<int32_t>();
+                wi.src_sub = w.src_sub.as<int32_t>();
+                wi.fold_pairs = w.fold_pairs.as<int2>();
+                wi.fold_start = w.fold_start.as<int32_t>();
+                wi.poly = w.poly.ptr;
+                wi.bconv = w.bconv.ptr;
+                wi.twiddle = w.twiddle.ptr;
+                wi.alpha = ci.alpha;
+                wi.grid = bp.grid_override;  // patched below when owned
+                wi.n = w.n;
+                wi.tile = w.tile;
+                wi.tpd = w.tiles_per_dim;
+                wi.chunks = w.chunks;
+                wi.vol = (int32_t)w.region_elems();
+                wi.n_sub = (int32_t)w.n_sub;
+                wi.n_nonempty = (int32_t)w.n_nonempty;
+                wi.n_tiles = (int32_t)w.n_tiles;
+                wi.n_regions = (int32_t)w.n_regions;
+                wi.N = (int32_t)w.n_points;
+                wi.dA = w.dA;
+                wi.width = 2 * w.m;
+                insts.push_back(wi);
+                cwins.push_back(CombineWin{nullptr, w.iperm.as<int32_t>(), w.eta});
+                ++nw;
+            }
+            ci.P = nw;
+            combs.push_back(ci);
+        }
+    }
+    if (!work.ptr || work.bytes < total) work.alloc(total);
+    char *base = static_cast<char *>(work.ptr);
+    for (size_t i = 0; i < insts.size(); ++i) {
+        if (!insts[i].grid) insts[i].grid = base + slots[i].grid;
+        insts[i].priv = base + slots[i].priv;
+        insts[i].treg = base + slots[i].treg;
+        insts[i].tmp = base + slots[i].tmp;
+        cwins[i].tmp = insts[i].tmp;
+    }
+    // ---- groups: key -> member list, per stage
+    std::vector<int32_t> table;  // all members and prefixes, packed
+    struct PendingGroup {
+        BatchGroup g;
+        std::vector<int32_t> members, blocks;
+    };
+    std::vector<PendingGroup> pending;
+    auto add_stage = [&](int stage, auto key_of, auto blocks_of, auto fill) {
+        std::map<std::tuple<int, int, int, int, int, int>, size_t> idx;
+        for (size_t i = 0; i < insts.size(); ++i) {
+            int b = 0;
+            if (!blocks_of(insts[i], b) || b <= 0) continue;
+            const auto key = key_of(insts[i]);
+            auto it = idx.find(key);
+            if (it == idx.end()) {
+                PendingGroup pg;
+                pg.g.stage = stage;
+                fill(pg.g, insts[i]);
+                it = idx.emplace(key, pending.size()).first;
+                pending.push_back(pg);
+            }
+            pending[it->second].members.push_back((int32_t)i);
+            pending[it->second].blocks.push_back(b);
+        }
+    };
+    // permute: coefficients into each window's sorted order
+    add_stage(
+        kStagePermute, [](const WinInst &) { return std::make_tuple(0, 0, 0, 0, 0, 0); },
+        [](const WinInst &w, int &b) {
+            b = (w.N + 4 * block_threads() - 1) / (4 * block_threads());
+            return true;
+        },
+        [](BatchGroup &, const WinInst &) {});
+    // spread
+    add_stage(
+        kStageSpread,
+        [](const WinInst &w) {
+            return std::make_tuple(w.cell_start != nullptr ? 1 : 0, w.dA, w.width, w.tile, 0, 0);
+        },
+        [](const WinInst &w, int &b) {
+            b = w.cell_start != nullptr ? w.n_nonempty * w.chunks : w.n_sub;
+            return true;
+        },
+        [](BatchGroup &g, const WinInst &w) {
+            g.cell = w.cell_start != nullptr ? 1 : 0;
+            g.dA = w.dA;
+            g.W = w.width;
+            g.tile = w.tile;
+        });
+    // tile sum (instances whose tiles hold several regions)
+    add_stage(
+        kStageTileSum, [](const WinInst &) { return std::make_tuple(0, 0, 0, 0, 0, 0); },
+        [](const WinInst &w, int &b) {
+            if (w.n_regions == w.n_nonempty) return false;
+            b = w.n_nonempty * ((w.vol + 255) / 256);
+            return true;
+        },
+        [](BatchGroup &, const WinInst &) {});
+    // fold
+    add_stage(
+        kStageFold, [](const WinInst &w) { return std::make_tuple(w.dA, 0, 0, 0, 0, 0); },
+        [](const WinInst &w, int &b) {
+            b = w.n_tiles;
+            return true;
+        },
+        [](BatchGroup &g, const WinInst &w) { g.dA = w.dA; });
+    // convolve, one pass per axis
+    for (int axis = 0; axis < 3; ++axis) {
+        add_stage(
+            kStageConvolve, [](const WinInst &w) { return std::make_tuple(w.n, w.dA, 0, 0, 0, 0); },
+            [axis](const WinInst &w, int &b) {
+                if (axis >= w.dA) return false;
+                int nlines = 1;
+                for (int t = 1; t < w.dA; ++t) nlines *= w.n;
+                const int nq = (nlines + 1) / 2;
+                const int np = convolve_lines_per_block(w.n, nq);
+                b = (nq + np - 1) / np;
+                return true;
+            },
+            [axis](BatchGroup &g, const WinInst &w) {
+                g.n = w.n;
+                g.axis = axis;
+                // instances of one group share n and d_A, hence the line count
+                int nlines = 1;
+                for (int t = 1; t < w.dA; ++t) nlines *= w.n;
+                g.np = convolve_lines_per_block(w.n, (nlines + 1) / 2);
+            });
+    }
+    // gather
+    add_stage(
+        kStageGather,
+        [](const WinInst &w) {
+            return std::make_tuple(w.cell_start != nullptr ? 1 : 0, w.dA, w.width, w.tile, 0, 0);
+        },
+        [](const WinInst &w, int &b) {
+            b = w.cell_start != nullptr ? w.n_nonempty * w.chunks : w.n_sub;
+            return true;
+        },
+        [](BatchGroup &g, const WinInst &w) {
+            g.cell = w.cell_start != nullptr ? 1 : 0;
+            g.dA = w.dA;
+            g.W = w.width;
+            g.tile = w.tile;
+        });
+    // pack tables
+    std::vector<size_t> moff, poff;
+    for (PendingGroup &pg : pending) {
+        moff.push_back(table.size());
+        table.insert(table.end(), pg.members.begin(), pg.members.end());
+        poff.push_back(table.size());
+        int acc = 0;
+        table.push_back(0);
+        for (int b : pg.blocks) {
+            acc += b;
+            table.push_back(acc);
+        }
+        pg.g.blocks = acc;
+        pg.g.cnt = (int)pg.members.size();
+    }
+    // combine prefix
+    const size_t coff = table.size();
+    {
+        int acc = 0;
+        table.push_back(0);
+        for (const CombInst &ci : combs) {
+            acc += (ci.N + combine_span() - 1) / combine_span();
+            table.push_back(acc);
+        }
+        comb_blocks = acc;
+        comb_cnt = (int)combs.size();
+    }
+    upload(d_tables, table);
+    upload(d_insts, insts);
+    upload(d_combs, combs);
+    upload(d_cwins, cwins);
+    const int32_t *tb = d_tables.as<int32_t>();
+    for (size_t k = 0; k < pending.size(); ++k) {
+        pending[k].g.members = tb + moff[k];
+        pending[k].g.prefix = tb + poff[k];
+        groups.push_back(pending[k].g);
+    }
+    comb_prefix = tb + coff;
+    probs = problems;
+}
+
+void Batch::run(hipStream_t s, anova_plan_s *timing, unsigned mask) const {
+    const WinInst *di = d_insts.as<WinInst>();
+    size_t k = 0;
+    // groups are stored stage by stage in execution order
+    while (k < groups.size()) {
+        const int stage = groups[k].stage;
+        size_t e = k;
+        while (e < groups.size() && groups[e].stage == stage &&
+               (stage != kStageConvolve || groups[e].axis == groups[k].axis))
+            ++e;
+        if (mask & (1u << stage)) {
+            timed_launch(timing, stage, s, [&] {
+                for (size_t q = k; q < e; ++q) run_group(groups[q], precision, di, s);
+            });
+        }
+        k = e;
+    }
+    if ((mask & (1u << kStageCombine)) && comb_cnt > 0) {
+        timed_launch(timing, kStageCombine, s, [&] {
+            run_combine(d_combs.as<CombInst>(), d_cwins.as<CombineWin>(), comb_prefix, comb_cnt,
+                        comb_blocks, precision, s);
+        });
+    }
+}
+
+}  // namespace anova

@@ -2,25 +2,32 @@
 // symmetric positive definite for beta > 0 and is solved by CG with one
 // kernel product per iteration; no preconditioner, Sec. 6).
 //
-// Everything except the kernel product runs in float64 on the device: dot
-// products are two-stage reductions (per-block partial sums, then one
-// workgroup per column adding the partials in a fixed order, so results do
-// not depend on scheduling), and the CG scalars stay in device memory, so an
-// iteration needs no host round trip.  Each iteration is captured once into a
-// hipGraph and replayed; the host reads the convergence flags every few
-// iterations.  Every kResidualPeriod iterations the recursive residual is
-// replaced by y - A x (residual replacement), and at exit the true residual
-// is recomputed for the report.
+// A solve (anova_cg_s) holds one problem's CG state for nrhs independent
+// columns.  krr_cg_iterate advances any list of solves together: one
+// iteration is a batched product over every (solve, window, column) followed
+// by five vector kernels over the list of all columns, so problems of
+// different sizes share each launch.  Everything except the product runs in
+// float64: dot products are two-stage reductions (per-block partial sums,
+// then one workgroup per column adding its partials in a fixed order, so
+// results do not depend on scheduling), and the CG scalars stay in device
+// memory, so an iteration needs no host round trip.  The iteration is
+// captured once per solve list into a hipGraph and replayed.  At every
+// kResidualPeriod-th iteration of a column its recursive residual is
+// replaced by y - A x (residual replacement); at the end the true residual
+// is recomputed.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
+#include <memory>
+#include <mutex>
 
 #include "anova_internal.h"
 
 namespace anova {
 
 constexpr int kRedBlock = 256;
+constexpr int kSpan = 4 * kRedBlock;  // elements per block and column
 constexpr int kResidualPeriod = 50;
-constexpr int kCheckEvery = 8;
 
 struct CgScal {
     double rho;      // r.r of the current residual
@@ -29,39 +36,60 @@ struct CgScal {
     double a, b;     // step length and direction update
     double pq;       // p.q of the current iteration
     int32_t active;  // 1 while the column iterates
-    int32_t status;  // 0 running/converged, 1 converged, 2 breakdown
+    int32_t status;  // 0 running, 1 converged, 2 breakdown, 3 maxit reached
     int32_t iters;
+    int32_t maxit;
+};
+
+// One column of one solve, as seen by the vector kernels.
+struct CgCol {
+    double *x;             // caller's alpha column
+    double *r, *p, *q;
+    const double *y;
+    double *partial;       // nblk partial sums
+    CgScal *sc;
+    int64_t N;
+    int32_t nblk;
     int32_t pad;
 };
 
-// ---------------------------------------------------------------- reductions
+// ---------------------------------------------------------------- device helpers
 __device__ __forceinline__ double block_sum(double v, double *sh) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0) sh[wid] = v;
     __syncthreads();
     double t = 0.0;
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
-    }
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kRedBlock / 64; ++i) t += sh[i];
     __syncthreads();
     return t;  // valid in thread 0
 }
 
-// partial[c*nblk + blockIdx.x] = sum over this block's share of a_c . b_c
-__global__ __launch_bounds__(kRedBlock) void dot_partial_kernel(
-    const double *__restrict__ a, int64_t lda, const double *__restrict__ b, int64_t ldb,
-    int64_t N, double *__restrict__ partial, int nblk) {
-    __shared__ double sh[kRedBlock / 64];
-    const int c = blockIdx.y;
-    const double *ac = a + (size_t)c * lda;
-    const double *bc = b + (size_t)c * ldb;
-    double v = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; i < N;
-         i += (int64_t)nblk * kRedBlock)
-        v += ac[i] * bc[i];
-    v = block_sum(v, sh);
-    if (threadIdx.x == 0) partial[(size_t)c * nblk + blockIdx.x] = v;
+__device__ __forceinline__ int find_col(const int32_t *__restrict__ prefix, int cnt, int b) {
+    int lo = 0, hi = cnt;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Block b of the column list: column c, element range [i0, i1).
+struct ColRange {
+    CgCol col;
+    int lb;
+    int64_t i0, i1;
+};
+__device__ __forceinline__ ColRange col_range(const CgCol *__restrict__ cols,
+                                              const int32_t *__restrict__ prefix, int cnt) {
+    const int c = find_col(prefix, cnt, blockIdx.x);
+    ColRange r;
+    r.col = cols[c];
+    r.lb = blockIdx.x - prefix[c];
+    r.i0 = (int64_t)r.lb * kSpan;
+    r.i1 = min(r.col.N, r.i0 + kSpan);
+    return r;
 }
 
 __device__ double sum_partials(const double *__restrict__ partial, int nblk, double *sh) {
@@ -70,212 +98,248 @@ __device__ double sum_partials(const double *__restrict__ partial, int nblk, dou
     return block_sum(v, sh);
 }
 
-// ---------------------------------------------------------------- CG steps
-// x = 0, r = y, p = y, partial r.r
-__global__ __launch_bounds__(kRedBlock) void cg_init_kernel(
-    const double *__restrict__ y, int64_t ldy, double *__restrict__ x, int64_t ldx,
-    double *__restrict__ r, double *__restrict__ p, int64_t N, double *__restrict__ partial,
-    int nblk) {
+// ---------------------------------------------------------------- CG kernels
+// x = 0, r = y, p = y, partial y.y
+__global__ __launch_bounds__(kRedBlock) void cg_init_kernel(const CgCol *__restrict__ cols,
+                                                            const int32_t *__restrict__ prefix,
+                                                            int cnt) {
     __shared__ double sh[kRedBlock / 64];
-    const int c = blockIdx.y;
+    const ColRange cr = col_range(cols, prefix, cnt);
     double v = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; i < N;
-         i += (int64_t)nblk * kRedBlock) {
-        const double yi = y[(size_t)c * ldy + i];
-        x[(size_t)c * ldx + i] = 0.0;
-        r[(size_t)c * N + i] = yi;
-        p[(size_t)c * N + i] = yi;
+    for (int64_t i = cr.i0 + threadIdx.x; i < cr.i1; i += kRedBlock) {
+        const double yi = cr.col.y[i];
+        cr.col.x[i] = 0.0;
+        cr.col.r[i] = yi;
+        cr.col.p[i] = yi;
         v += yi * yi;
     }
     v = block_sum(v, sh);
-    if (threadIdx.x == 0) partial[(size_t)c * nblk + blockIdx.x] = v;
+    if (threadIdx.x == 0) cr.col.partial[cr.lb] = v;
 }
 
-__global__ __launch_bounds__(kRedBlock) void cg_init_scal_kernel(
-    const double *__restrict__ partial, int nblk, CgScal *__restrict__ sc, double tol) {
+__global__ __launch_bounds__(kRedBlock) void cg_init_scal_kernel(const CgCol *__restrict__ cols,
+                                                                 double tol, int maxit) {
     __shared__ double sh[kRedBlock / 64];
-    const int c = blockIdx.x;
-    const double y2 = sum_partials(partial + (size_t)c * nblk, nblk, sh);
+    const CgCol col = cols[blockIdx.x];
+    const double y2 = sum_partials(col.partial, col.nblk, sh);
     if (threadIdx.x == 0) {
         CgScal s{};
         s.rho = y2;
         s.ynorm2 = y2;
         s.tol2 = tol * tol;
-        s.active = (y2 > 0.0 && std::isfinite(y2)) ? 1 : 0;
-        s.status = y2 > 0.0 ? (std::isfinite(y2) ? 0 : 2) : 1;
+        s.active = (y2 > 0.0 && isfinite(y2)) ? 1 : 0;
+        s.status = y2 > 0.0 ? (isfinite(y2) ? 0 : 2) : 1;
         s.iters = 0;
-        sc[c] = s;
+        s.maxit = maxit;
+        *col.sc = s;
     }
 }
 
-// a = rho / (p.q)
-__global__ __launch_bounds__(kRedBlock) void cg_alpha_kernel(
-    const double *__restrict__ partial, int nblk, CgScal *__restrict__ sc) {
+// partial p.q
+__global__ __launch_bounds__(kRedBlock) void cg_dot_pq_kernel(const CgCol *__restrict__ cols,
+                                                              const int32_t *__restrict__ prefix,
+                                                              int cnt) {
     __shared__ double sh[kRedBlock / 64];
-    const int c = blockIdx.x;
-    const double pq = sum_partials(partial + (size_t)c * nblk, nblk, sh);
+    const ColRange cr = col_range(cols, prefix, cnt);
+    double v = 0.0;
+    for (int64_t i = cr.i0 + threadIdx.x; i < cr.i1; i += kRedBlock) v += cr.col.p[i] * cr.col.q[i];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) cr.col.partial[cr.lb] = v;
+}
+
+// a = rho / (p.q)
+__global__ __launch_bounds__(kRedBlock) void cg_alpha_kernel(const CgCol *__restrict__ cols) {
+    __shared__ double sh[kRedBlock / 64];
+    const CgCol col = cols[blockIdx.x];
+    const double pq = sum_partials(col.partial, col.nblk, sh);
     if (threadIdx.x == 0) {
-        CgScal s = sc[c];
+        CgScal s = *col.sc;
         s.pq = pq;
         if (s.active) {
-            if (!(pq > 0.0) || !std::isfinite(pq)) {
+            if (!(pq > 0.0) || !isfinite(pq)) {
                 s.active = 0;
                 s.status = 2;
             } else {
                 s.a = s.rho / pq;
             }
         }
-        sc[c] = s;
+        *col.sc = s;
     }
 }
 
 // x += a p; r -= a q; partial r.r
-__global__ __launch_bounds__(kRedBlock) void cg_update_xr_kernel(
-    double *__restrict__ x, int64_t ldx, double *__restrict__ r, const double *__restrict__ p,
-    const double *__restrict__ q, int64_t N, const CgScal *__restrict__ sc,
-    double *__restrict__ partial, int nblk) {
+__global__ __launch_bounds__(kRedBlock) void cg_update_xr_kernel(const CgCol *__restrict__ cols,
+                                                                 const int32_t *__restrict__ prefix,
+                                                                 int cnt) {
     __shared__ double sh[kRedBlock / 64];
-    const int c = blockIdx.y;
-    const bool act = sc[c].active != 0;
-    const double a = sc[c].a;
+    const ColRange cr = col_range(cols, prefix, cnt);
+    const CgScal sc = *cr.col.sc;
     double v = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; i < N;
-         i += (int64_t)nblk * kRedBlock) {
-        double ri = r[(size_t)c * N + i];
-        if (act) {
-            x[(size_t)c * ldx + i] += a * p[(size_t)c * N + i];
-            ri -= a * q[(size_t)c * N + i];
-            r[(size_t)c * N + i] = ri;
+    for (int64_t i = cr.i0 + threadIdx.x; i < cr.i1; i += kRedBlock) {
+        double ri = cr.col.r[i];
+        if (sc.active) {
+            cr.col.x[i] += sc.a * cr.col.p[i];
+            ri -= sc.a * cr.col.q[i];
+            cr.col.r[i] = ri;
         }
         v += ri * ri;
     }
     v = block_sum(v, sh);
-    if (threadIdx.x == 0) partial[(size_t)c * nblk + blockIdx.x] = v;
+    if (threadIdx.x == 0) cr.col.partial[cr.lb] = v;
 }
 
-// r = y - q (q = A x); partial r.r
-__global__ __launch_bounds__(kRedBlock) void cg_replace_kernel(
-    const double *__restrict__ y, int64_t ldy, double *__restrict__ r,
-    const double *__restrict__ q, int64_t N, const CgScal *__restrict__ sc,
-    double *__restrict__ partial, int nblk, int force) {
+// r = y - q (q = A x); partial r.r.  A column is replaced at its own
+// iterations kResidualPeriod, 2 kResidualPeriod, ... (the current iteration
+// is iters + 1), so the cadence does not depend on which other solves share
+// the launch; `force` replaces every column (final residual).
+__global__ __launch_bounds__(kRedBlock) void cg_replace_kernel(const CgCol *__restrict__ cols,
+                                                               const int32_t *__restrict__ prefix,
+                                                               int cnt, int force) {
     __shared__ double sh[kRedBlock / 64];
-    const int c = blockIdx.y;
-    const bool act = force || sc[c].active != 0;
+    const ColRange cr = col_range(cols, prefix, cnt);
+    const CgScal sc = *cr.col.sc;
+    const bool act = force || (sc.active != 0 && (sc.iters + 1) % kResidualPeriod == 0);
     double v = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; i < N;
-         i += (int64_t)nblk * kRedBlock) {
+    for (int64_t i = cr.i0 + threadIdx.x; i < cr.i1; i += kRedBlock) {
         double ri;
         if (act) {
-            ri = y[(size_t)c * ldy + i] - q[(size_t)c * N + i];
-            r[(size_t)c * N + i] = ri;
+            ri = cr.col.y[i] - cr.col.q[i];
+            cr.col.r[i] = ri;
         } else {
-            ri = r[(size_t)c * N + i];
+            ri = cr.col.r[i];
         }
         v += ri * ri;
     }
     v = block_sum(v, sh);
-    if (threadIdx.x == 0) partial[(size_t)c * nblk + blockIdx.x] = v;
+    if (threadIdx.x == 0) cr.col.partial[cr.lb] = v;
 }
 
-// rho' = r.r; convergence test; b = rho'/rho
-__global__ __launch_bounds__(kRedBlock) void cg_beta_kernel(
-    const double *__restrict__ partial, int nblk, CgScal *__restrict__ sc) {
+// rho' = r.r; convergence and iteration-limit tests; b = rho'/rho
+__global__ __launch_bounds__(kRedBlock) void cg_beta_kernel(const CgCol *__restrict__ cols) {
     __shared__ double sh[kRedBlock / 64];
-    const int c = blockIdx.x;
-    const double rr = sum_partials(partial + (size_t)c * nblk, nblk, sh);
+    const CgCol col = cols[blockIdx.x];
+    const double rr = sum_partials(col.partial, col.nblk, sh);
     if (threadIdx.x == 0) {
-        CgScal s = sc[c];
+        CgScal s = *col.sc;
         if (s.active) {
             s.iters += 1;
-            if (!std::isfinite(rr)) {
+            if (!isfinite(rr)) {
                 s.active = 0;
                 s.status = 2;
             } else if (rr <= s.tol2 * s.ynorm2) {
                 s.active = 0;
                 s.status = 1;
                 s.rho = rr;
+            } else if (s.iters >= s.maxit) {
+                s.active = 0;
+                s.status = 3;
+                s.rho = rr;
             } else {
                 s.b = rr / s.rho;
                 s.rho = rr;
             }
         }
-        sc[c] = s;
+        *col.sc = s;
     }
 }
 
 // p = r + b p
-__global__ __launch_bounds__(kRedBlock) void cg_update_p_kernel(
-    double *__restrict__ p, const double *__restrict__ r, int64_t N,
-    const CgScal *__restrict__ sc, int nblk) {
-    const int c = blockIdx.y;
-    if (!sc[c].active) return;
-    const double b = sc[c].b;
-    for (int64_t i = blockIdx.x * (int64_t)kRedBlock + threadIdx.x; i < N;
-         i += (int64_t)nblk * kRedBlock)
-        p[(size_t)c * N + i] = r[(size_t)c * N + i] + b * p[(size_t)c * N + i];
+__global__ __launch_bounds__(kRedBlock) void cg_update_p_kernel(const CgCol *__restrict__ cols,
+                                                                const int32_t *__restrict__ prefix,
+                                                                int cnt) {
+    const ColRange cr = col_range(cols, prefix, cnt);
+    const CgScal sc = *cr.col.sc;
+    if (!sc.active) return;
+    for (int64_t i = cr.i0 + threadIdx.x; i < cr.i1; i += kRedBlock)
+        cr.col.p[i] = cr.col.r[i] + sc.b * cr.col.p[i];
 }
 
-// ---------------------------------------------------------------- solver
-struct Solver {
+// ---------------------------------------------------------------- column lists
+struct ColList {
+    std::vector<CgCol> cols;
+    DevBuf d_cols, d_prefix;
+    int blocks = 0, cnt = 0;
+    void upload_lists() {
+        std::vector<int32_t> prefix(cols.size() + 1, 0);
+        for (size_t c = 0; c < cols.size(); ++c) prefix[c + 1] = prefix[c] + cols[c].nblk;
+        blocks = prefix.back();
+        cnt = (int)cols.size();
+        upload(d_cols, cols);
+        upload(d_prefix, prefix);
+    }
+};
+
+}  // namespace anova
+
+using namespace anova;
+
+static std::atomic<uint64_t> g_next_solve_id{1};
+
+struct anova_cg_s {
     anova_plan_s *plan = nullptr;
+    uint64_t id = 0;
     int nrhs = 0;
-    int64_t N = 0;
-    int nblk = 0;
+    int64_t N = 0, ld = 0;
+    const double *y = nullptr;
+    double *x = nullptr;
+    double beta = 1.0, tol = 0.0;
+    int maxit = 0;
+    int64_t it = 0;  // iterations taken (every active column has taken as many)
     DevBuf r, p, q, partial, scal;
+    ColList own;  // this solve's columns alone (init, final residual)
+    std::unique_ptr<Batch> xq;  // q = A x, for the final residual
+};
+
+namespace anova {
+
+// Captured iteration for one list of solves.
+struct StepGraph {
+    std::vector<uint64_t> ids;
+    std::vector<anova_cg_s *> solves;
+    ColList list;
+    Batch pq, xq;  // q = A p, q = A x over every solve in the list
     hipStream_t cap = nullptr;
     hipGraphExec_t g_plain = nullptr, g_replace = nullptr;
-    ~Solver() {
+    ~StepGraph() {
         if (g_plain) (void)hipGraphExecDestroy(g_plain);
         if (g_replace) (void)hipGraphExecDestroy(g_replace);
         if (cap) (void)hipStreamDestroy(cap);
     }
 };
 
-static void apply_A(Solver &S, const double *x, int64_t ldx, double *y, double beta,
-                    hipStream_t s) {
-    for (int c = 0; c < S.nrhs; ++c)
-        plan_matvec(S.plan, x + (size_t)c * ldx, y + (size_t)c * S.N, beta, s);
-}
+static std::mutex g_step_mu;
+static std::vector<std::unique_ptr<StepGraph>> g_steps;  // small cache of captured lists
+constexpr size_t kStepCache = 4;
 
-static void record_iteration(Solver &S, double *x, int64_t ldx, const double *y, int64_t ldy,
-                             double beta, bool replace, hipStream_t s) {
-    const dim3 g2(S.nblk, S.nrhs);
-    double *r = S.r.as<double>(), *p = S.p.as<double>(), *q = S.q.as<double>();
-    double *part = S.partial.as<double>();
-    CgScal *sc = S.scal.as<CgScal>();
-    apply_A(S, p, S.N, q, beta, s);
-    hipLaunchKernelGGL(dot_partial_kernel, g2, dim3(kRedBlock), 0, s, p, S.N, q, S.N, S.N, part,
-                       S.nblk);
-    hipLaunchKernelGGL(cg_alpha_kernel, dim3(S.nrhs), dim3(kRedBlock), 0, s, part, S.nblk, sc);
-    hipLaunchKernelGGL(cg_update_xr_kernel, g2, dim3(kRedBlock), 0, s, x, ldx, r, p, q, S.N, sc,
-                       part, S.nblk);
+static void record_iteration(StepGraph &G, bool replace, hipStream_t s) {
+    const ColList &L = G.list;
+    const CgCol *dc = L.d_cols.as<CgCol>();
+    const int32_t *dp = L.d_prefix.as<int32_t>();
+    G.pq.run(s);
+    hipLaunchKernelGGL(cg_dot_pq_kernel, dim3(L.blocks), dim3(kRedBlock), 0, s, dc, dp, L.cnt);
+    hipLaunchKernelGGL(cg_alpha_kernel, dim3(L.cnt), dim3(kRedBlock), 0, s, dc);
+    hipLaunchKernelGGL(cg_update_xr_kernel, dim3(L.blocks), dim3(kRedBlock), 0, s, dc, dp, L.cnt);
     if (replace) {
-        apply_A(S, x, ldx, q, beta, s);
-        hipLaunchKernelGGL(cg_replace_kernel, g2, dim3(kRedBlock), 0, s, y, ldy, r, q, S.N, sc,
-                           part, S.nblk, 0);
+        G.xq.run(s);
+        hipLaunchKernelGGL(cg_replace_kernel, dim3(L.blocks), dim3(kRedBlock), 0, s, dc, dp, L.cnt,
+                           0);
     }
-    hipLaunchKernelGGL(cg_beta_kernel, dim3(S.nrhs), dim3(kRedBlock), 0, s, part, S.nblk, sc);
-    hipLaunchKernelGGL(cg_update_p_kernel, g2, dim3(kRedBlock), 0, s, p, r, S.N, sc, S.nblk);
+    hipLaunchKernelGGL(cg_beta_kernel, dim3(L.cnt), dim3(kRedBlock), 0, s, dc);
+    hipLaunchKernelGGL(cg_update_p_kernel, dim3(L.blocks), dim3(kRedBlock), 0, s, dc, dp, L.cnt);
     ANOVA_HIP_CHECK(hipGetLastError());
 }
 
-static hipGraphExec_t capture(Solver &S, double *x, int64_t ldx, const double *y, int64_t ldy,
-                              double beta, bool replace) {
+static hipGraphExec_t capture(StepGraph &G, bool replace) {
     hipGraph_t g = nullptr;
-    // per-stage event timing is not recorded inside graphs
-    const bool timing = S.plan->timing;
-    S.plan->timing = false;
-    ANOVA_HIP_CHECK(hipStreamBeginCapture(S.cap, hipStreamCaptureModeThreadLocal));
+    ANOVA_HIP_CHECK(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
     try {
-        record_iteration(S, x, ldx, y, ldy, beta, replace, S.cap);
+        record_iteration(G, replace, G.cap);
     } catch (...) {
-        (void)hipStreamEndCapture(S.cap, &g);
+        (void)hipStreamEndCapture(G.cap, &g);
         if (g) (void)hipGraphDestroy(g);
-        S.plan->timing = timing;
         throw;
     }
-    S.plan->timing = timing;
-    ANOVA_HIP_CHECK(hipStreamEndCapture(S.cap, &g));
+    ANOVA_HIP_CHECK(hipStreamEndCapture(G.cap, &g));
     hipGraphExec_t ex = nullptr;
     const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
@@ -283,15 +347,104 @@ static hipGraphExec_t capture(Solver &S, double *x, int64_t ldx, const double *y
     return ex;
 }
 
+static BatchProblem product(anova_cg_s *sv, const double *in) {
+    BatchProblem bp;
+    bp.plan = sv->plan;
+    bp.alpha = in;
+    bp.out = sv->q.as<double>();
+    bp.nrhs = sv->nrhs;
+    bp.ld = sv->N;
+    bp.beta = sv->beta;
+    return bp;
+}
+
+static StepGraph &step_graph(anova_cg_s *const *solves, int count) {
+    std::vector<uint64_t> ids(count);
+    for (int i = 0; i < count; ++i) ids[i] = solves[i]->id;
+    for (size_t k = 0; k < g_steps.size(); ++k)
+        if (g_steps[k]->ids == ids) {
+            std::unique_ptr<StepGraph> hit = std::move(g_steps[k]);
+            g_steps.erase(g_steps.begin() + k);
+            g_steps.push_back(std::move(hit));  // most recently used last
+            return *g_steps.back();
+        }
+    std::unique_ptr<StepGraph> G(new StepGraph());
+    G->ids = ids;
+    G->solves.assign(solves, solves + count);
+    std::vector<BatchProblem> pq_probs, xq_probs;
+    for (int i = 0; i < count; ++i) {
+        anova_cg_s *sv = solves[i];
+        G->list.cols.insert(G->list.cols.end(), sv->own.cols.begin(), sv->own.cols.end());
+        pq_probs.push_back(product(sv, sv->p.as<double>()));
+        BatchProblem bx = product(sv, sv->x);
+        bx.ld = sv->ld;      // x columns follow the caller's leading dimension
+        bx.ld_out = sv->N;   // q is packed
+        xq_probs.push_back(bx);
+    }
+    G->list.upload_lists();
+    G->pq.build(pq_probs);
+    G->xq.build(xq_probs);
+    ANOVA_HIP_CHECK(hipStreamCreateWithFlags(&G->cap, hipStreamNonBlocking));
+    G->g_plain = capture(*G, false);
+    G->g_replace = capture(*G, true);
+    if (g_steps.size() >= kStepCache) g_steps.erase(g_steps.begin());
+    g_steps.push_back(std::move(G));
+    return *g_steps.back();
+}
+
+static void drop_step_graphs(uint64_t id) {
+    for (size_t k = 0; k < g_steps.size();) {
+        if (std::find(g_steps[k]->ids.begin(), g_steps[k]->ids.end(), id) != g_steps[k]->ids.end())
+            g_steps.erase(g_steps.begin() + k);
+        else
+            ++k;
+    }
+}
+
+template <typename F>
+static anova_status guarded_cg(F &&f) {
+    try {
+        return f();
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return ANOVA_E_NOMEM;
+    }
+}
+
+static void fill_info(const anova_cg_s *sv, const std::vector<CgScal> &hs,
+                      const std::vector<double> *true_rr, krr_cg_info *info) {
+    for (int c = 0; c < sv->nrhs; ++c) {
+        const CgScal &s = hs[c];
+        info[c].iters = s.iters;
+        info[c].converged = s.status == 1 ? 1 : 0;
+        info[c].relres = s.ynorm2 > 0 ? std::sqrt(s.rho / s.ynorm2) : 0.0;
+        info[c].true_relres =
+            true_rr ? (s.ynorm2 > 0 ? std::sqrt((*true_rr)[c] / s.ynorm2) : 0.0) : info[c].relres;
+    }
+}
+
+static std::vector<CgScal> read_scalars(const anova_cg_s *sv, hipStream_t s) {
+    std::vector<CgScal> hs(sv->nrhs);
+    ANOVA_HIP_CHECK(hipMemcpyAsync(hs.data(), sv->scal.ptr, sizeof(CgScal) * sv->nrhs,
+                                   hipMemcpyDeviceToHost, s));
+    ANOVA_HIP_CHECK(hipStreamSynchronize(s));
+    return hs;
+}
+
 }  // namespace anova
 
-using namespace anova;
-
-extern "C" anova_status krr_cg_solve(anova_plan_t plan, const double *y, double *alpha,
-                                     int32_t nrhs, int64_t ld, double beta, double tol,
-                                     int32_t maxit, krr_cg_info *info, void *stream) {
-    anova_status result = ANOVA_OK;
-    try {
+extern "C" anova_status krr_cg_start(anova_cg_t *out, anova_plan_t plan, const double *y,
+                                     double *alpha, int32_t nrhs, int64_t ld, double beta,
+                                     double tol, int32_t maxit, void *stream) {
+    if (!out) {
+        set_error("out is NULL");
+        return ANOVA_E_INVALID;
+    }
+    *out = nullptr;
+    return guarded_cg([&] {
         ANOVA_REQUIRE(plan != nullptr, "NULL plan");
         ANOVA_REQUIRE(y != nullptr && alpha != nullptr, "NULL vector");
         ANOVA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
@@ -300,89 +453,207 @@ extern "C" anova_status krr_cg_solve(anova_plan_t plan, const double *y, double 
         ANOVA_REQUIRE(std::isfinite(tol) && tol >= 0, "tol must be finite and >= 0");
         ANOVA_REQUIRE(maxit >= 1, "maxit must be >= 1");
         hipStream_t s = (hipStream_t)stream;
-        Solver S;
-        S.plan = plan;
-        S.nrhs = nrhs;
-        S.N = plan->N;
-        S.nblk = (int)std::min<int64_t>((S.N + 4 * kRedBlock - 1) / (4 * kRedBlock), 1024);
-        const size_t vec = (size_t)S.N * nrhs * sizeof(double);
-        S.r.alloc(vec);
-        S.p.alloc(vec);
-        S.q.alloc(vec);
-        S.partial.alloc((size_t)S.nblk * nrhs * sizeof(double));
-        S.scal.alloc(sizeof(CgScal) * nrhs);
-        ensure_grid(plan, 1);
-        ANOVA_HIP_CHECK(hipStreamCreateWithFlags(&S.cap, hipStreamNonBlocking));
-        const dim3 g2(S.nblk, nrhs);
-        hipLaunchKernelGGL(cg_init_kernel, g2, dim3(kRedBlock), 0, s, y, ld, alpha, ld,
-                           S.r.as<double>(), S.p.as<double>(), S.N, S.partial.as<double>(),
-                           S.nblk);
-        hipLaunchKernelGGL(cg_init_scal_kernel, dim3(nrhs), dim3(kRedBlock), 0, s,
-                           S.partial.as<double>(), S.nblk, S.scal.as<CgScal>(), tol);
-        ANOVA_HIP_CHECK(hipGetLastError());
-        S.g_plain = capture(S, alpha, ld, y, ld, beta, false);
-        S.g_replace = capture(S, alpha, ld, y, ld, beta, true);
-        std::vector<CgScal> hs(nrhs);
-        int it = 0;
-        ANOVA_HIP_CHECK(hipMemcpyAsync(hs.data(), S.scal.ptr, sizeof(CgScal) * nrhs,
-                                       hipMemcpyDeviceToHost, s));
-        ANOVA_HIP_CHECK(hipStreamSynchronize(s));
-        auto any_active = [&] {
-            for (auto &c : hs)
-                if (c.active) return true;
-            return false;
-        };
-        while (it < maxit && any_active()) {
-            const int k = std::min(kCheckEvery, maxit - it);
-            for (int j = 0; j < k; ++j) {
-                const bool rep = ((it + j + 1) % kResidualPeriod) == 0;
-                ANOVA_HIP_CHECK(hipGraphLaunch(rep ? S.g_replace : S.g_plain, s));
-            }
-            it += k;
-            ANOVA_HIP_CHECK(hipMemcpyAsync(hs.data(), S.scal.ptr, sizeof(CgScal) * nrhs,
-                                           hipMemcpyDeviceToHost, s));
-            ANOVA_HIP_CHECK(hipStreamSynchronize(s));
-        }
-        // true residual at exit: r = y - A x (all columns)
-        apply_A(S, alpha, ld, S.q.as<double>(), beta, s);
-        hipLaunchKernelGGL(cg_replace_kernel, g2, dim3(kRedBlock), 0, s, y, ld, S.r.as<double>(),
-                           S.q.as<double>(), S.N, S.scal.as<CgScal>(), S.partial.as<double>(),
-                           S.nblk, 1);
-        ANOVA_HIP_CHECK(hipGetLastError());
-        std::vector<double> part((size_t)S.nblk * nrhs);
-        ANOVA_HIP_CHECK(hipMemcpyAsync(part.data(), S.partial.ptr, part.size() * sizeof(double),
-                                       hipMemcpyDeviceToHost, s));
-        ANOVA_HIP_CHECK(hipMemcpyAsync(hs.data(), S.scal.ptr, sizeof(CgScal) * nrhs,
-                                       hipMemcpyDeviceToHost, s));
-        ANOVA_HIP_CHECK(hipStreamSynchronize(s));
-        bool all_conv = true, breakdown = false;
+        std::unique_ptr<anova_cg_s> sv(new anova_cg_s());
+        sv->plan = plan;
+        sv->id = g_next_solve_id++;
+        sv->nrhs = nrhs;
+        sv->N = plan->N;
+        sv->ld = ld;
+        sv->y = y;
+        sv->x = alpha;
+        sv->beta = beta;
+        sv->tol = tol;
+        sv->maxit = maxit;
+        const int nblk = (int)((sv->N + kSpan - 1) / kSpan);
+        const size_t vec = (size_t)sv->N * nrhs * sizeof(double);
+        sv->r.alloc(vec);
+        sv->p.alloc(vec);
+        sv->q.alloc(vec);
+        sv->partial.alloc((size_t)nblk * nrhs * sizeof(double));
+        sv->scal.alloc(sizeof(CgScal) * nrhs);
         for (int c = 0; c < nrhs; ++c) {
-            double tr = 0.0;
-            for (int b = 0; b < S.nblk; ++b) tr += part[(size_t)c * S.nblk + b];
-            const CgScal &sc = hs[c];
-            const bool conv = sc.status == 1;
-            all_conv = all_conv && conv;
-            breakdown = breakdown || sc.status == 2;
-            if (info) {
-                info[c].iters = sc.iters;
-                info[c].converged = conv ? 1 : 0;
-                info[c].relres = sc.ynorm2 > 0 ? std::sqrt(sc.rho / sc.ynorm2) : 0.0;
-                info[c].true_relres = sc.ynorm2 > 0 ? std::sqrt(tr / sc.ynorm2) : 0.0;
-            }
+            CgCol col{};
+            col.x = alpha + (size_t)c * ld;
+            col.r = sv->r.as<double>() + (size_t)c * sv->N;
+            col.p = sv->p.as<double>() + (size_t)c * sv->N;
+            col.q = sv->q.as<double>() + (size_t)c * sv->N;
+            col.y = y + (size_t)c * ld;
+            col.partial = sv->partial.as<double>() + (size_t)c * nblk;
+            col.sc = sv->scal.as<CgScal>() + c;
+            col.N = sv->N;
+            col.nblk = nblk;
+            sv->own.cols.push_back(col);
+        }
+        sv->own.upload_lists();
+        const CgCol *dc = sv->own.d_cols.as<CgCol>();
+        hipLaunchKernelGGL(cg_init_kernel, dim3(sv->own.blocks), dim3(kRedBlock), 0, s, dc,
+                           sv->own.d_prefix.as<int32_t>(), sv->own.cnt);
+        hipLaunchKernelGGL(cg_init_scal_kernel, dim3(sv->own.cnt), dim3(kRedBlock), 0, s, dc, tol,
+                           maxit);
+        ANOVA_HIP_CHECK(hipGetLastError());
+        *out = sv.release();
+        return ANOVA_OK;
+    });
+}
+
+extern "C" anova_status krr_cg_iterate(anova_cg_t *solves, int32_t count, int32_t iters,
+                                       void *stream) {
+    return guarded_cg([&] {
+        ANOVA_REQUIRE(solves != nullptr && count >= 1, "empty solve list");
+        ANOVA_REQUIRE(iters >= 0, "iters must be >= 0");
+        for (int i = 0; i < count; ++i) {
+            ANOVA_REQUIRE(solves[i] != nullptr, "NULL solve");
+            for (int j = 0; j < i; ++j) ANOVA_REQUIRE(solves[j] != solves[i], "repeated solve");
+            ANOVA_REQUIRE(solves[i]->plan->precision == solves[0]->plan->precision,
+                          "solves of one list must share the precision");
+        }
+        std::lock_guard<std::mutex> lock(g_step_mu);
+        StepGraph &G = step_graph(solves, count);
+        hipStream_t s = (hipStream_t)stream;
+        for (int k = 0; k < iters; ++k) {
+            bool rep = false;
+            for (int i = 0; i < count; ++i) rep = rep || (solves[i]->it + 1) % kResidualPeriod == 0;
+            ANOVA_HIP_CHECK(hipGraphLaunch(rep ? G.g_replace : G.g_plain, s));
+            for (int i = 0; i < count; ++i) ++solves[i]->it;
+        }
+        return ANOVA_OK;
+    });
+}
+
+extern "C" anova_status krr_cg_poll(anova_cg_t sv, int32_t *active, krr_cg_info *info,
+                                    void *stream) {
+    return guarded_cg([&] {
+        ANOVA_REQUIRE(sv != nullptr, "NULL solve");
+        const std::vector<CgScal> hs = read_scalars(sv, (hipStream_t)stream);
+        int a = 0;
+        for (auto &c : hs) a += c.active ? 1 : 0;
+        if (active) *active = a;
+        if (info) fill_info(sv, hs, nullptr, info);
+        return ANOVA_OK;
+    });
+}
+
+extern "C" anova_status krr_cg_finish(anova_cg_t sv, krr_cg_info *info, void *stream) {
+    return guarded_cg([&] {
+        ANOVA_REQUIRE(sv != nullptr, "NULL solve");
+        hipStream_t s = (hipStream_t)stream;
+        // true residual r = y - (K~ + beta I) x for every column
+        if (!sv->xq) {
+            sv->xq.reset(new Batch());
+            BatchProblem bp;
+            bp.plan = sv->plan;
+            bp.alpha = sv->x;
+            bp.out = sv->q.as<double>();
+            bp.nrhs = sv->nrhs;
+            bp.ld = sv->ld;
+            bp.ld_out = sv->N;
+            bp.beta = sv->beta;
+            sv->xq->build({bp});
+        }
+        sv->xq->run(s);
+        hipLaunchKernelGGL(cg_replace_kernel, dim3(sv->own.blocks), dim3(kRedBlock), 0, s,
+                           sv->own.d_cols.as<CgCol>(), sv->own.d_prefix.as<int32_t>(),
+                           sv->own.cnt, 1);
+        ANOVA_HIP_CHECK(hipGetLastError());
+        const int nblk = sv->own.cols.empty() ? 0 : sv->own.cols[0].nblk;
+        std::vector<double> part((size_t)nblk * sv->nrhs);
+        ANOVA_HIP_CHECK(hipMemcpyAsync(part.data(), sv->partial.ptr, part.size() * sizeof(double),
+                                       hipMemcpyDeviceToHost, s));
+        const std::vector<CgScal> hs = read_scalars(sv, s);
+        std::vector<double> trr(sv->nrhs, 0.0);
+        for (int c = 0; c < sv->nrhs; ++c)
+            for (int b = 0; b < nblk; ++b) trr[c] += part[(size_t)c * nblk + b];
+        if (info) fill_info(sv, hs, &trr, info);
+        bool all_conv = true, breakdown = false;
+        for (auto &c : hs) {
+            all_conv = all_conv && c.status == 1;
+            breakdown = breakdown || c.status == 2;
         }
         if (breakdown) {
             set_error("CG breakdown (p^T A p <= 0 or a non-finite value)");
-            result = ANOVA_E_BREAKDOWN;
-        } else if (!all_conv) {
-            set_error("CG reached maxit before the tolerance");
-            result = ANOVA_E_NOT_CONVERGED;
+            return ANOVA_E_BREAKDOWN;
         }
-    } catch (const Error &e) {
-        set_error(e.msg);
-        return e.st;
-    } catch (const std::bad_alloc &) {
-        set_error("host allocation failed");
-        return ANOVA_E_NOMEM;
+        if (!all_conv) {
+            set_error("CG reached maxit before the tolerance");
+            return ANOVA_E_NOT_CONVERGED;
+        }
+        return ANOVA_OK;
+    });
+}
+
+extern "C" anova_status krr_cg_destroy(anova_cg_t sv) {
+    if (!sv) return ANOVA_OK;
+    return guarded_cg([&] {
+        {
+            std::lock_guard<std::mutex> lock(g_step_mu);
+            drop_step_graphs(sv->id);
+        }
+        (void)hipDeviceSynchronize();
+        delete sv;
+        return ANOVA_OK;
+    });
+}
+
+static anova_status solve_lists(int32_t count, anova_cg_t *svs, int32_t check_every,
+                                void *stream) {
+    // iterate until no column is active, reading the flags every few steps
+    std::vector<anova_cg_t> live(svs, svs + count);
+    while (!live.empty()) {
+        anova_status st = krr_cg_iterate(live.data(), (int32_t)live.size(), check_every, stream);
+        if (st != ANOVA_OK) return st;
+        std::vector<anova_cg_t> still;
+        for (anova_cg_t sv : live) {
+            int32_t a = 0;
+            st = krr_cg_poll(sv, &a, nullptr, stream);
+            if (st != ANOVA_OK) return st;
+            if (a > 0) still.push_back(sv);
+        }
+        live.swap(still);
     }
-    return result;
+    return ANOVA_OK;
+}
+
+extern "C" anova_status krr_cg_solve(anova_plan_t plan, const double *y, double *alpha,
+                                     int32_t nrhs, int64_t ld, double beta, double tol,
+                                     int32_t maxit, krr_cg_info *info, void *stream) {
+    anova_cg_t sv = nullptr;
+    anova_status st = krr_cg_start(&sv, plan, y, alpha, nrhs, ld, beta, tol, maxit, stream);
+    if (st != ANOVA_OK) return st;
+    st = solve_lists(1, &sv, 8, stream);
+    if (st == ANOVA_OK) st = krr_cg_finish(sv, info, stream);
+    const std::string msg = st != ANOVA_OK ? anova_last_error() : "";
+    krr_cg_destroy(sv);
+    if (st != ANOVA_OK) set_error(msg);
+    return st;
+}
+
+extern "C" anova_status krr_cg_solve_batched(int32_t count, const anova_plan_t *plans,
+                                             const double *const *y, double *const *alpha,
+                                             const int32_t *nrhs, const int64_t *ld,
+                                             const double *beta, double tol, int32_t maxit,
+                                             krr_cg_info *info, void *stream) {
+    if (count < 1 || !plans || !y || !alpha || !nrhs || !ld || !beta) {
+        set_error("invalid batched solve arguments");
+        return ANOVA_E_INVALID;
+    }
+    std::vector<anova_cg_t> svs(count, nullptr);
+    anova_status st = ANOVA_OK;
+    for (int i = 0; i < count && st == ANOVA_OK; ++i)
+        st = krr_cg_start(&svs[i], plans[i], y[i], alpha[i], nrhs[i], ld[i], beta[i], tol, maxit,
+                          stream);
+    if (st == ANOVA_OK) st = solve_lists(count, svs.data(), 8, stream);
+    anova_status worst = st;
+    std::string msg = st != ANOVA_OK ? anova_last_error() : "";
+    int64_t off = 0;
+    for (int i = 0; i < count && st == ANOVA_OK; ++i) {
+        const anova_status fi = krr_cg_finish(svs[i], info ? info + off : nullptr, stream);
+        off += nrhs[i];
+        if (fi != ANOVA_OK && (worst == ANOVA_OK || worst == ANOVA_E_NOT_CONVERGED)) {
+            worst = fi;
+            msg = anova_last_error();
+        }
+    }
+    for (anova_cg_t sv : svs) krr_cg_destroy(sv);
+    if (worst != ANOVA_OK) set_error(msg);
+    return worst;
 }

@@ -281,13 +281,6 @@ Choice choose(const anova_params &prm, double D, int dA, double budget, int64_t 
     return c;
 }
 
-template <typename T>
-void upload(DevBuf &buf, const std::vector<T> &v) {
-    size_t bytes = v.size() * sizeof(T);
-    bytes = (bytes + 255) & ~(size_t)255;
-    buf.alloc(bytes);
-    if (!v.empty()) ANOVA_HIP_CHECK(hipMemcpy(buf.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-}
 
 // For every tile of the n^dA grid (tile edge `tile`, tpd = n/tile per
 // dimension), the source regions (one per non-empty tile, src_tiles[k] its
@@ -562,36 +555,6 @@ void validate(const double *X, int64_t N, int32_t d, int64_t ldx, const anova_wi
 
 }  // namespace
 
-void ensure_grid(anova_plan_s *p, int slots) {
-    size_t maxg = 0, maxp = 0;
-    for (auto &w : p->win) {
-        maxg = std::max(maxg, w.grid_elems());
-        maxp = std::max(maxp, (size_t)w.n_regions * w.region_elems());
-    }
-    const size_t es = p->precision == ANOVA_FP64 ? 8 : 4;
-    if (!p->priv.ptr || p->priv.bytes < maxp * es) p->priv.alloc(maxp * es);
-    size_t maxt = 0;
-    for (auto &w : p->win)
-        if (w.n_regions != w.n_nonempty)
-            maxt = std::max(maxt, (size_t)w.n_nonempty * w.region_elems());
-    if (maxt && (!p->treg.ptr || p->treg.bytes < maxt * es)) p->treg.alloc(maxt * es);
-    if (!p->asort.ptr || p->asort.bytes < (size_t)p->N * es) p->asort.alloc((size_t)p->N * es);
-    const size_t tmp_bytes = (size_t)p->P * (size_t)p->N * es;
-    if (!p->tmp.ptr || p->tmp.bytes < tmp_bytes) {
-        p->tmp.alloc(tmp_bytes);
-        std::vector<CombineWin> cw(p->P);
-        for (int l = 0; l < p->P; ++l)
-            cw[l] = CombineWin{(const char *)p->tmp.ptr + (size_t)l * p->N * es,
-                               p->win[l].iperm.as<int32_t>(), p->win[l].eta};
-        upload(p->combine, cw);
-    }
-    size_t slot = ((maxg * es + 255) / 256) * 256 / es;
-    if (p->grid.ptr && p->grid_slot_elems >= slot && p->grid_slots >= slots) return;
-    p->grid.alloc(slot * es * slots);
-    p->grid_slot_elems = slot;
-    p->grid_slots = slots;
-}
-
 hipEvent_t pool_event(anova_plan_s *p) {
     if (!p->event_pool.empty()) {
         hipEvent_t e = p->event_pool.back();
@@ -603,24 +566,22 @@ hipEvent_t pool_event(anova_plan_s *p) {
     return e;
 }
 
-void plan_matvec(anova_plan_s *p, const double *alpha, double *out, double beta, hipStream_t s) {
-    ensure_grid(p, 1);
-    for (int l = 0; l < p->P; ++l) {
-        const WindowPlan &w = p->win[l];
-        void *g = p->grid.ptr;
-        void *pv = p->priv.ptr;
-        void *as = p->asort.ptr;
-        timed_launch(p, kStageSpread, s,
-                     [&] { launch_spread_regions(w, p->precision, alpha, as, pv, s); });
-        void *tr = p->treg.ptr;
-        timed_launch(p, kStageFold, s, [&] { launch_fold(w, p->precision, pv, tr, g, s); });
-        timed_launch(p, kStageConvolve, s, [&] { launch_convolve(w, p->precision, g, s); });
-        void *tl = (char *)p->tmp.ptr + (size_t)l * p->N * (p->precision == ANOVA_FP64 ? 8 : 4);
-        timed_launch(p, kStageGather, s, [&] { launch_gather(w, p->precision, g, tl, s); });
-    }
-    timed_launch(p, kStageCombine, s, [&] {
-        launch_combine(p->combine.ptr, p->P, p->precision, alpha, out, beta, p->N, false, s);
-    });
+// out = (K~ + beta I) alpha for nrhs columns: one batched launch per stage
+// over all windows and columns; the launch tables are rebuilt only when the
+// vectors, their layout or the shift change.
+void plan_matvec(anova_plan_s *p, const double *alpha, double *out, int nrhs, int64_t ld,
+                 double beta, hipStream_t s) {
+    BatchProblem bp;
+    bp.plan = p;
+    bp.alpha = alpha;
+    bp.out = out;
+    bp.nrhs = nrhs;
+    bp.ld = ld;
+    bp.beta = beta;
+    const std::vector<BatchProblem> probs{bp};
+    if (!p->mv_batch) p->mv_batch.reset(new Batch());
+    if (!p->mv_batch->same(probs)) p->mv_batch->build(probs);
+    p->mv_batch->run(s, p);
 }
 
 }  // namespace anova
@@ -712,7 +673,6 @@ extern "C" anova_status anova_fastsum_plan(anova_plan_t *out, const double *X, i
                 throw Error{ANOVA_E_ACCURACY, "estimated per-entry error " + std::to_string(tot) +
                                                   " exceeds target_err"};
         }
-        ensure_grid(p, 1);
         ANOVA_HIP_CHECK(hipDeviceSynchronize());
     });
     if (st != ANOVA_OK) {
@@ -798,10 +758,25 @@ extern "C" anova_status anova_matvec(anova_plan_t p, const double *alpha, double
         ANOVA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
         ANOVA_REQUIRE(ld >= p->N, "ld must be >= N");
         ANOVA_REQUIRE(std::isfinite(beta), "beta must be finite");
-        hipStream_t s = (hipStream_t)stream;
-        for (int c = 0; c < nrhs; ++c)
-            plan_matvec(p, alpha + (size_t)c * ld, out + (size_t)c * ld, beta, s);
+        plan_matvec(p, alpha, out, nrhs, ld, beta, (hipStream_t)stream);
     });
+}
+
+// one-window batches over the caller's grid (stage entry points)
+static void stage_run(anova_plan_s *p, int32_t l, const double *alpha, double *out, void *grid,
+                      unsigned mask, hipStream_t s) {
+    BatchProblem bp;
+    bp.plan = p;
+    bp.alpha = alpha;
+    bp.out = out;
+    bp.nrhs = 1;
+    bp.ld = p->N;
+    bp.only_window = l;
+    bp.grid_override = grid;
+    Batch b;
+    b.build({bp});
+    b.run(s, nullptr, mask);
+    ANOVA_HIP_CHECK(hipStreamSynchronize(s));  // the batch's work space dies here
 }
 
 extern "C" anova_status anova_stage_spread(anova_plan_t p, int32_t l, const double *alpha,
@@ -809,9 +784,9 @@ extern "C" anova_status anova_stage_spread(anova_plan_t p, int32_t l, const doub
     return guarded([&] {
         ANOVA_REQUIRE(p != nullptr && alpha != nullptr && grid != nullptr, "NULL argument");
         ANOVA_REQUIRE(l >= 0 && l < p->P, "window index out of range");
-        ensure_grid(p, 1);
-        launch_spread(p->win[l], p->precision, alpha, grid, p->asort.ptr, p->priv.ptr,
-                      p->treg.ptr, (hipStream_t)stream);
+        stage_run(p, l, alpha, nullptr, grid, (1u << kStagePermute) | (1u << kStageSpread) |
+                      (1u << kStageTileSum) | (1u << kStageFold),
+                  (hipStream_t)stream);
     });
 }
 
@@ -819,7 +794,9 @@ extern "C" anova_status anova_stage_convolve(anova_plan_t p, int32_t l, void *gr
     return guarded([&] {
         ANOVA_REQUIRE(p != nullptr && grid != nullptr, "NULL argument");
         ANOVA_REQUIRE(l >= 0 && l < p->P, "window index out of range");
-        launch_convolve(p->win[l], p->precision, grid, (hipStream_t)stream);
+        // the coefficient column is not read by the convolution
+        stage_run(p, l, static_cast<const double *>(grid), nullptr, grid, 1u << kStageConvolve,
+                  (hipStream_t)stream);
     });
 }
 
@@ -828,11 +805,7 @@ extern "C" anova_status anova_stage_gather(anova_plan_t p, int32_t l, const void
     return guarded([&] {
         ANOVA_REQUIRE(p != nullptr && grid != nullptr && out != nullptr, "NULL argument");
         ANOVA_REQUIRE(l >= 0 && l < p->P, "window index out of range");
-        ensure_grid(p, 1);
-        const size_t es = p->precision == ANOVA_FP64 ? 8 : 4;
-        void *tl = (char *)p->tmp.ptr + (size_t)l * p->N * es;
-        launch_gather(p->win[l], p->precision, grid, tl, (hipStream_t)stream);
-        launch_combine((const CombineWin *)p->combine.ptr + l, 1, p->precision, nullptr, out, 0.0,
-                       p->N, true, (hipStream_t)stream);
+        stage_run(p, l, out, out, const_cast<void *>(grid),
+                  (1u << kStageGather) | (1u << kStageCombine), (hipStream_t)stream);
     });
 }
