@@ -41,6 +41,14 @@ def parse():
                     help="approximate oracle CPU time for the baseline sample")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--skip-fixed", action="store_true")
+    ap.add_argument("--skip-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests of the serving stream (first 10%% are warm-up)")
+    ap.add_argument("--serve-load", type=float, default=0.75,
+                    help="Poisson arrival rate as a fraction of the measured capacity")
+    ap.add_argument("--serve-n-hi", type=int, default=500_000)
+    ap.add_argument("--serve-budget-gb", type=float, default=32.0,
+                    help="device memory the live requests may hold together")
     return ap.parse_args()
 
 
@@ -94,6 +102,66 @@ def stage_profile(A, torch, plan, a, out, beta, steps):
     t = plan.stage_times()
     plan.set_timing(False)
     return t
+
+
+def serve_stream(Server, ex, reqs, arrivals, budget, max_live):
+    """Feed requests to a server at the given arrival offsets (seconds) in
+    real time; returns the server once every request is done."""
+    srv = Server(ex, budget=budget, max_live=max_live, iters_per_round=4)
+    order = sorted(range(len(reqs)), key=lambda k: arrivals[k])
+    t0 = time.perf_counter()
+    k = 0
+    while k < len(order) or srv.busy():
+        now = time.perf_counter() - t0
+        while k < len(order) and arrivals[order[k]] <= now:
+            p = reqs[order[k]].problem
+            srv.submit(p.X, p.windows, p.ell, p.beta, p.y, tol=1e-6, maxit=2000,
+                       arrival=t0 + arrivals[order[k]])
+            k += 1
+        if srv.busy():
+            srv.step()
+        elif k < len(order):
+            time.sleep(max(0.0, arrivals[order[k]] - (time.perf_counter() - t0)))
+    return srv
+
+
+def serving(args, A):
+    """Served KRR solves: closed-loop capacity (every request queued at t=0),
+    the same with one request at a time, then Poisson arrivals at
+    serve_load x capacity; latency = result time - arrival."""
+    import workloads
+    from paper_2111_10140_amd.serve import HipExecutor, Server
+    R = args.serve_requests
+    reqs = workloads.serving_stream(R, rate=1.0, n_hi=args.serve_n_hi)  # unit-rate arrivals
+    ex = HipExecutor(A.ANOVA_FP32_NFFT, target_err=1e-4)
+    budget = int(args.serve_budget_gb * (1 << 30))
+    closed = serve_stream(Server, ex, reqs, [0.0] * R, budget, 64)
+    cap = closed.stats(0.0)["solves_per_s"]
+    print(f"# serving: capacity {cap:.2f} solves/s (closed loop, {R} requests)", file=sys.stderr,
+          flush=True)
+    seq = serve_stream(Server, ex, reqs, [0.0] * R, budget, 1)
+    seq_rate = seq.stats(0.0)["solves_per_s"]
+    rate = args.serve_load * cap
+    srv = serve_stream(Server, ex, reqs, [r.arrival / rate for r in reqs], budget, 64)
+    st = srv.stats(0.1)
+    statuses = {}
+    for r in srv.results.values():
+        statuses[r.status] = statuses.get(r.status, 0) + 1
+    iters = [max(i["iters"] for i in r.info) for r in srv.results.values() if r.info]
+    return {
+        "workload": f"Poisson stream of {R} KRR solves: N uniform in [1000, {args.serve_n_hi}], "
+                    "d in {6,9,12} (consecutive triples), ell uniform in [0.1, 0.4], beta=1, "
+                    "1-8 RHS, fp32 NFFT + fp64 CG, tol 1e-6, plan for err<=1e-4",
+        "requests": R, "load": args.serve_load, "rate_per_s": round(rate, 3),
+        "capacity_solves_per_s": round(cap, 3),
+        "one_at_a_time_solves_per_s": round(seq_rate, 3),
+        "p50_ms": round(st["p50_s"] * 1e3, 2), "p99_ms": round(st["p99_s"] * 1e3, 2),
+        "mean_ms": round(st["mean_s"] * 1e3, 2), "solves_per_s": round(st["solves_per_s"], 3),
+        "latency_from": "arrival (queueing, planning, CG, result copy); first 10% excluded",
+        "peak_live": st["peak_live"], "budget_gb": args.serve_budget_gb,
+        "peak_reserved_gb": round(st["peak_reserved_bytes"] / 2**30, 3),
+        "statuses": statuses, "cg_iters_median": int(np.median(iters)) if iters else None,
+    }
 
 
 def main():
@@ -182,6 +250,8 @@ def main():
     else:
         err = None
 
+    served = None if args.skip_serve else serving(args, A)
+
     res = {
         "metric": "ANOVA matvecs/s N=1M,3 windows d_A=3 (err<=1e-4)",
         "value": round(1e3 / ms, 2), "unit": "matvecs/s", "n_gpus": 1, "steps": args.steps,
@@ -197,6 +267,7 @@ def main():
         "stages_per_launch": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
                                   for kk, vv in v.items()} for k, v in per_launch.items()},
         "fixed_params": fixed,
+        "serving": served,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res))

@@ -85,8 +85,22 @@ typedef struct {
     double target_err;   /* 0 -> 1e-4 (FP32_NFFT) or 1e-9 (FP64) */
     int32_t center;      /* 0: centre each window's bounding box before
                             scaling by 1/h; 1: scale only, x~ = x/h (Sec. 4.2) */
-    int32_t reserved;    /* must be 0 */
+    int32_t residual;    /* anova_residual: how CG recomputes its residual
+                            on a FP32_NFFT plan (ignored for FP64 plans) */
 } anova_params;
+
+/* Residual product of CG on FP32_NFFT plans.  The float32 product's rounding
+ * error grows with ||K|| (about N times the mean kernel value), so for large
+ * N it exceeds tol * beta and CG's recursive residual stagnates or drifts
+ * away from the true one.  With ANOVA_RESIDUAL_FP64 the plan also holds the
+ * same windows in float64 (same M, n, m, h; about twice the plan memory and
+ * planning time), every periodic residual recomputation y - (K~ + beta I) x
+ * uses the float64 product, and a column counts as converged only on such a
+ * recomputed residual. */
+typedef enum {
+    ANOVA_RESIDUAL_FP64 = 0,  /* default */
+    ANOVA_RESIDUAL_SAME = 1   /* residuals with the plan's own float32 product */
+} anova_residual;
 
 /* What a plan chose for window l (host struct filled by anova_plan_query). */
 typedef struct {
@@ -126,7 +140,7 @@ typedef struct {
  * Errors: ANOVA_E_INVALID for out == NULL, X == NULL, N < 1, N > 2^31-1,
  * d < 1, ldx < d, P < 1, P > 64, d_A not in {1,2,3}, a feature index out of
  * range or repeated inside one window, a non-finite eta or X, ell <= 0,
- * odd M, n not a power of two or n < M, m out of range, reserved != 0.
+ * odd M, n not a power of two or n < M, m out of range, residual not an anova_residual.
  * ANOVA_E_ACCURACY when fixed parameters miss target_err.
  */
 anova_status anova_fastsum_plan(anova_plan_t *out, const double *X, int64_t N, int32_t d,
@@ -146,10 +160,15 @@ anova_status anova_matvec(anova_plan_t plan, const double *alpha, double *out, i
 
 /*
  * Solve (K~ + beta I) alpha = y by conjugate gradients (Sec. 2), one
- * independent recurrence per column, no preconditioner.  x0 = 0; a column
- * stops when ||r||_2 <= tol ||y||_2; every 50 iterations, and at exit, the
- * residual is recomputed as y - (K~ + beta I) alpha (residual replacement).
- * Dot products, vector updates and the residual recomputation are float64.
+ * independent recurrence per column, no preconditioner.  x0 = 0; dot
+ * products, vector updates and residual recomputations are float64.  Every
+ * R iterations of a column its residual is recomputed as y - (K~ + beta I) x
+ * (residual replacement): R = 50 on FP64 plans; R = 25 on FP32_NFFT plans,
+ * where the recomputation uses the float64 product (ANOVA_RESIDUAL_FP64,
+ * the default) and a column stops only when such a recomputed residual
+ * satisfies ||r||_2 <= tol ||y||_2 (on FP64 plans, and with
+ * ANOVA_RESIDUAL_SAME, any iteration's residual may stop it).  At exit the
+ * true residual is recomputed the same way.
  * y, alpha: device, column-major N x nrhs, leading dimension ld.
  * info: host array of nrhs entries (may be NULL).  Synchronises `stream`.
  * Returns ANOVA_E_NOT_CONVERGED if some column reached maxit (alpha then
@@ -170,10 +189,11 @@ anova_status krr_cg_solve(anova_plan_t plan, const double *y, double *alpha, int
  * kernel signature, plus five float64 vector kernels over all columns of
  * all solves; it is captured once per solve list into a hipGraph and
  * replayed (lists of up to 4 recently used combinations are cached).  At
- * each column's iterations 50, 100, ... its residual is recomputed as
- * y - A x, so a column iterates the same way alone and in any list.  The solves
- * of one list must share the precision; a solve may appear in several lists
- * over time (continuous batching).  Asynchronous on `stream`.
+ * each column's iterations R, 2R, ... (as in krr_cg_solve) its residual is
+ * recomputed as y - A x, so a column iterates the same way alone and in any
+ * list.  The solves of one list must share the precision and the residual
+ * mode; a solve may appear in several lists over time (continuous
+ * batching).  Asynchronous on `stream`.
  * krr_cg_poll reads the number of still-iterating columns and the current
  * per-column info (synchronises).  krr_cg_finish recomputes the true residual
  * of every column and returns ANOVA_OK, ANOVA_E_NOT_CONVERGED or
@@ -210,6 +230,21 @@ const char *anova_last_error(void);
 
 /* Parameters and error estimates chosen for window l (0 <= l < P).  Host. */
 anova_status anova_plan_query(anova_plan_t plan, int32_t l, anova_window_info *info);
+
+/*
+ * Device memory, for admission by memory footprint (the solver's memory of
+ * Sec. 2's CG around the Sec. 3 products).  plan_bytes: bytes the plan holds
+ * now (its sorted nodes, permutations, tile lists, window polynomials,
+ * multipliers, and the work space of anova_matvec once it has run).
+ * solve_bytes: bytes that krr_cg_start with nrhs columns on this plan
+ * allocates (three float64 N x nrhs vectors, reduction partials, scalars and
+ * the product work space of its (window, column) instances); iterate and
+ * finish add only launch tables of under 1 KB per window and column.
+ * The caller's y and alpha are not counted.  Host outputs (may be NULL).
+ * Errors: ANOVA_E_INVALID for a NULL plan or nrhs < 1.
+ */
+anova_status anova_plan_footprint(anova_plan_t plan, int32_t nrhs, int64_t *plan_bytes,
+                                  int64_t *solve_bytes);
 
 /* Number of points and windows of a plan (host outputs, may be NULL). */
 anova_status anova_plan_shape(anova_plan_t plan, int64_t *N, int32_t *P, int32_t *precision);

@@ -28,6 +28,9 @@ STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NOMEM", 3: "E_HIP", 4: "E_NOT_CON
 ANOVA_FP64 = 0
 ANOVA_FP32_NFFT = 1
 
+ANOVA_RESIDUAL_FP64 = 0
+ANOVA_RESIDUAL_SAME = 1
+
 
 class anova_window(ctypes.Structure):
     _fields_ = [("d_A", ctypes.c_int32), ("feat", ctypes.c_int32 * 3), ("eta", ctypes.c_double)]
@@ -37,7 +40,7 @@ class anova_params(ctypes.Structure):
     _fields_ = [("ell", ctypes.c_double), ("precision", ctypes.c_int32), ("M", ctypes.c_int32),
                 ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("h", ctypes.c_double),
                 ("target_err", ctypes.c_double), ("center", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("residual", ctypes.c_int32)]
 
 
 class anova_window_info(ctypes.Structure):
@@ -96,6 +99,7 @@ def load():
                                  ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(dbl),
                                  dbl, i32, ctypes.POINTER(krr_cg_info), VP],
         "anova_plan_stage_times": [VP, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
+        "anova_plan_footprint": [VP, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -157,10 +161,11 @@ def make_windows(windows) -> "ctypes.Array":
 
 
 def make_params(ell: float, precision: int = ANOVA_FP32_NFFT, M: int = 0, m: int = 0, n: int = 0,
-                h: float = 0.0, target_err: float = 0.0, center: int = 0) -> anova_params:
+                h: float = 0.0, target_err: float = 0.0, center: int = 0,
+                residual: int = 0) -> anova_params:
     p = anova_params()
     p.ell, p.precision, p.M, p.m, p.n = float(ell), int(precision), int(M), int(m), int(n)
-    p.h, p.target_err, p.center, p.reserved = float(h), float(target_err), int(center), 0
+    p.h, p.target_err, p.center, p.residual = float(h), float(target_err), int(center), int(residual)
     return p
 
 
@@ -221,6 +226,13 @@ class Plan:
         cnt = (ctypes.c_int64 * len(STAGE_KINDS))()
         _check(load().anova_plan_stage_times(self.handle, ms, cnt))
         return {k: (ms[i], cnt[i]) for i, k in enumerate(STAGE_KINDS)}
+
+    def footprint(self, nrhs: int = 1):
+        """(plan_bytes, solve_bytes): device bytes the plan holds and that a
+        CG solve with nrhs columns allocates."""
+        pb, sb = ctypes.c_int64(), ctypes.c_int64()
+        _check(load().anova_plan_footprint(self.handle, nrhs, ctypes.byref(pb), ctypes.byref(sb)))
+        return pb.value, sb.value
 
     def err_estimate(self) -> float:
         return sum(self.info(l).err_total for l in range(self.P))

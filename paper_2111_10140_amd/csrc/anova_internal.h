@@ -156,6 +156,9 @@ struct anova_plan_s {
     int32_t precision = 0;
     double ell = 0;
     std::vector<anova::WindowPlan> win;
+    // float32 plans with float64 residuals: the same windows in float64
+    // (empty otherwise)
+    std::vector<anova::WindowPlan> win64;
     int device = 0;
     // batched launches of this plan's own products (anova_matvec), reused
     // while the vectors and the shift stay the same
@@ -236,7 +239,25 @@ struct BatchProblem {
     double beta = 0.0;
     int only_window = -1;           // >= 0: stage entry points (one window)
     void *grid_override = nullptr;  // stage entry points: the caller's grid
+    void *work = nullptr;           // problem_work_bytes() of work space owned by
+                                    // the caller (nullptr: the batch allocates)
+    bool residual = false;          // use the plan's float64 residual windows
+                                    // when it has them
 };
+
+// Windows and arithmetic precision a batch problem runs with.
+inline const std::vector<WindowPlan> &problem_windows(const BatchProblem &bp) {
+    return bp.residual && !bp.plan->win64.empty() ? bp.plan->win64 : bp.plan->win;
+}
+inline int problem_precision(const BatchProblem &bp) {
+    return bp.residual && !bp.plan->win64.empty() ? ANOVA_FP64 : bp.plan->precision;
+}
+
+// Work space (grids, spread regions, sorted values) of one problem's
+// instances in a batch.
+size_t problem_work_bytes(const BatchProblem &bp);
+// Device bytes held by a plan's own buffers.
+size_t plan_device_bytes(const anova_plan_s *p);
 
 // A set of products run with one launch per stage and kernel signature.
 class Batch {
@@ -254,7 +275,9 @@ class Batch {
     // (re)build for the given problems; workspace is reused when it fits
     void build(const std::vector<BatchProblem> &problems);
     bool same(const std::vector<BatchProblem> &problems) const;
-    // stage mask: bit k = stage kind k (combine = 4)
+    // device bytes of the tables and of the batch-owned work space
+    size_t device_bytes() const;
+    // stage mask: bit k = stage kind k
     void run(hipStream_t s, anova_plan_s *timing = nullptr, unsigned mask = 0xffu) const;
 };
 

@@ -35,6 +35,23 @@ Sizes instance_sizes(const WindowPlan &w, size_t es, bool own_grid) {
 
 }  // namespace
 
+size_t problem_work_bytes(const BatchProblem &bp) {
+    const size_t es = problem_precision(bp) == ANOVA_FP64 ? 8 : 4;
+    const std::vector<WindowPlan> &wins = problem_windows(bp);
+    size_t total = 0;
+    for (int c = 0; c < bp.nrhs; ++c)
+        for (int l = 0; l < bp.plan->P; ++l) {
+            if (bp.only_window >= 0 && l != bp.only_window) continue;
+            const Sizes z = instance_sizes(wins[l], es, bp.grid_override == nullptr);
+            total += z.grid + z.priv + z.treg + z.tmp;
+        }
+    return total;
+}
+
+size_t Batch::device_bytes() const {
+    return d_insts.bytes + d_combs.bytes + d_cwins.bytes + d_tables.bytes + work.bytes;
+}
+
 bool Batch::same(const std::vector<BatchProblem> &problems) const {
     if (problems.size() != probs.size()) return false;
     for (size_t i = 0; i < problems.size(); ++i) {
@@ -42,7 +59,8 @@ bool Batch::same(const std::vector<BatchProblem> &problems) const {
         if (a.plan != b.plan || a.alpha != b.alpha || a.out != b.out || a.nrhs != b.nrhs ||
             a.ld != b.ld || a.ld_out != b.ld_out || a.beta != b.beta ||
             a.only_window != b.only_window ||
-            a.grid_override != b.grid_override)
+            a.grid_override != b.grid_override || a.work != b.work ||
+            a.residual != b.residual)
             return false;
     }
     return true;
@@ -50,9 +68,10 @@ bool Batch::same(const std::vector<BatchProblem> &problems) const {
 
 void Batch::build(const std::vector<BatchProblem> &problems) {
     ANOVA_REQUIRE(!problems.empty(), "empty batch");
-    precision = problems[0].plan->precision;
+    precision = problem_precision(problems[0]);
     for (const BatchProblem &bp : problems)
-        ANOVA_REQUIRE(bp.plan->precision == precision, "a batch mixes float32 and float64 plans");
+        ANOVA_REQUIRE(problem_precision(bp) == precision,
+                      "a batch mixes float32 and float64 products");
     const size_t es = precision == ANOVA_FP64 ? 8 : 4;
     insts.clear();
     combs.clear();
@@ -63,9 +82,12 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
         size_t grid, priv, treg, tmp;
     };
     std::vector<Slot> slots;
+    std::vector<char *> slot_base;  // nullptr: the batch's own work space
     size_t total = 0;
     for (const BatchProblem &bp : problems) {
         anova_plan_s *p = bp.plan;
+        size_t own = 0;  // offsets inside the caller's work space
+        size_t &off = bp.work ? own : total;
         for (int c = 0; c < bp.nrhs; ++c) {
             CombInst ci{};
             const int64_t ldo = bp.ld_out >= 0 ? bp.ld_out : bp.ld;
@@ -78,12 +100,12 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
             int nw = 0;
             for (int l = 0; l < p->P; ++l) {
                 if (bp.only_window >= 0 && l != bp.only_window) continue;
-                const WindowPlan &w = p->win[l];
+                const WindowPlan &w = problem_windows(bp)[l];
                 const Sizes z = instance_sizes(w, es, bp.grid_override == nullptr);
-                Slot sl{total, total + z.grid, total + z.grid + z.priv,
-                        total + z.grid + z.priv + z.treg};
-                total += z.grid + z.priv + z.treg + z.tmp;
+                Slot sl{off, off + z.grid, off + z.grid + z.priv, off + z.grid + z.priv + z.treg};
+                off += z.grid + z.priv + z.treg + z.tmp;
                 slots.push_back(sl);
+                slot_base.push_back(static_cast<char *>(bp.work));
                 WinInst wi{};
                 wi.nodes = w.nodes.ptr;
                 wi.perm = w.perm.as<int32_t>();
@@ -118,9 +140,12 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
             combs.push_back(ci);
         }
     }
-    if (!work.ptr || work.bytes < total) work.alloc(total);
-    char *base = static_cast<char *>(work.ptr);
+    if (total == 0)
+        work.release();
+    else if (!work.ptr || work.bytes < total)
+        work.alloc(total);
     for (size_t i = 0; i < insts.size(); ++i) {
+        char *base = slot_base[i] ? slot_base[i] : static_cast<char *>(work.ptr);
         if (!insts[i].grid) insts[i].grid = base + slots[i].grid;
         insts[i].priv = base + slots[i].priv;
         insts[i].treg = base + slots[i].treg;

@@ -12,9 +12,12 @@
 // results do not depend on scheduling), and the CG scalars stay in device
 // memory, so an iteration needs no host round trip.  The iteration is
 // captured once per solve list into a hipGraph and replayed.  At every
-// kResidualPeriod-th iteration of a column its recursive residual is
-// replaced by y - A x (residual replacement); at the end the true residual
-// is recomputed.
+// period-th iteration of a column its recursive residual is replaced by
+// y - A x (residual replacement); at the end the true residual is
+// recomputed.  On float32 plans the replacement product is the float64 one
+// (the plan's residual windows): the float32 product's rounding error grows
+// with ||K|| and would otherwise stall the residual above tol for large N,
+// so such a column stops only on a recomputed float64 residual.
 #include <algorithm>
 #include <atomic>
 #include <cmath>
@@ -27,7 +30,8 @@ namespace anova {
 
 constexpr int kRedBlock = 256;
 constexpr int kSpan = 4 * kRedBlock;  // elements per block and column
-constexpr int kResidualPeriod = 50;
+constexpr int kResidualPeriod = 50;        // replacement with the plan's own product
+constexpr int kResidualPeriodExact = 25;   // float64 residuals of float32 plans
 
 struct CgScal {
     double rho;      // r.r of the current residual
@@ -39,6 +43,8 @@ struct CgScal {
     int32_t status;  // 0 running, 1 converged, 2 breakdown, 3 maxit reached
     int32_t iters;
     int32_t maxit;
+    int32_t period;      // residual recomputed at iterations period, 2 period, ...
+    int32_t exact_only;  // 1: stop only on a recomputed (float64) residual
 };
 
 // One column of one solve, as seen by the vector kernels.
@@ -118,7 +124,8 @@ __global__ __launch_bounds__(kRedBlock) void cg_init_kernel(const CgCol *__restr
 }
 
 __global__ __launch_bounds__(kRedBlock) void cg_init_scal_kernel(const CgCol *__restrict__ cols,
-                                                                 double tol, int maxit) {
+                                                                 double tol, int maxit,
+                                                                 int period, int exact_only) {
     __shared__ double sh[kRedBlock / 64];
     const CgCol col = cols[blockIdx.x];
     const double y2 = sum_partials(col.partial, col.nblk, sh);
@@ -131,6 +138,8 @@ __global__ __launch_bounds__(kRedBlock) void cg_init_scal_kernel(const CgCol *__
         s.status = y2 > 0.0 ? (isfinite(y2) ? 0 : 2) : 1;
         s.iters = 0;
         s.maxit = maxit;
+        s.period = period;
+        s.exact_only = exact_only;
         *col.sc = s;
     }
 }
@@ -156,7 +165,9 @@ __global__ __launch_bounds__(kRedBlock) void cg_alpha_kernel(const CgCol *__rest
         CgScal s = *col.sc;
         s.pq = pq;
         if (s.active) {
-            if (!(pq > 0.0) || !isfinite(pq)) {
+            if (pq == 0.0 && s.rho == 0.0) {
+                s.a = 0.0;  // zero residual waiting for its float64 check
+            } else if (!(pq > 0.0) || !isfinite(pq)) {
                 s.active = 0;
                 s.status = 2;
             } else {
@@ -189,16 +200,16 @@ __global__ __launch_bounds__(kRedBlock) void cg_update_xr_kernel(const CgCol *__
 }
 
 // r = y - q (q = A x); partial r.r.  A column is replaced at its own
-// iterations kResidualPeriod, 2 kResidualPeriod, ... (the current iteration
-// is iters + 1), so the cadence does not depend on which other solves share
-// the launch; `force` replaces every column (final residual).
+// iterations period, 2 period, ... (the current iteration is iters + 1), so
+// the cadence does not depend on which other solves share the launch;
+// `force` replaces every column (final residual).
 __global__ __launch_bounds__(kRedBlock) void cg_replace_kernel(const CgCol *__restrict__ cols,
                                                                const int32_t *__restrict__ prefix,
                                                                int cnt, int force) {
     __shared__ double sh[kRedBlock / 64];
     const ColRange cr = col_range(cols, prefix, cnt);
     const CgScal sc = *cr.col.sc;
-    const bool act = force || (sc.active != 0 && (sc.iters + 1) % kResidualPeriod == 0);
+    const bool act = force || (sc.active != 0 && (sc.iters + 1) % sc.period == 0);
     double v = 0.0;
     for (int64_t i = cr.i0 + threadIdx.x; i < cr.i1; i += kRedBlock) {
         double ri;
@@ -214,19 +225,24 @@ __global__ __launch_bounds__(kRedBlock) void cg_replace_kernel(const CgCol *__re
     if (threadIdx.x == 0) cr.col.partial[cr.lb] = v;
 }
 
-// rho' = r.r; convergence and iteration-limit tests; b = rho'/rho
-__global__ __launch_bounds__(kRedBlock) void cg_beta_kernel(const CgCol *__restrict__ cols) {
+// rho' = r.r; convergence and iteration-limit tests; b = rho'/rho.
+// `replaced`: this launch recomputed the residual of the columns whose
+// period is due; an exact_only column may stop only then.
+__global__ __launch_bounds__(kRedBlock) void cg_beta_kernel(const CgCol *__restrict__ cols,
+                                                            int replaced) {
     __shared__ double sh[kRedBlock / 64];
     const CgCol col = cols[blockIdx.x];
     const double rr = sum_partials(col.partial, col.nblk, sh);
     if (threadIdx.x == 0) {
         CgScal s = *col.sc;
         if (s.active) {
+            const bool checked =
+                !s.exact_only || (replaced && (s.iters + 1) % s.period == 0);
             s.iters += 1;
             if (!isfinite(rr)) {
                 s.active = 0;
                 s.status = 2;
-            } else if (rr <= s.tol2 * s.ynorm2) {
+            } else if (checked && rr <= s.tol2 * s.ynorm2) {
                 s.active = 0;
                 s.status = 1;
                 s.rho = rr;
@@ -235,7 +251,7 @@ __global__ __launch_bounds__(kRedBlock) void cg_beta_kernel(const CgCol *__restr
                 s.status = 3;
                 s.rho = rr;
             } else {
-                s.b = rr / s.rho;
+                s.b = s.rho > 0.0 ? rr / s.rho : 0.0;
                 s.rho = rr;
             }
         }
@@ -284,13 +300,27 @@ struct anova_cg_s {
     double *x = nullptr;
     double beta = 1.0, tol = 0.0;
     int maxit = 0;
+    int period = 0;           // residual replacement period
+    bool exact_only = false;  // float32 plan with float64 residuals
     int64_t it = 0;  // iterations taken (every active column has taken as many)
     DevBuf r, p, q, partial, scal;
+    DevBuf work;  // product work space of this solve's (window, column) instances
     ColList own;  // this solve's columns alone (init, final residual)
     std::unique_ptr<Batch> xq;  // q = A x, for the final residual
 };
 
 namespace anova {
+
+// Work space of one solve: its products p -> q (plan precision) and x -> q
+// (residual windows) run one after another and share it.
+static size_t solve_work_bytes(anova_plan_s *plan, int nrhs) {
+    BatchProblem bp;
+    bp.plan = plan;
+    bp.nrhs = nrhs;
+    const size_t a = problem_work_bytes(bp);
+    bp.residual = true;
+    return std::max(a, problem_work_bytes(bp));
+}
 
 // Captured iteration for one list of solves.
 struct StepGraph {
@@ -324,7 +354,7 @@ static void record_iteration(StepGraph &G, bool replace, hipStream_t s) {
         hipLaunchKernelGGL(cg_replace_kernel, dim3(L.blocks), dim3(kRedBlock), 0, s, dc, dp, L.cnt,
                            0);
     }
-    hipLaunchKernelGGL(cg_beta_kernel, dim3(L.cnt), dim3(kRedBlock), 0, s, dc);
+    hipLaunchKernelGGL(cg_beta_kernel, dim3(L.cnt), dim3(kRedBlock), 0, s, dc, replace ? 1 : 0);
     hipLaunchKernelGGL(cg_update_p_kernel, dim3(L.blocks), dim3(kRedBlock), 0, s, dc, dp, L.cnt);
     ANOVA_HIP_CHECK(hipGetLastError());
 }
@@ -347,14 +377,16 @@ static hipGraphExec_t capture(StepGraph &G, bool replace) {
     return ex;
 }
 
-static BatchProblem product(anova_cg_s *sv, const double *in) {
+static BatchProblem product(anova_cg_s *sv, const double *in, bool residual) {
     BatchProblem bp;
+    bp.residual = residual;
     bp.plan = sv->plan;
     bp.alpha = in;
     bp.out = sv->q.as<double>();
     bp.nrhs = sv->nrhs;
     bp.ld = sv->N;
     bp.beta = sv->beta;
+    bp.work = sv->work.ptr;  // products of one solve run one after another on its stream
     return bp;
 }
 
@@ -375,8 +407,8 @@ static StepGraph &step_graph(anova_cg_s *const *solves, int count) {
     for (int i = 0; i < count; ++i) {
         anova_cg_s *sv = solves[i];
         G->list.cols.insert(G->list.cols.end(), sv->own.cols.begin(), sv->own.cols.end());
-        pq_probs.push_back(product(sv, sv->p.as<double>()));
-        BatchProblem bx = product(sv, sv->x);
+        pq_probs.push_back(product(sv, sv->p.as<double>(), false));
+        BatchProblem bx = product(sv, sv->x, true);
         bx.ld = sv->ld;      // x columns follow the caller's leading dimension
         bx.ld_out = sv->N;   // q is packed
         xq_probs.push_back(bx);
@@ -471,6 +503,9 @@ extern "C" anova_status krr_cg_start(anova_cg_t *out, anova_plan_t plan, const d
         sv->q.alloc(vec);
         sv->partial.alloc((size_t)nblk * nrhs * sizeof(double));
         sv->scal.alloc(sizeof(CgScal) * nrhs);
+        sv->exact_only = plan->precision == ANOVA_FP32_NFFT && !plan->win64.empty();
+        sv->period = sv->exact_only ? kResidualPeriodExact : kResidualPeriod;
+        sv->work.alloc(solve_work_bytes(plan, nrhs));
         for (int c = 0; c < nrhs; ++c) {
             CgCol col{};
             col.x = alpha + (size_t)c * ld;
@@ -489,7 +524,7 @@ extern "C" anova_status krr_cg_start(anova_cg_t *out, anova_plan_t plan, const d
         hipLaunchKernelGGL(cg_init_kernel, dim3(sv->own.blocks), dim3(kRedBlock), 0, s, dc,
                            sv->own.d_prefix.as<int32_t>(), sv->own.cnt);
         hipLaunchKernelGGL(cg_init_scal_kernel, dim3(sv->own.cnt), dim3(kRedBlock), 0, s, dc, tol,
-                           maxit);
+                           maxit, sv->period, sv->exact_only ? 1 : 0);
         ANOVA_HIP_CHECK(hipGetLastError());
         *out = sv.release();
         return ANOVA_OK;
@@ -504,15 +539,17 @@ extern "C" anova_status krr_cg_iterate(anova_cg_t *solves, int32_t count, int32_
         for (int i = 0; i < count; ++i) {
             ANOVA_REQUIRE(solves[i] != nullptr, "NULL solve");
             for (int j = 0; j < i; ++j) ANOVA_REQUIRE(solves[j] != solves[i], "repeated solve");
-            ANOVA_REQUIRE(solves[i]->plan->precision == solves[0]->plan->precision,
-                          "solves of one list must share the precision");
+            ANOVA_REQUIRE(solves[i]->plan->precision == solves[0]->plan->precision &&
+                              solves[i]->exact_only == solves[0]->exact_only,
+                          "solves of one list must share the precision and residual mode");
         }
         std::lock_guard<std::mutex> lock(g_step_mu);
         StepGraph &G = step_graph(solves, count);
         hipStream_t s = (hipStream_t)stream;
         for (int k = 0; k < iters; ++k) {
             bool rep = false;
-            for (int i = 0; i < count; ++i) rep = rep || (solves[i]->it + 1) % kResidualPeriod == 0;
+            for (int i = 0; i < count; ++i)
+                rep = rep || (solves[i]->it + 1) % solves[i]->period == 0;
             ANOVA_HIP_CHECK(hipGraphLaunch(rep ? G.g_replace : G.g_plain, s));
             for (int i = 0; i < count; ++i) ++solves[i]->it;
         }
@@ -548,6 +585,8 @@ extern "C" anova_status krr_cg_finish(anova_cg_t sv, krr_cg_info *info, void *st
             bp.ld = sv->ld;
             bp.ld_out = sv->N;
             bp.beta = sv->beta;
+            bp.work = sv->work.ptr;
+            bp.residual = true;
             sv->xq->build({bp});
         }
         sv->xq->run(s);
@@ -590,6 +629,28 @@ extern "C" anova_status krr_cg_destroy(anova_cg_t sv) {
         }
         (void)hipDeviceSynchronize();
         delete sv;
+        return ANOVA_OK;
+    });
+}
+
+extern "C" anova_status anova_plan_footprint(anova_plan_t plan, int32_t nrhs,
+                                             int64_t *plan_bytes, int64_t *solve_bytes) {
+    return guarded_cg([&] {
+        ANOVA_REQUIRE(plan != nullptr, "NULL plan");
+        ANOVA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+        if (plan_bytes) *plan_bytes = (int64_t)plan_device_bytes(plan);
+        if (solve_bytes) {
+            const int64_t N = plan->N;
+            const int64_t nblk = (N + kSpan - 1) / kSpan;
+            // r, p, q, partial sums, scalars, work space, column tables
+            // (each allocation rounded as DevBuf rounds an empty one)
+            auto dev = [](size_t b) { return (int64_t)std::max<size_t>(b, 256); };
+            int64_t b = 3 * dev((size_t)N * nrhs * sizeof(double));
+            b += dev((size_t)nblk * nrhs * sizeof(double)) + dev(sizeof(CgScal) * nrhs);
+            b += dev(solve_work_bytes(plan, nrhs));
+            b += dev(sizeof(CgCol) * nrhs) + dev(sizeof(int32_t) * (nrhs + 1));
+            *solve_bytes = b;
+        }
         return ANOVA_OK;
     });
 }

@@ -540,7 +540,8 @@ void validate(const double *X, int64_t N, int32_t d, int64_t ldx, const anova_wi
     ANOVA_REQUIRE(std::isfinite(prm->h) && prm->h >= 0, "h must be finite and >= 0");
     ANOVA_REQUIRE(std::isfinite(prm->target_err) && prm->target_err >= 0, "target_err must be >= 0");
     ANOVA_REQUIRE(prm->center == 0 || prm->center == 1, "center must be 0 or 1");
-    ANOVA_REQUIRE(prm->reserved == 0, "reserved must be 0");
+    ANOVA_REQUIRE(prm->residual == ANOVA_RESIDUAL_FP64 || prm->residual == ANOVA_RESIDUAL_SAME,
+                  "residual must be ANOVA_RESIDUAL_FP64 or ANOVA_RESIDUAL_SAME");
     for (int l = 0; l < P; ++l) {
         const anova_window &w = win[l];
         ANOVA_REQUIRE(w.d_A >= 1 && w.d_A <= 3, "window d_A must be 1, 2 or 3");
@@ -605,6 +606,18 @@ static anova_status guarded(F &&f) {
     }
 }
 
+size_t anova::plan_device_bytes(const anova_plan_s *p) {
+    size_t b = 0;
+    for (const std::vector<WindowPlan> *ws : {&p->win, &p->win64})
+      for (const WindowPlan &w : *ws)
+        for (const DevBuf *d : {&w.nodes, &w.perm, &w.iperm, &w.subs, &w.poly, &w.bconv, &w.twiddle,
+                                &w.src_sub, &w.cell_start, &w.tiles_ne, &w.fold_pairs,
+                                &w.fold_start})
+            b += d->bytes;
+    if (p->mv_batch) b += p->mv_batch->device_bytes();
+    return b;
+}
+
 extern "C" anova_status anova_fastsum_plan(anova_plan_t *out, const double *X, int64_t N,
                                            int32_t d, int64_t ldx, const anova_window *win,
                                            int32_t P, const anova_params *prm, void *stream) {
@@ -665,6 +678,18 @@ extern "C" anova_status anova_fastsum_plan(anova_plan_t *out, const double *X, i
                 build_window<double, NodeF64>(w, Xh, N, ldx, prm->precision);
             else
                 build_window<float, NodeF32>(w, Xh, N, ldx, prm->precision);
+        }
+        if (prm->precision == ANOVA_FP32_NFFT && prm->residual == ANOVA_RESIDUAL_FP64) {
+            // the same windows and parameters in float64, for CG's residuals
+            p->win64.resize(P);
+            for (int l = 0; l < P; ++l) {
+                const WindowPlan &w = p->win[l];
+                WindowPlan &v = p->win64[l];
+                v.dA = w.dA; v.eta = w.eta; v.ell = w.ell; v.h = w.h; v.extent = w.extent;
+                v.M = w.M; v.n = w.n; v.m = w.m; v.kb_b = w.kb_b;
+                for (int t = 0; t < 3; ++t) { v.feat[t] = w.feat[t]; v.center[t] = w.center[t]; }
+                build_window<double, NodeF64>(v, Xh, N, ldx, ANOVA_FP64);
+            }
         }
         if (prm->target_err > 0) {
             double tot = 0.0;

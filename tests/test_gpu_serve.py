@@ -1,0 +1,108 @@
+"""The serving loop on the GPU: requests that join and leave the running list
+give the same alpha as the same solve run alone (bitwise: every column
+iterates independently and every product is deterministic), and the
+footprint the library reports matches the device memory it takes."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_util import dev_cols, dev_rows, empty_cols, to_np
+
+pytestmark = pytest.mark.gpu
+
+F32 = 1
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2111_10140_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def alone(A, p, precision, tol, maxit):
+    import torch
+    plan = A.anova_fastsum_plan(dev_rows(p.X), p.windows,
+                                A.make_params(p.ell, precision, target_err=1e-4))
+    y = dev_cols(p.y)
+    x = empty_cols(p.N, p.nrhs)
+    info = A.krr_cg_solve(plan, y, x, p.beta, tol, maxit, allow_not_converged=True)
+    torch.cuda.synchronize()
+    out = to_np(x).reshape(p.N, p.nrhs)
+    plan.destroy()
+    return out, info
+
+
+def test_served_requests_equal_alone_bitwise(A):
+    from paper_2111_10140_amd.serve import HipExecutor, Server
+    reqs = workloads.serving_stream(7, rate=1.0, n_lo=500, n_hi=6000, rhs_max=3)
+    ex = HipExecutor(F32, target_err=1e-4)
+    # a budget that holds about three of these requests: the rest queue
+    est = sorted(ex.estimate_problem(r.problem) for r in reqs)
+    srv = Server(ex, budget=int(est[-1] + est[-2] + est[-3]), max_live=4, iters_per_round=3)
+    hs = []
+    for k, r in enumerate(reqs):
+        p = r.problem
+        hs.append(srv.submit(p.X, p.windows, p.ell, p.beta, p.y, tol=1e-6, maxit=2000))
+        if k in (2, 4):  # later requests arrive while earlier ones iterate
+            srv.step()
+            srv.step()
+    while srv.busy():
+        srv.step()
+        assert srv.reserved <= srv.budget
+    assert srv.reserved == 0
+    assert srv.peak_live >= 2, "requests did not overlap"
+    for r, h in zip(reqs, hs):
+        p = r.problem
+        res = srv.result(h)
+        assert res.status == "OK", (res.status, res.error)
+        ref, info = alone(A, p, F32, 1e-6, 2000)
+        assert [i["iters"] for i in res.info] == [i["iters"] for i in info]
+        assert np.array_equal(res.alpha.reshape(p.N, p.nrhs), ref), f"request {h} differs"
+        assert all(i["true_relres"] <= 1e-5 for i in res.info)
+    # one request against the oracle's exact operator on sampled rows
+    p = reqs[0].problem
+    a = srv.result(hs[0]).alpha.reshape(p.N, p.nrhs)
+    rows = np.arange(0, p.N, max(1, p.N // 40))
+    Ka = oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a, rows=rows)
+    res = np.max(np.abs(p.y[rows] - Ka)) / np.abs(a).sum(axis=0).min()
+    assert res <= 1e-4
+    st = srv.stats(warmup_fraction=0.0)
+    assert st["completed"] == len(reqs) and st["p99_s"] >= st["p50_s"] > 0
+
+
+def test_oversized_request_rejected_on_device(A):
+    from paper_2111_10140_amd.serve import HipExecutor, Server
+    p = workloads.random_problem(200_000, 6, [(0, 1, 2), (3, 4, 5)], 0.2, nrhs=4, seed=71)
+    q = workloads.random_problem(2000, 3, [(0, 1, 2)], 0.2, seed=72)
+    ex = HipExecutor(F32)
+    srv = Server(ex, budget=ex.estimate_problem(q) * 4)
+    big = srv.submit(p.X, p.windows, p.ell, p.beta, p.y)
+    small = srv.submit(q.X, q.windows, q.ell, q.beta, q.y)
+    srv.run_until_idle()
+    assert srv.result(big).status == "REJECTED"
+    assert srv.result(small).status == "OK"
+    assert srv.reserved == 0
+
+
+def test_footprint_matches_device_memory(A):
+    import torch
+    p = workloads.random_problem(200_000, 9, [(0, 1, 2), (3, 4, 5), (6, 7, 8)], 0.2, nrhs=2,
+                                 seed=73)
+    X = dev_rows(p.X)
+    y = dev_cols(p.y)
+    x = empty_cols(p.N, p.nrhs)
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
+    plan = A.anova_fastsum_plan(X, p.windows, A.make_params(p.ell, F32, target_err=1e-4))
+    sv = A.Solve(plan, y, x, p.beta, 1e-6, 10)
+    torch.cuda.synchronize()
+    used = free0 - torch.cuda.mem_get_info()[0]
+    pb, sb = plan.footprint(p.nrhs)
+    print(f"device bytes taken {used}, reported plan {pb} + solve {sb} = {pb + sb}")
+    assert 0.8 * (pb + sb) - (4 << 20) <= used <= 1.25 * (pb + sb) + (16 << 20)
+    sv.destroy()
+    plan.destroy()
