@@ -107,7 +107,7 @@ def stage_profile(A, torch, plan, a, out, beta, steps):
 def serve_stream(Server, ex, reqs, arrivals, budget, max_live):
     """Feed requests to a server at the given arrival offsets (seconds) in
     real time; returns the server once every request is done."""
-    srv = Server(ex, budget=budget, max_live=max_live, iters_per_round=4)
+    srv = Server(ex, budget=budget, max_live=max_live, iters_per_round=4, planners=4)
     order = sorted(range(len(reqs)), key=lambda k: arrivals[k])
     t0 = time.perf_counter()
     k = 0
@@ -122,7 +122,37 @@ def serve_stream(Server, ex, reqs, arrivals, budget, max_live):
             srv.step()
         elif k < len(order):
             time.sleep(max(0.0, arrivals[order[k]] - (time.perf_counter() - t0)))
+    srv.close()
     return srv
+
+
+def precision_split(A, torch, X, p, a, out, plan32, target):
+    """The float32-NFFT path (float64 CG, float64 residuals) against the
+    plain float64 path on the same GPU, both planned for the same per-entry
+    error target: matvecs/s and one full CG solve of the headline system."""
+    y = torch.from_numpy(np.ascontiguousarray(p.y[:, 0])).cuda()
+    res, xs = {}, {}
+    plan64 = A.anova_fastsum_plan(X, p.windows, A.make_params(p.ell, A.ANOVA_FP64,
+                                                              target_err=target))
+    for name, plan in [("fp32_nfft", plan32), ("fp64_plain", plan64)]:
+        ms = time_matvecs(A, torch, plan, a, out, p.beta, 50, 5)
+        x = torch.empty_like(y)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = A.krr_cg_solve(plan, y, x, p.beta, 1e-6, 3000, allow_not_converged=True)
+        torch.cuda.synchronize()
+        t_cg = time.perf_counter() - t
+        xs[name] = x.cpu().numpy()
+        i0 = plan.info(0)
+        res[name] = {"matvecs_per_s": round(1e3 / ms, 2), "ms_per_matvec": round(ms, 4),
+                     "params": dict(M=i0.M, n=i0.n, m=i0.m), "err_estimate": plan.err_estimate(),
+                     "cg_iters": info[0]["iters"], "cg_true_relres": info[0]["true_relres"],
+                     "cg_seconds": round(t_cg, 4)}
+    plan64.destroy()
+    d = np.linalg.norm(xs["fp32_nfft"] - xs["fp64_plain"]) / np.linalg.norm(xs["fp64_plain"])
+    res["solution_rel_diff"] = float(d)
+    res["cg"] = "tol 1e-6 on y of the headline workload, beta=1, x0=0"
+    return res
 
 
 def serving(args, A):
@@ -250,6 +280,10 @@ def main():
     else:
         err = None
 
+    split = None
+    if not args.skip_fixed:
+        split = precision_split(A, torch, X, p, a, out, plan, args.target)
+        print(f"# precision split: {json.dumps(split)}", file=sys.stderr, flush=True)
     served = None if args.skip_serve else serving(args, A)
 
     res = {
@@ -267,6 +301,7 @@ def main():
         "stages_per_launch": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
                                   for kk, vv in v.items()} for k, v in per_launch.items()},
         "fixed_params": fixed,
+        "precision_split": split,
         "serving": served,
         "cpu_baseline": cpu,
     }

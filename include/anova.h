@@ -148,6 +148,17 @@ anova_status anova_fastsum_plan(anova_plan_t *out, const double *X, int64_t N, i
                                 const anova_params *prm, void *stream);
 
 /*
+ * anova_fastsum_plan with X in host memory (N x d row-major float64, ldx >=
+ * d): the same plan without a device copy of the points.  Safe to call from
+ * several host threads at once and while other threads run solves; the
+ * library's own device allocations and uploads are serialised with its graph
+ * captures.  Errors as anova_fastsum_plan.
+ */
+anova_status anova_fastsum_plan_host(anova_plan_t *out, const double *X, int64_t N, int32_t d,
+                                     int64_t ldx, const anova_window *win, int32_t P,
+                                     const anova_params *prm);
+
+/*
  * out = (K~ + beta I) alpha for nrhs columns (device arrays, column-major,
  * leading dimension ld >= N; alpha and out must not overlap).  K~ is the
  * fast-summation approximation of K (Sec. 4.3, K alpha ~ Phi D Phi^* alpha,
@@ -162,9 +173,9 @@ anova_status anova_matvec(anova_plan_t plan, const double *alpha, double *out, i
  * Solve (K~ + beta I) alpha = y by conjugate gradients (Sec. 2), one
  * independent recurrence per column, no preconditioner.  x0 = 0; dot
  * products, vector updates and residual recomputations are float64.  Every
- * R iterations of a column its residual is recomputed as y - (K~ + beta I) x
- * (residual replacement): R = 50 on FP64 plans; R = 25 on FP32_NFFT plans,
- * where the recomputation uses the float64 product (ANOVA_RESIDUAL_FP64,
+ * R = 50 iterations of a column its residual is recomputed as
+ * y - (K~ + beta I) x (residual replacement); on FP32_NFFT plans the
+ * recomputation uses the float64 product (ANOVA_RESIDUAL_FP64,
  * the default) and a column stops only when such a recomputed residual
  * satisfies ||r||_2 <= tol ||y||_2 (on FP64 plans, and with
  * ANOVA_RESIDUAL_SAME, any iteration's residual may stop it).  At exit the

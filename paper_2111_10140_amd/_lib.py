@@ -100,6 +100,8 @@ def load():
                                  dbl, i32, ctypes.POINTER(krr_cg_info), VP],
         "anova_plan_stage_times": [VP, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
         "anova_plan_footprint": [VP, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "anova_fastsum_plan_host": [ctypes.POINTER(VP), VP, i64, i32, i64,
+                                    ctypes.POINTER(anova_window), i32, ctypes.POINTER(anova_params)],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -248,6 +250,22 @@ def anova_fastsum_plan(X, windows, params: anova_params, stream=None) -> Plan:
     h = VP()
     st = load().anova_fastsum_plan(ctypes.byref(h), X.data_ptr(), N, d, X.stride(0), wins,
                                    len(windows), ctypes.byref(params), _stream(stream))
+    _check(st)
+    return Plan(h.value, N, len(windows), params.precision)
+
+
+def anova_fastsum_plan_host(X, windows, params: anova_params) -> Plan:
+    """Plan for host points X ((N, d) float64 numpy array); no device copy of
+    X is made, and it may run on any host thread."""
+    import numpy as np
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    if X.ndim != 2:
+        raise ValueError("X must be (N, d)")
+    N, d = X.shape
+    wins = make_windows(windows)
+    h = VP()
+    st = load().anova_fastsum_plan_host(ctypes.byref(h), X.ctypes.data, N, d, d, wins,
+                                        len(windows), ctypes.byref(params))
     _check(st)
     return Plan(h.value, N, len(windows), params.precision)
 

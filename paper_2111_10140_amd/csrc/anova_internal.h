@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -35,6 +36,11 @@ struct Error {
     } while (0)
 
 // ---------------------------------------------------------------- device buffer
+// Serialises the library's device allocations, frees and synchronous
+// uploads with hipGraph captures, which other threads' such calls can
+// invalidate (plans may be built on several host threads).
+std::recursive_mutex &device_mutex();
+
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
@@ -51,11 +57,15 @@ struct DevBuf {
     void alloc(size_t b) {
         release();
         if (b == 0) b = 256;
+        std::lock_guard<std::recursive_mutex> lock(device_mutex());
         ANOVA_HIP_CHECK(hipMalloc(&ptr, b));
         bytes = b;
     }
     void release() {
-        if (ptr) (void)hipFree(ptr);
+        if (ptr) {
+            std::lock_guard<std::recursive_mutex> lock(device_mutex());
+            (void)hipFree(ptr);
+        }
         ptr = nullptr; bytes = 0;
     }
     template <typename T> T *as() const { return static_cast<T *>(ptr); }
@@ -299,6 +309,7 @@ template <typename T>
 void upload(DevBuf &buf, const std::vector<T> &v) {
     size_t bytes = v.size() * sizeof(T);
     bytes = (bytes + 255) & ~(size_t)255;
+    std::lock_guard<std::recursive_mutex> lock(device_mutex());
     if (!buf.ptr || buf.bytes < bytes) buf.alloc(bytes);
     if (!v.empty())
         ANOVA_HIP_CHECK(hipMemcpy(buf.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));

@@ -31,7 +31,7 @@ namespace anova {
 constexpr int kRedBlock = 256;
 constexpr int kSpan = 4 * kRedBlock;  // elements per block and column
 constexpr int kResidualPeriod = 50;        // replacement with the plan's own product
-constexpr int kResidualPeriodExact = 25;   // float64 residuals of float32 plans
+constexpr int kResidualPeriodExact = 50;   // float64 residuals of float32 plans
 
 struct CgScal {
     double rho;      // r.r of the current residual
@@ -53,6 +53,7 @@ struct CgCol {
     double *r, *p, *q;
     const double *y;
     double *partial;       // nblk partial sums
+    double *partial2;      // nblk partial sums of the replaced (recursive) residual
     CgScal *sc;
     int64_t N;
     int32_t nblk;
@@ -199,7 +200,8 @@ __global__ __launch_bounds__(kRedBlock) void cg_update_xr_kernel(const CgCol *__
     if (threadIdx.x == 0) cr.col.partial[cr.lb] = v;
 }
 
-// r = y - q (q = A x); partial r.r.  A column is replaced at its own
+// r = y - q (q = A x); partial r.r, and in partial2 the r.r of the
+// recursive residual it replaces.  A column is replaced at its own
 // iterations period, 2 period, ... (the current iteration is iters + 1), so
 // the cadence does not depend on which other solves share the launch;
 // `force` replaces every column (final residual).
@@ -210,34 +212,43 @@ __global__ __launch_bounds__(kRedBlock) void cg_replace_kernel(const CgCol *__re
     const ColRange cr = col_range(cols, prefix, cnt);
     const CgScal sc = *cr.col.sc;
     const bool act = force || (sc.active != 0 && (sc.iters + 1) % sc.period == 0);
-    double v = 0.0;
+    double v = 0.0, v_rec = 0.0;
     for (int64_t i = cr.i0 + threadIdx.x; i < cr.i1; i += kRedBlock) {
-        double ri;
+        double ri = cr.col.r[i];
         if (act) {
+            v_rec += ri * ri;
             ri = cr.col.y[i] - cr.col.q[i];
             cr.col.r[i] = ri;
-        } else {
-            ri = cr.col.r[i];
         }
         v += ri * ri;
     }
     v = block_sum(v, sh);
-    if (threadIdx.x == 0) cr.col.partial[cr.lb] = v;
+    v_rec = block_sum(v_rec, sh);
+    if (threadIdx.x == 0) {
+        cr.col.partial[cr.lb] = v;
+        cr.col.partial2[cr.lb] = v_rec;
+    }
 }
 
 // rho' = r.r; convergence and iteration-limit tests; b = rho'/rho.
 // `replaced`: this launch recomputed the residual of the columns whose
-// period is due; an exact_only column may stop only then.
+// period is due; an exact_only column may stop only then.  When such a
+// recomputed (float64) residual has drifted above the recursive one
+// (r.r more than 4 times larger), the float32 recursion has reached its
+// rounding floor: continuing its directions would scale p by rho'/rho and
+// the product's rounding with it, so the column restarts with p = r.
 __global__ __launch_bounds__(kRedBlock) void cg_beta_kernel(const CgCol *__restrict__ cols,
                                                             int replaced) {
     __shared__ double sh[kRedBlock / 64];
     const CgCol col = cols[blockIdx.x];
     const double rr = sum_partials(col.partial, col.nblk, sh);
+    const double rr_rec = replaced ? sum_partials(col.partial2, col.nblk, sh) : 0.0;
     if (threadIdx.x == 0) {
         CgScal s = *col.sc;
         if (s.active) {
-            const bool checked =
-                !s.exact_only || (replaced && (s.iters + 1) % s.period == 0);
+            const bool now = replaced && (s.iters + 1) % s.period == 0;
+            const bool checked = !s.exact_only || now;
+            const bool restart = s.exact_only && now && rr > 4.0 * rr_rec;
             s.iters += 1;
             if (!isfinite(rr)) {
                 s.active = 0;
@@ -251,7 +262,7 @@ __global__ __launch_bounds__(kRedBlock) void cg_beta_kernel(const CgCol *__restr
                 s.status = 3;
                 s.rho = rr;
             } else {
-                s.b = s.rho > 0.0 ? rr / s.rho : 0.0;
+                s.b = (s.rho > 0.0 && !restart) ? rr / s.rho : 0.0;
                 s.rho = rr;
             }
         }
@@ -391,6 +402,8 @@ static BatchProblem product(anova_cg_s *sv, const double *in, bool residual) {
 }
 
 static StepGraph &step_graph(anova_cg_s *const *solves, int count) {
+    // building and capturing must not overlap other threads' allocations
+    std::lock_guard<std::recursive_mutex> dev_lock(device_mutex());
     std::vector<uint64_t> ids(count);
     for (int i = 0; i < count; ++i) ids[i] = solves[i]->id;
     for (size_t k = 0; k < g_steps.size(); ++k)
@@ -501,7 +514,7 @@ extern "C" anova_status krr_cg_start(anova_cg_t *out, anova_plan_t plan, const d
         sv->r.alloc(vec);
         sv->p.alloc(vec);
         sv->q.alloc(vec);
-        sv->partial.alloc((size_t)nblk * nrhs * sizeof(double));
+        sv->partial.alloc((size_t)2 * nblk * nrhs * sizeof(double));
         sv->scal.alloc(sizeof(CgScal) * nrhs);
         sv->exact_only = plan->precision == ANOVA_FP32_NFFT && !plan->win64.empty();
         sv->period = sv->exact_only ? kResidualPeriodExact : kResidualPeriod;
@@ -514,6 +527,7 @@ extern "C" anova_status krr_cg_start(anova_cg_t *out, anova_plan_t plan, const d
             col.q = sv->q.as<double>() + (size_t)c * sv->N;
             col.y = y + (size_t)c * ld;
             col.partial = sv->partial.as<double>() + (size_t)c * nblk;
+            col.partial2 = sv->partial.as<double>() + (size_t)(nrhs + c) * nblk;
             col.sc = sv->scal.as<CgScal>() + c;
             col.N = sv->N;
             col.nblk = nblk;
@@ -646,7 +660,7 @@ extern "C" anova_status anova_plan_footprint(anova_plan_t plan, int32_t nrhs,
             // (each allocation rounded as DevBuf rounds an empty one)
             auto dev = [](size_t b) { return (int64_t)std::max<size_t>(b, 256); };
             int64_t b = 3 * dev((size_t)N * nrhs * sizeof(double));
-            b += dev((size_t)nblk * nrhs * sizeof(double)) + dev(sizeof(CgScal) * nrhs);
+            b += dev((size_t)2 * nblk * nrhs * sizeof(double)) + dev(sizeof(CgScal) * nrhs);
             b += dev(solve_work_bytes(plan, nrhs));
             b += dev(sizeof(CgCol) * nrhs) + dev(sizeof(int32_t) * (nrhs + 1));
             *solve_bytes = b;

@@ -260,6 +260,20 @@ struct CellShape {
     static constexpr int cells = DA == 3 ? TILE * TILE * TILE : (DA == 2 ? TILE * TILE : TILE);
 };
 
+// Sum over the four lanes of a quad (lanes 4c .. 4c+3) with DPP quad
+// permutations; every lane of the quad gets the same bits (each step adds
+// two values in an order-independent way).  All four lanes must be active.
+__device__ __forceinline__ float quad_sum(float v) {
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));  // [1,0,3,2]
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));  // [2,3,0,1]
+    return v;
+}
+
+// Spreading per cell.  After the point loop, the S splits of a cell are
+// summed across their lanes, the cells' W^d_A register tiles are staged in
+// LDS, and each thread forms the region values it owns by adding the staged
+// contributions of every cell whose support covers them, in a fixed order.
+// No atomics: the region is the same bits for any scheduling.
 template <int DA, int W, int TILE, int S>
 __global__ __launch_bounds__(kBlock) void spread_cell_kernel(const WinInst *__restrict__ insts,
                                                              const int32_t *__restrict__ members,
@@ -270,9 +284,10 @@ __global__ __launch_bounds__(kBlock) void spread_cell_kernel(const WinInst *__re
     constexpr int VOL = DA == 3 ? L2 * L : L2;
     constexpr int CELLS = CellShape<DA, TILE>::cells;
     static_assert(CELLS * S == kBlock, "one thread per (cell, split)");
+    static_assert(S == 1 || S == 4, "splits of a cell are summed within a quad");
     constexpr int WY = DA >= 2 ? W : 1, WZ = DA == 3 ? W : 1;
-    __shared__ unsigned long long acc_lds[VOL];
-    __shared__ float red[kBlock / 64];
+    constexpr int VW = WZ * WY * W;  // support values of one cell
+    __shared__ float stage[CELLS * VW];
     const Located loc = locate(insts, members, prefix, cnt);
     const WinInst &wi = *loc.w;
     const NodeF32 *__restrict__ nodes = static_cast<const NodeF32 *>(wi.nodes);
@@ -282,12 +297,8 @@ __global__ __launch_bounds__(kBlock) void spread_cell_kernel(const WinInst *__re
     const int K = wi.chunks;
     const int tk = loc.lb / K, chunk = loc.lb % K;
     const int key0 = wi.tiles_ne[tk] * CELLS;
-    for (int e = threadIdx.x; e < VOL; e += kBlock) acc_lds[e] = 0ull;
-    const int cell = threadIdx.x / S;
-    const int q = chunk * S + (int)(threadIdx.x % S), QS = K * S;
-    const int lx = cell % TILE;
-    const int ly = DA >= 2 ? (cell / TILE) % TILE : 0;
-    const int lz = DA == 3 ? cell / (TILE * TILE) : 0;
+    const int cell = threadIdx.x / S, split = (int)(threadIdx.x % S);
+    const int q = chunk * S + split, QS = K * S;
     float acc[WZ][WY][W];
 #pragma unroll
     for (int c = 0; c < WZ; ++c)
@@ -295,9 +306,6 @@ __global__ __launch_bounds__(kBlock) void spread_cell_kernel(const WinInst *__re
         for (int b = 0; b < WY; ++b)
 #pragma unroll
             for (int i = 0; i < W; ++i) acc[c][b][i] = 0.0f;
-    // the fixed-point scale is needed only for the final flush, so the
-    // largest |coefficient| of the workgroup is tracked along the way
-    float amax = 0.0f;
     const int c1 = wi.cell_start[key0 + cell + 1];
     int j = wi.cell_start[key0 + cell] + q;
     // software pipeline: the next point's record and coefficient load while
@@ -315,7 +323,6 @@ __global__ __launch_bounds__(kBlock) void spread_cell_kernel(const WinInst *__re
             rec_n = nodes[j + QS];
             a_n = as[j + QS];
         }
-        amax = fmaxf(amax, abs_for_max((double)a));
         float wx[W], wy[W], wz[W];
         wp.eval(rec.f[0], wx);
         if constexpr (DA >= 2) wp.eval(rec.f[1], wy);
@@ -331,33 +338,54 @@ __global__ __launch_bounds__(kBlock) void spread_cell_kernel(const WinInst *__re
             }
         }
     }
-    // each register sum holds at most `taken` contributions of magnitude
-    // <= max|alpha|: the scale keeps every rounded sum below 2^30
-    const int c0 = wi.cell_start[key0 + cell] + q;
-    const float taken = c0 < c1 ? (float)((c1 - c0 + QS - 1) / QS) : 0.0f;
-    const float tmax = block_max(taken, red);
-    amax = block_max(amax, red);  // also orders the zero fill before the adds
-    float *out = static_cast<float *>(wi.priv) + (size_t)loc.lb * VOL;
-    if (trivial_region(amax, out, VOL)) return;
-    int ex2, ct;
-    (void)frexpf(amax * 1.0000002f, &ex2);
-    (void)frexpf(fmaxf(tmax, 1.0f), &ct);  // tmax < 2^ct
-    const int Sx = 30 - ex2 - ct;
+    // the cell's total over its S splits, staged as stage[cell][c][b][i];
+    // lane `split` of the quad stores the values with flat index = split mod S
+    float *cst = stage + cell * VW;
 #pragma unroll
-    for (int c = 0; c < WZ; ++c)
+    for (int k = 0; k < VW; k += S) {
+        float v = 0.0f;
 #pragma unroll
-        for (int b = 0; b < WY; ++b)
-#pragma unroll
-            for (int i = 0; i < W; ++i) {
-                const float v = acc[c][b][i];
-                if (v != 0.0f)
-                    atomicAdd(&acc_lds[((lz + c) * L + ly + b) * L + lx + i],
-                              (unsigned long long)round_to_ll(ldexpf(v, Sx)));
+        for (int t = 0; t < S; ++t) {
+            if (k + t < VW) {
+                const int kk = k + t;
+                float x = acc[kk / (WY * W)][(kk / W) % WY][kk % W];
+                if constexpr (S == 4) x = quad_sum(x);
+                if (t == split) v = x;
             }
+        }
+        if (k + split < VW) cst[k + split] = v;
+    }
     __syncthreads();
-    const double inv = ldexp(1.0, -Sx);
-    for (int e = threadIdx.x; e < VOL; e += kBlock)
-        out[e] = (float)((double)(long long)acc_lds[e] * inv);
+    // region point (X, Y, Z) gets cell (dx, dy, dz)'s value at offset
+    // (X - dx, Y - dy, Z - dz) when that offset lies in [0, W)
+    float *out = static_cast<float *>(wi.priv) + (size_t)loc.lb * VOL;
+    constexpr int KX = TILE < W ? TILE : W;  // loop over the shorter range
+    for (int e = threadIdx.x; e < VOL; e += kBlock) {
+        const int X = e % L;
+        const int Y = DA >= 2 ? (e / L) % L : 0;
+        const int Z = DA == 3 ? e / L2 : 0;
+        float sum = 0.0f;
+#pragma unroll 1
+        for (int kz = 0; kz < (DA == 3 ? KX : 1); ++kz) {
+            const int dz = DA == 3 ? (TILE <= W ? kz : Z - kz) : 0;
+            const int oz = Z - dz;
+            if (DA == 3 && (dz < 0 || dz >= TILE || oz < 0 || oz >= W)) continue;
+            for (int ky = 0; ky < (DA >= 2 ? KX : 1); ++ky) {
+                const int dy = DA >= 2 ? (TILE <= W ? ky : Y - ky) : 0;
+                const int oy = Y - dy;
+                if (DA >= 2 && (dy < 0 || dy >= TILE || oy < 0 || oy >= W)) continue;
+#pragma unroll
+                for (int kx = 0; kx < KX; ++kx) {
+                    const int dx = TILE <= W ? kx : X - kx;
+                    const int ox = X - dx;
+                    if (dx < 0 || dx >= TILE || ox < 0 || ox >= W) continue;
+                    const int cidx = (dz * (DA >= 2 ? TILE : 1) + dy) * TILE + dx;
+                    sum += stage[cidx * VW + (oz * WY + oy) * W + ox];
+                }
+            }
+        }
+        out[e] = sum;
+    }
 }
 
 template <int DA, int W, int TILE, int S>

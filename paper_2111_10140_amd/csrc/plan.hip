@@ -332,7 +332,7 @@ void build_fold_lists(const std::vector<int32_t> &src_tiles, int dA, int n, int 
 }
 
 template <typename T, typename Node>
-void build_window(WindowPlan &w, const std::vector<double> &Xh, int64_t N, int64_t ldx, int prec) {
+void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int prec) {
     const int dA = w.dA, n = w.n, m = w.m;
     // binning: cell index and fractional offset per point and dimension, from
     // t = n (x - c) / h + n/2 in float64 (periodic on [0, n))
@@ -556,6 +556,11 @@ void validate(const double *X, int64_t N, int32_t d, int64_t ldx, const anova_wi
 
 }  // namespace
 
+std::recursive_mutex &device_mutex() {
+    static std::recursive_mutex mu;
+    return mu;
+}
+
 hipEvent_t pool_event(anova_plan_s *p) {
     if (!p->event_pool.empty()) {
         hipEvent_t e = p->event_pool.back();
@@ -618,21 +623,12 @@ size_t anova::plan_device_bytes(const anova_plan_s *p) {
     return b;
 }
 
-extern "C" anova_status anova_fastsum_plan(anova_plan_t *out, const double *X, int64_t N,
-                                           int32_t d, int64_t ldx, const anova_window *win,
-                                           int32_t P, const anova_params *prm, void *stream) {
-    if (!out) {
-        set_error("out is NULL");
-        return ANOVA_E_INVALID;
-    }
-    *out = nullptr;
+// Plan from validated arguments and host points Xh (rows ldx apart).
+static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, int32_t d,
+                              int64_t ldx, const anova_window *win, int32_t P,
+                              const anova_params *prm) {
     anova_plan_s *p = nullptr;
     anova_status st = guarded([&] {
-        validate(X, N, d, ldx, win, P, prm);
-        hipStream_t s = (hipStream_t)stream;
-        std::vector<double> Xh((size_t)N * ldx);
-        ANOVA_HIP_CHECK(hipStreamSynchronize(s));
-        ANOVA_HIP_CHECK(hipMemcpy(Xh.data(), X, Xh.size() * sizeof(double), hipMemcpyDeviceToHost));
         for (size_t i = 0; i < (size_t)N; ++i)
             for (int t = 0; t < d; ++t)
                 ANOVA_REQUIRE(std::isfinite(Xh[i * ldx + t]), "X holds a non-finite value");
@@ -698,7 +694,8 @@ extern "C" anova_status anova_fastsum_plan(anova_plan_t *out, const double *X, i
                 throw Error{ANOVA_E_ACCURACY, "estimated per-entry error " + std::to_string(tot) +
                                                   " exceeds target_err"};
         }
-        ANOVA_HIP_CHECK(hipDeviceSynchronize());
+        // every upload above was a synchronous copy: the plan is complete and
+        // other streams' work is not waited for
     });
     if (st != ANOVA_OK) {
         delete p;
@@ -706,6 +703,42 @@ extern "C" anova_status anova_fastsum_plan(anova_plan_t *out, const double *X, i
     }
     *out = p;
     return ANOVA_OK;
+}
+
+extern "C" anova_status anova_fastsum_plan(anova_plan_t *out, const double *X, int64_t N,
+                                           int32_t d, int64_t ldx, const anova_window *win,
+                                           int32_t P, const anova_params *prm, void *stream) {
+    if (!out) {
+        set_error("out is NULL");
+        return ANOVA_E_INVALID;
+    }
+    *out = nullptr;
+    std::vector<double> Xh;
+    const anova_status st = guarded([&] {
+        validate(X, N, d, ldx, win, P, prm);
+        hipStream_t s = (hipStream_t)stream;
+        ANOVA_HIP_CHECK(hipStreamSynchronize(s));
+        // rows are ldx apart; the last row ends after its d entries
+        const size_t cnt = (size_t)(N - 1) * ldx + d;
+        Xh.resize(cnt);
+        std::lock_guard<std::recursive_mutex> lock(device_mutex());
+        ANOVA_HIP_CHECK(hipMemcpy(Xh.data(), X, cnt * sizeof(double), hipMemcpyDeviceToHost));
+    });
+    if (st != ANOVA_OK) return st;
+    return make_plan(out, Xh.data(), N, d, ldx, win, P, prm);
+}
+
+extern "C" anova_status anova_fastsum_plan_host(anova_plan_t *out, const double *X, int64_t N,
+                                                int32_t d, int64_t ldx, const anova_window *win,
+                                                int32_t P, const anova_params *prm) {
+    if (!out) {
+        set_error("out is NULL");
+        return ANOVA_E_INVALID;
+    }
+    *out = nullptr;
+    const anova_status st = guarded([&] { validate(X, N, d, ldx, win, P, prm); });
+    if (st != ANOVA_OK) return st;
+    return make_plan(out, X, N, d, ldx, win, P, prm);
 }
 
 extern "C" anova_status anova_plan_destroy(anova_plan_t p) {

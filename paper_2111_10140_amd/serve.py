@@ -38,7 +38,7 @@ import numpy as np
 DONE_STATES = ("OK", "E_NOT_CONVERGED", "E_BREAKDOWN", "ERROR", "REJECTED", "CANCELLED")
 
 
-@dataclass
+@dataclass(eq=False)  # compared by identity
 class Request:
     """One KRR solve: X (N, d) float64, windows [(features, eta)], y (N,) or (N, nrhs)."""
     X: np.ndarray
@@ -53,8 +53,10 @@ class Request:
     # filled by the server
     est_bytes: int = 0
     exact_bytes: Optional[int] = None
+    hold: int = 0                    # bytes reserved for it now
     admitted: float = math.nan
     state: Any = None
+    future: Any = None
 
     @property
     def N(self) -> int:
@@ -133,13 +135,16 @@ class Server:
     scheduling round (iterate the live list, admit, retire); result(handle)
     returns the Result once the request is done.  ``budget`` is the device
     memory (bytes) the live requests may hold together; ``max_live`` caps the
-    number of requests iterating at once; ``iters_per_round`` CG iterations
-    are run between polls of the live requests.
+    number of requests planning or iterating at once; ``iters_per_round`` CG
+    iterations are run between polls of the live requests.  With
+    ``planners`` > 0, plans are built by that many host threads while the
+    device iterates (the library releases the interpreter lock during a
+    call); with 0 they are built in step().
     """
 
     def __init__(self, executor, budget: int, max_live: int = 64, iters_per_round: int = 4,
-                 clock: Callable[[], float] = time.perf_counter):
-        if budget <= 0 or max_live < 1 or iters_per_round < 1:
+                 planners: int = 0, clock: Callable[[], float] = time.perf_counter):
+        if budget <= 0 or max_live < 1 or iters_per_round < 1 or planners < 0:
             raise ValueError("budget, max_live and iters_per_round must be positive")
         self.ex = executor
         self.budget = int(budget)
@@ -147,6 +152,7 @@ class Server:
         self.iters_per_round = int(iters_per_round)
         self.clock = clock
         self.queue: Deque[Request] = collections.deque()
+        self.planning: List[Request] = []
         self.live: List[Request] = []
         self.results: Dict[int, Result] = {}
         self.reserved = 0
@@ -154,6 +160,18 @@ class Server:
         self.peak_live = 0
         self.rounds = 0
         self._next = 0
+        self._pool = None
+        if planners > 0:
+            import concurrent.futures
+            self._pool = concurrent.futures.ThreadPoolExecutor(max_workers=planners)
+
+    def close(self) -> None:
+        """Cancel everything still pending and stop the planner threads."""
+        for q in list(self.queue) + list(self.planning) + list(self.live):
+            self.cancel(q.handle)
+        if self._pool is not None:
+            self._pool.shutdown(wait=True)
+            self._pool = None
 
     # ------------------------------------------------------------ client side
     def submit(self, X, windows, ell: float, beta: float, y, tol: float = 1e-6,
@@ -173,11 +191,22 @@ class Server:
         return self.results.get(handle)
 
     def cancel(self, handle: int) -> bool:
-        """Drop a queued or live request (its result says CANCELLED)."""
+        """Drop a queued, planning or live request (its result says CANCELLED)."""
         for q in list(self.queue):
             if q.handle == handle:
                 self.queue.remove(q)
                 self._done(q, "CANCELLED", None, [], "")
+                return True
+        for r in list(self.planning):
+            if r.handle == handle:
+                self.planning.remove(r)
+                try:
+                    state, _ = r.future.result()
+                    self.ex.release(state)
+                except Exception:
+                    pass
+                self._unhold(r)
+                self._done(r, "CANCELLED", None, [], "")
                 return True
         for r in self.live:
             if r.handle == handle:
@@ -188,57 +217,88 @@ class Server:
         return False
 
     def busy(self) -> bool:
-        return bool(self.queue or self.live)
+        return bool(self.queue or self.planning or self.live)
 
     # ------------------------------------------------------------ scheduling
     def _done(self, req: Request, status: str, alpha, info, err: str) -> None:
         self.results[req.handle] = Result(req.handle, status, alpha, info, req.arrival,
                                           req.admitted, self.clock(), err)
 
+    def _hold(self, req: Request, nbytes: int) -> None:
+        self.reserved += nbytes - req.hold
+        req.hold = nbytes
+        self.peak_reserved = max(self.peak_reserved, self.reserved)
+
+    def _unhold(self, req: Request) -> None:
+        self.reserved -= req.hold
+        req.hold = 0
+
     def _release(self, req: Request) -> None:
         if req.state is not None:
             self.ex.release(req.state)
             req.state = None
-        if req.exact_bytes is not None and not math.isnan(req.admitted):
-            self.reserved -= req.exact_bytes
+        self._unhold(req)
+
+    def _place(self, req: Request, state, exact: int) -> None:
+        """A plan is built: reserve its exact footprint and start it, or put
+        the request back at the head of the queue until memory frees up."""
+        req.exact_bytes = int(exact)
+        if req.exact_bytes > self.budget:
+            self.ex.release(state)
+            self._unhold(req)
+            self._done(req, "REJECTED", None, [],
+                       f"needs {req.exact_bytes} bytes, budget {self.budget}")
+            return
+        if req.exact_bytes - req.hold > self.budget - self.reserved:
+            self.ex.release(state)  # plan again once memory frees up
+            self._unhold(req)
+            self.queue.appendleft(req)
+            return
+        self._hold(req, req.exact_bytes)
+        try:
+            self.ex.start(state)
+        except Exception as e:
+            self.ex.release(state)
+            self._unhold(req)
+            self._done(req, "ERROR", None, [], str(e))
+            return
+        req.state = state
+        req.admitted = self.clock()
+        self.live.append(req)
+        self.peak_live = max(self.peak_live, len(self.live))
 
     def _admit(self) -> None:
-        while self.queue and len(self.live) < self.max_live:
+        # plans finished by the planner threads, in submission order
+        for req in sorted(self.planning, key=lambda r: r.handle):
+            if not req.future.done():
+                continue
+            self.planning.remove(req)
+            try:
+                state, exact = req.future.result()
+            except Exception as e:  # invalid for the library, accuracy, memory
+                self._unhold(req)
+                self._done(req, "ERROR", None, [], str(e))
+                continue
+            self._place(req, state, exact)
+        # start plans for waiting requests while the estimate fits
+        while self.queue and len(self.live) + len(self.planning) < self.max_live:
             req = self.queue[0]
-            free = self.budget - self.reserved
             need = req.exact_bytes if req.exact_bytes is not None else req.est_bytes
-            if need > free and self.live:
+            if need > self.budget - self.reserved and (self.live or self.planning):
                 return  # wait for memory; first come, first served
+            self.queue.popleft()
+            self._hold(req, need)
+            if self._pool is not None:
+                req.future = self._pool.submit(self.ex.plan, req)
+                self.planning.append(req)
+                continue
             try:
                 state, exact = self.ex.plan(req)
-            except Exception as e:  # invalid problem for the library, accuracy, memory
-                self.queue.popleft()
-                self._done(req, "ERROR", None, [], str(e))
-                continue
-            req.exact_bytes = int(exact)
-            if req.exact_bytes > self.budget:
-                self.ex.release(state)
-                self.queue.popleft()
-                self._done(req, "REJECTED", None, [],
-                           f"needs {req.exact_bytes} bytes, budget {self.budget}")
-                continue
-            if req.exact_bytes > free:
-                self.ex.release(state)  # plan again once memory frees up
-                return
-            try:
-                self.ex.start(state)
             except Exception as e:
-                self.ex.release(state)
-                self.queue.popleft()
+                self._unhold(req)
                 self._done(req, "ERROR", None, [], str(e))
                 continue
-            self.queue.popleft()
-            req.state = state
-            req.admitted = self.clock()
-            self.reserved += req.exact_bytes
-            self.peak_reserved = max(self.peak_reserved, self.reserved)
-            self.live.append(req)
-            self.peak_live = max(self.peak_live, len(self.live))
+            self._place(req, state, exact)
 
     def step(self) -> None:
         """One round: launch iterations of the live list, admit waiting
@@ -249,7 +309,7 @@ class Server:
         self._admit()
         still = []
         for r in self.live:
-            if self.ex.active(r.state) > 0:
+            if r.state is None or self.ex.active(r.state) > 0:
                 still.append(r)
                 continue
             try:
@@ -259,6 +319,11 @@ class Server:
                 self._done(r, "ERROR", None, [], str(e))
             self._release(r)
         self.live = still
+        if not self.live and self.planning:
+            # nothing to iterate: wait for the oldest plan instead of spinning
+            import concurrent.futures
+            concurrent.futures.wait([r.future for r in self.planning],
+                                    return_when=concurrent.futures.FIRST_COMPLETED)
 
     def run_until_idle(self, max_rounds: int = 1_000_000) -> None:
         for _ in range(max_rounds):
@@ -290,8 +355,9 @@ class Server:
 
 class HipExecutor:
     """Device work of the server through the C ABI: plan, CG state, batched
-    iterations.  All work runs on one stream; planning uploads the points on
-    a second stream so that it overlaps the iterations already launched."""
+    iterations.  Iterations run on one stream; plans are built from the host
+    points (possibly on planner threads, overlapping the iterations already
+    launched)."""
 
     def __init__(self, precision: Optional[int] = None, target_err: float = 1e-4,
                  params: Optional[Dict[str, Any]] = None):
@@ -304,7 +370,6 @@ class HipExecutor:
         self.target_err = target_err
         self.params = dict(params or {})
         self.stream = torch.cuda.Stream()
-        self.plan_stream = torch.cuda.Stream()
 
     def estimate(self, req: Request) -> int:
         return estimate_bytes(req.N, len(req.windows), req.nrhs,
@@ -317,13 +382,11 @@ class HipExecutor:
                               4 if self.precision == self.A.ANOVA_FP32_NFFT else 8)
 
     def plan(self, req: Request):
-        torch, A = self.torch, self.A
-        with torch.cuda.stream(self.plan_stream):
-            Xd = torch.from_numpy(req.X).to("cuda", non_blocking=False)
-            prm = A.make_params(req.ell, self.precision, target_err=self.target_err,
-                                **self.params)
-            plan = A.anova_fastsum_plan(Xd, req.windows, prm, stream=self.plan_stream)
-            del Xd
+        """Build the plan from the host points (any thread); returns
+        (state, exact device bytes)."""
+        A = self.A
+        prm = A.make_params(req.ell, self.precision, target_err=self.target_err, **self.params)
+        plan = A.anova_fastsum_plan_host(req.X, req.windows, prm)
         pb, sb = plan.footprint(req.nrhs)
         io = 2 * req.N * req.nrhs * 8  # y and alpha
         return {"plan": plan, "req": req, "solve": None}, pb + sb + io

@@ -248,3 +248,19 @@ def test_headline_size_sampled_rows(A):
     e = float(np.max(np.abs(out[rows] - ref)) / np.abs(a).sum())
     print(f"N=1e6 auto sampled-row E = {e:.3e}")
     assert e <= 1e-4
+
+
+def test_host_plan_equals_device_plan(A):
+    import torch
+    p = workloads.random_problem(5000, 6, [(0, 1, 2), (3, 4), (5,)], 0.2, seed=33)
+    for prec in (F32, F64):
+        prm = A.make_params(p.ell, prec)
+        pd = A.anova_fastsum_plan(dev_rows(p.X), p.windows, prm)
+        ph = A.anova_fastsum_plan_host(p.X, p.windows, prm)
+        assert pd.footprint(1) == ph.footprint(1)
+        a = dev_cols(p.alpha[:, 0])
+        o1, o2 = torch.empty_like(a), torch.empty_like(a)
+        A.anova_matvec(pd, a, o1, 1.0)
+        A.anova_matvec(ph, a, o2, 1.0)
+        torch.cuda.synchronize()
+        assert torch.equal(o1, o2)

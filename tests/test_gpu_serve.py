@@ -36,13 +36,15 @@ def alone(A, p, precision, tol, maxit):
     return out, info
 
 
-def test_served_requests_equal_alone_bitwise(A):
+@pytest.mark.parametrize("planners", [0, 3])
+def test_served_requests_equal_alone_bitwise(A, planners):
     from paper_2111_10140_amd.serve import HipExecutor, Server
     reqs = workloads.serving_stream(7, rate=1.0, n_lo=500, n_hi=6000, rhs_max=3)
     ex = HipExecutor(F32, target_err=1e-4)
     # a budget that holds about three of these requests: the rest queue
     est = sorted(ex.estimate_problem(r.problem) for r in reqs)
-    srv = Server(ex, budget=int(est[-1] + est[-2] + est[-3]), max_live=4, iters_per_round=3)
+    srv = Server(ex, budget=int(est[-1] + est[-2] + est[-3]), max_live=4, iters_per_round=3,
+                 planners=planners)
     hs = []
     for k, r in enumerate(reqs):
         p = r.problem
@@ -72,6 +74,7 @@ def test_served_requests_equal_alone_bitwise(A):
     assert res <= 1e-4
     st = srv.stats(warmup_fraction=0.0)
     assert st["completed"] == len(reqs) and st["p99_s"] >= st["p50_s"] > 0
+    srv.close()
 
 
 def test_oversized_request_rejected_on_device(A):

@@ -180,3 +180,32 @@ def test_estimate_grows_with_size():
     r = Request(np.zeros((4, 3)), [((0, 1, 2), 1.0)], 0.1, 1.0, np.zeros((4, 2)), 1e-6, 10, 0.0)
     validate(r)
     assert r.nrhs == 2 and r.N == 4
+
+
+class SlowPlanExecutor(FakeExecutor):
+    def plan(self, req):
+        import time
+        time.sleep(0.002 * (1 + req.handle % 3))  # finish out of order
+        return super().plan(req)
+
+
+def test_planner_threads_keep_order_and_budget():
+    ex = SlowPlanExecutor()
+    srv = Server(ex, budget=8_000, max_live=6, iters_per_round=1, planners=3, clock=Clock())
+    hs = [submit(srv, 10 + 7 * (k % 5), need=2 + k % 4) for k in range(15)]
+    while srv.busy():
+        srv.step()
+        assert srv.reserved <= srv.budget
+    assert srv.reserved == 0 and not ex.live_states
+    assert all(srv.result(h).status == "OK" for h in hs)
+    srv.close()
+
+
+def test_close_cancels_pending():
+    ex = SlowPlanExecutor()
+    srv = Server(ex, budget=100_000, planners=2, clock=Clock())
+    hs = [submit(srv, 10, need=50) for _ in range(5)]
+    srv.step()
+    srv.close()
+    assert all(srv.result(h).status == "CANCELLED" for h in hs)
+    assert srv.reserved == 0 and not ex.live_states
