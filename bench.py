@@ -28,6 +28,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# float32 FMA without packed instructions (the library is built without
+# them): 256 CUs x 64 lanes x 2 flop x 2.4 GHz
+VALU_FP32_PEAK_TFLOPS = 78.6
+POLY_DEG_FP32 = 8  # degree of the float32 window polynomials
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "headline_pmc_traffic.txt")
 
 
 def parse():
@@ -49,6 +54,8 @@ def parse():
     ap.add_argument("--serve-n-hi", type=int, default=500_000)
     ap.add_argument("--serve-budget-gb", type=float, default=32.0,
                     help="device memory the live requests may hold together")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run 5 device-to-device copies of 1 GiB (counter calibration)")
     return ap.parse_args()
 
 
@@ -79,6 +86,40 @@ def alg_bytes(stage: str, N: int, G: int, elem: int, P: int = 3) -> float:
     if stage == "convolve":
         return 2.0 * G * elem
     return float(G * elem)  # tile_sum, fold
+
+
+def alg_flops(stage: str, N: int, dA: int, W: int, deg: int = POLY_DEG_FP32) -> float:
+    """Algorithmic flops per window of the float32 spread and gather (an FMA
+    counts 2): per point, the W window weights in each of the d_A
+    dimensions by Horner's rule (deg FMAs each, plus the argument map), and
+    the tensor-product weights: spread multiplies alpha by the weight
+    products (W^(d_A-1) + ... products) and accumulates W^d_A FMAs; gather
+    contracts W^d_A + ... + W FMAs."""
+    horner = 2 * dA * (W * deg + 1)
+    if stage == "spread":
+        prods = sum(W ** k for k in range(1, dA))  # W + W^2 for d_A = 3
+        return N * (horner + prods + 2 * W ** dA)
+    if stage == "gather":
+        return N * (horner + 2 * sum(W ** k for k in range(1, dA + 1)))
+    return 0.0
+
+
+def measured_traffic(kernel_stage: str):
+    """HBM bytes per launch of a stage from the committed counter summary,
+    if it was taken from the current kernel source (else None)."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    src = os.path.join(ROOT, "paper_2111_10140_amd", "csrc", "kernels.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if f"kernel_source_sha256: {digest}" not in text:
+        return None
+    for line in text.splitlines():
+        if line.startswith(f"traffic {kernel_stage}:"):
+            return float(line.split(":")[1].split()[0])
+    return None
 
 
 def time_matvecs(A, torch, plan, a, out, beta, steps, warmup):
@@ -202,6 +243,16 @@ def main():
         sys.exit(2)
     import torch
 
+    if args.copy_probe:
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": a.numel() * 4,
+                          "copy_probe_bytes_written": b.numel() * 4, "copies": 5}))
+        return
+
     import workloads
     from paper_2111_10140_amd import _lib as A
 
@@ -237,10 +288,28 @@ def main():
             b = alg_bytes(k, N, G, 4, P) * (1 if k == "combine" else P)
             per_launch[k] = dict(avg_us=avg_ms * 1e3, launches=cnt, alg_bytes=b,
                                  gbs=b / (avg_ms * 1e-3) / 1e9)
+    W = 2 * infos[0].m
+    for k in ("spread", "gather"):
+        if k in per_launch:
+            f = alg_flops(k, N, infos[0].d_A, W) * P
+            per_launch[k]["alg_flops"] = f
+            per_launch[k]["tflops"] = f / (per_launch[k]["avg_us"] * 1e-6) / 1e12
+            per_launch[k]["hbm_frac"] = per_launch[k]["gbs"] / HBM_PEAK_GBS
     dom = max(per_launch, key=lambda k: per_launch[k]["avg_us"])
-    roof = {"bound": "hbm", "kernel": dom, "achieved": round(per_launch[dom]["gbs"], 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(per_launch[dom]["gbs"] / HBM_PEAK_GBS, 4), "traffic": None}
+    if "tflops" in per_launch[dom]:
+        # spread and gather at these parameters do ~40 flop per algorithmic
+        # byte, above the float32 ridge (78.6 TFLOP/s / 8 TB/s ~ 10): ALU-bound
+        roof = {"bound": "alu", "kernel": dom, "achieved": round(per_launch[dom]["tflops"], 2),
+                "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(per_launch[dom]["tflops"] / VALU_FP32_PEAK_TFLOPS, 4),
+                "traffic": measured_traffic(dom),
+                "alg_bytes": per_launch[dom]["alg_bytes"],
+                "hbm_frac_of_alg_bytes": round(per_launch[dom]["hbm_frac"], 4)}
+    else:
+        roof = {"bound": "hbm", "kernel": dom, "achieved": round(per_launch[dom]["gbs"], 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(per_launch[dom]["gbs"] / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(dom)}
 
     fixed = None
     if not args.skip_fixed:

@@ -123,7 +123,8 @@ struct WindowPlan {
     int64_t n_tiles = 0, n_nonempty = 0, n_sub = 0;
     int poly_deg = 0;
     bool dense = false;          // per-cell register accumulation (see kernels.hip)
-    int chunks = 1;              // dense regime: workgroups per tile
+    int chunks = 1;              // dense regime: most workgroups of one tile
+    std::vector<int32_t> chunk_start;  // dense regime: first workgroup of each non-empty tile
     int64_t n_points = 0;
     int64_t n_regions = 0;       // spread regions per launch (sub-problems, or tiles x chunks)
     // device data

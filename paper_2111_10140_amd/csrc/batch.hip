@@ -192,7 +192,7 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
             return std::make_tuple(w.cell_start != nullptr ? 1 : 0, w.dA, w.width, w.tile, 0, 0);
         },
         [](const WinInst &w, int &b) {
-            b = w.cell_start != nullptr ? w.n_nonempty * w.chunks : w.n_sub;
+            b = w.cell_start != nullptr ? w.n_regions : w.n_sub;
             return true;
         },
         [](BatchGroup &g, const WinInst &w) {
@@ -247,7 +247,7 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
             return std::make_tuple(w.cell_start != nullptr ? 1 : 0, w.dA, w.width, w.tile, 0, 0);
         },
         [](const WinInst &w, int &b) {
-            b = w.cell_start != nullptr ? w.n_nonempty * w.chunks : w.n_sub;
+            b = w.cell_start != nullptr ? w.n_regions : w.n_sub;
             return true;
         },
         [](BatchGroup &g, const WinInst &w) {

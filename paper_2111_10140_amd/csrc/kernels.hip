@@ -250,23 +250,51 @@ __global__ __launch_bounds__(kBlock) void spread_pt_kernel(const WinInst *__rest
 
 // ------------------------------------------------------------------ per-cell kernels
 // With many points per grid cell (float32, small support), points are sorted
-// by cell inside each tile and thread (cell, s) of chunk k handles points
-// q, q + K*S, ... (q = k*S + s) of its cell.  Spreading accumulates the cell's
-// W^d_A support values in registers and adds them to the tile region once
-// per thread; gathering reads the cell's support values from LDS once and
-// interpolates every point of the thread.  Workgroups: non-empty tiles x K.
+// by cell inside each tile; chunk k of K takes a contiguous range of each
+// cell's points and thread (cell, s) of the chunk handles points s, s + S,
+// ... of that range.  Spreading accumulates the cell's W^d_A support values
+// in registers and adds them to the tile region once per thread; gathering
+// reads the cell's support values from LDS once and interpolates every
+// point of the thread.  Workgroups: non-empty tiles x K.
+// Points of chunk k of K of a cell [cs, ce): a contiguous range, so that
+// the lines of the sorted records and values a workgroup touches are
+// consumed by that workgroup over consecutive iterations (neighbouring
+// chunks usually run on other XCDs, whose L2 caches are separate).
+__device__ __forceinline__ void chunk_range(int cs, int ce, int k, int K, int &b, int &e) {
+    const long long cnt = ce - cs;
+    b = cs + (int)(cnt * k / K);
+    e = cs + (int)(cnt * (k + 1) / K);
+}
+
+// Workgroup lb of a per-cell launch: its non-empty tile k (chunk_start =
+// src_sub, ascending), its chunk inside the tile and the tile's chunk count.
+__device__ __forceinline__ void locate_chunk(const int32_t *__restrict__ cstart, int n_ne, int lb,
+                                             int &k, int &chunk, int &K) {
+    int lo = 0, hi = n_ne;  // cstart[lo] <= lb < cstart[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cstart[mid] <= lb) lo = mid; else hi = mid;
+    }
+    k = __builtin_amdgcn_readfirstlane(lo);
+    const int c0 = __builtin_amdgcn_readfirstlane(cstart[k]);
+    K = __builtin_amdgcn_readfirstlane(cstart[k + 1]) - c0;
+    chunk = lb - c0;
+}
+
 template <int DA, int TILE>
 struct CellShape {
     static constexpr int cells = DA == 3 ? TILE * TILE * TILE : (DA == 2 ? TILE * TILE : TILE);
 };
 
-// Sum over the four lanes of a quad (lanes 4c .. 4c+3) with DPP quad
-// permutations; every lane of the quad gets the same bits (each step adds
-// two values in an order-independent way).  All four lanes must be active.
-__device__ __forceinline__ float quad_sum(float v) {
-    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));  // [1,0,3,2]
-    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, false));  // [2,3,0,1]
-    return v;
+// Steps of a sum over the four lanes of a quad (lanes 4c .. 4c+3) with DPP
+// quad permutations: after both steps every lane of the quad holds the same
+// bits (each step adds two values, and float addition is commutative).  All
+// four lanes must be active.
+__device__ __forceinline__ float quad_step1(float v) {  // + lane ^ 1
+    return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float quad_step2(float v) {  // + lane ^ 2
+    return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));
 }
 
 // Spreading per cell.  After the point loop, the S splits of a cell are
@@ -287,18 +315,19 @@ __global__ __launch_bounds__(kBlock) void spread_cell_kernel(const WinInst *__re
     static_assert(S == 1 || S == 4, "splits of a cell are summed within a quad");
     constexpr int WY = DA >= 2 ? W : 1, WZ = DA == 3 ? W : 1;
     constexpr int VW = WZ * WY * W;  // support values of one cell
-    __shared__ float stage[CELLS * VW];
+    __shared__ __align__(16) float stage[CELLS * VW];
     const Located loc = locate(insts, members, prefix, cnt);
     const WinInst &wi = *loc.w;
     const NodeF32 *__restrict__ nodes = static_cast<const NodeF32 *>(wi.nodes);
     const float *__restrict__ as = static_cast<const float *>(wi.tmp);  // sorted coefficients
     WinPoly<float, W> wp;
     wp.load(static_cast<const float *>(wi.poly));
-    const int K = wi.chunks;
-    const int tk = loc.lb / K, chunk = loc.lb % K;
+    int tk, chunk, K;
+    locate_chunk(wi.src_sub, wi.n_nonempty, loc.lb, tk, chunk, K);
     const int key0 = wi.tiles_ne[tk] * CELLS;
     const int cell = threadIdx.x / S, split = (int)(threadIdx.x % S);
-    const int q = chunk * S + split, QS = K * S;
+    int pb, pe;
+    chunk_range(wi.cell_start[key0 + cell], wi.cell_start[key0 + cell + 1], chunk, K, pb, pe);
     float acc[WZ][WY][W];
 #pragma unroll
     for (int c = 0; c < WZ; ++c)
@@ -306,8 +335,8 @@ __global__ __launch_bounds__(kBlock) void spread_cell_kernel(const WinInst *__re
         for (int b = 0; b < WY; ++b)
 #pragma unroll
             for (int i = 0; i < W; ++i) acc[c][b][i] = 0.0f;
-    const int c1 = wi.cell_start[key0 + cell + 1];
-    int j = wi.cell_start[key0 + cell] + q;
+    const int c1 = pe;
+    int j = pb + split;
     // software pipeline: the next point's record and coefficient load while
     // the current one is accumulated
     NodeF32 rec_n{};
@@ -316,12 +345,12 @@ __global__ __launch_bounds__(kBlock) void spread_cell_kernel(const WinInst *__re
         rec_n = nodes[j];
         a_n = as[j];
     }
-    for (; j < c1; j += QS) {
+    for (; j < c1; j += S) {
         const NodeF32 rec = rec_n;
         const float a = a_n;
-        if (j + QS < c1) {
-            rec_n = nodes[j + QS];
-            a_n = as[j + QS];
+        if (j + S < c1) {
+            rec_n = nodes[j + S];
+            a_n = as[j + S];
         }
         float wx[W], wy[W], wz[W];
         wp.eval(rec.f[0], wx);
@@ -338,22 +367,31 @@ __global__ __launch_bounds__(kBlock) void spread_cell_kernel(const WinInst *__re
             }
         }
     }
-    // the cell's total over its S splits, staged as stage[cell][c][b][i];
-    // lane `split` of the quad stores the values with flat index = split mod S
+    // the cell's total over its S splits, staged as stage[cell][c][b][i] by
+    // the first lane of the cell; values go in groups of 8, each DPP step
+    // over the group before the next, so no step waits on the one before
+    float *accf = &acc[0][0][0];
     float *cst = stage + cell * VW;
+    constexpr int G = 8;
 #pragma unroll
-    for (int k = 0; k < VW; k += S) {
-        float v = 0.0f;
+    for (int k0 = 0; k0 < VW; k0 += G) {
+        if constexpr (S == 4) {
 #pragma unroll
-        for (int t = 0; t < S; ++t) {
-            if (k + t < VW) {
-                const int kk = k + t;
-                float x = acc[kk / (WY * W)][(kk / W) % WY][kk % W];
-                if constexpr (S == 4) x = quad_sum(x);
-                if (t == split) v = x;
+            for (int k = k0; k < k0 + G && k < VW; ++k) accf[k] = quad_step1(accf[k]);
+#pragma unroll
+            for (int k = k0; k < k0 + G && k < VW; ++k) accf[k] = quad_step2(accf[k]);
+        }
+        if (split == 0) {
+            if constexpr (VW % 4 == 0) {
+#pragma unroll
+                for (int k = k0; k < k0 + G && k < VW; k += 4)
+                    *reinterpret_cast<float4 *>(cst + k) =
+                        make_float4(accf[k], accf[k + 1], accf[k + 2], accf[k + 3]);
+            } else {
+#pragma unroll
+                for (int k = k0; k < k0 + G && k < VW; ++k) cst[k] = accf[k];
             }
         }
-        if (k + split < VW) cst[k + split] = v;
     }
     __syncthreads();
     // region point (X, Y, Z) gets cell (dx, dy, dz)'s value at offset
@@ -408,9 +446,10 @@ __global__ __launch_bounds__(kBlock) void gather_cell_kernel(const WinInst *__re
     WinPoly<float, W> wp;
     wp.load(static_cast<const float *>(wi.poly));
     float *__restrict__ tmp = static_cast<float *>(wi.tmp);
-    const int K = wi.chunks, n = wi.n, tpd = wi.tpd;
-    const int chunk = loc.lb % K;
-    const int tile_id = wi.tiles_ne[loc.lb / K];
+    const int n = wi.n, tpd = wi.tpd;
+    int tk, chunk, K;
+    locate_chunk(wi.src_sub, wi.n_nonempty, loc.lb, tk, chunk, K);
+    const int tile_id = wi.tiles_ne[tk];
     const int key0 = tile_id * CELLS;
     const int ox = (tile_id % tpd) * TILE;
     const int oy = ((tile_id / tpd) % tpd) * TILE;
@@ -424,11 +463,12 @@ __global__ __launch_bounds__(kBlock) void gather_cell_kernel(const WinInst *__re
     }
     __syncthreads();
     const int cell = threadIdx.x / S;
-    const int q = chunk * S + (int)(threadIdx.x % S), QS = K * S;
+    int pb, pe;
+    chunk_range(wi.cell_start[key0 + cell], wi.cell_start[key0 + cell + 1], chunk, K, pb, pe);
     const int lx = cell % TILE;
     const int ly = DA >= 2 ? (cell / TILE) % TILE : 0;
     const int lz = DA == 3 ? cell / (TILE * TILE) : 0;
-    const int c0 = wi.cell_start[key0 + cell] + q, c1 = wi.cell_start[key0 + cell + 1];
+    const int c0 = pb + (int)(threadIdx.x % S), c1 = pe;
     if (c0 >= c1) return;
     float g[WZ][WY][W];
 #pragma unroll
@@ -437,7 +477,7 @@ __global__ __launch_bounds__(kBlock) void gather_cell_kernel(const WinInst *__re
         for (int b = 0; b < WY; ++b)
 #pragma unroll
             for (int i = 0; i < W; ++i) g[c][b][i] = g_lds[((lz + c) * L + ly + b) * L + lx + i];
-    for (int j = c0; j < c1; j += QS) {
+    for (int j = c0; j < c1; j += S) {
         const NodeF32 rec = nodes[j];
         float wx[W], wy[W], wz[W];
         wp.eval(rec.f[0], wx);

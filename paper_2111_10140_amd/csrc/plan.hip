@@ -431,14 +431,22 @@ void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int p
         for (int64_t t = 0; t < ntiles; ++t)
             if (start[t + 1] > start[t]) ne.push_back((int32_t)t);
         upload(w.tiles_ne, ne);
-        // workgroups per tile: about 12 points per thread (4 threads per
-        // cell in 3-D), and at least ~512 workgroups when the points allow
+        // workgroups (chunks) per tile: a thread handles its cell's share of
+        // one chunk, so a workgroup takes as long as its fullest cell; tiles
+        // at the edge of the data still hold full cells, so every tile gets
+        // the same count: about 12 points per thread of an average occupied
+        // cell (4 threads per cell in 3-D), and at least ~512 workgroups
+        // when the points allow
         const double per_cell = (double)N / (double)std::max<size_t>(nocc, 1);
         const int S = dA == 3 ? 4 : (dA == 2 ? 1 : 4);
         int K = (int)std::lround(per_cell / (12.0 * S));
         K = std::max(K, (int)((512 + ne.size() - 1) / std::max<size_t>(ne.size(), 1)));
         K = std::min(K, std::max(1, (int)(per_cell / S)));
-        w.chunks = std::max(1, std::min(K, 256));
+        K = std::max(1, std::min(K, 256));
+        std::vector<int32_t> cstart(ne.size() + 1);
+        for (size_t k = 0; k <= ne.size(); ++k) cstart[k] = (int32_t)(k * K);
+        w.chunk_start = cstart;
+        w.chunks = K;
     }
     // sub-problems
     const int64_t maxsub = 1024;
@@ -453,7 +461,7 @@ void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int p
     }
     w.n_nonempty = nonempty;
     w.n_sub = (int64_t)subs.size();
-    w.n_regions = w.dense ? w.n_nonempty * w.chunks : w.n_sub;
+    w.n_regions = w.dense ? (int64_t)w.chunk_start.back() : w.n_sub;
     upload(w.nodes, nodes);
     upload(w.perm, perm);
     {
@@ -471,8 +479,8 @@ void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int p
                 src_sub.push_back((int32_t)q);
             }
         src_sub.push_back((int32_t)subs.size());
-        if (w.dense)  // chunk regions of tile k: k*chunks .. (k+1)*chunks - 1
-            for (size_t k = 0; k < src_sub.size(); ++k) src_sub[k] = (int32_t)(k * w.chunks);
+        if (w.dense)  // chunk regions of tile k: chunk_start[k] .. chunk_start[k+1] - 1
+            src_sub = w.chunk_start;
         upload(w.src_sub, src_sub);
         std::vector<int32_t> fstart;
         std::vector<int2> pairs;
