@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--serve-n-hi", type=int, default=500_000)
     ap.add_argument("--serve-budget-gb", type=float, default=32.0,
                     help="device memory the live requests may hold together")
+    ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-large", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run 5 device-to-device copies of 1 GiB (counter calibration)")
     return ap.parse_args()
@@ -193,6 +195,94 @@ def precision_split(A, torch, X, p, a, out, plan32, target):
     d = np.linalg.norm(xs["fp32_nfft"] - xs["fp64_plain"]) / np.linalg.norm(xs["fp64_plain"])
     res["solution_rel_diff"] = float(d)
     res["cg"] = "tol 1e-6 on y of the headline workload, beta=1, x0=0"
+    return res
+
+
+def batched_config(A, torch):
+    """The batched configuration (64 problems, N log-uniform in [5000,
+    200000], windows of 3, 2 and 1 features, 4 right-hand sides, float32
+    products with float64 CG): all problems solved together (one launch per
+    stage and kernel signature per CG iteration, captured in a hipGraph)
+    against the same solves one after another."""
+    import workloads
+    probs = workloads.batched()
+    t = time.perf_counter()
+    plans = [A.anova_fastsum_plan_host(p.X, p.windows, A.make_params(p.ell, A.ANOVA_FP32_NFFT,
+                                                                     target_err=1e-4))
+             for p in probs]
+    plan_s = time.perf_counter() - t
+
+    def cols(a):
+        return torch.from_numpy(np.ascontiguousarray(a.T)).cuda().T
+
+    ys = [cols(p.y) for p in probs]
+    xs = [torch.empty((p.nrhs, p.N), dtype=torch.float64, device="cuda").T for p in probs]
+    A.krr_cg_solve_batched(plans[:2], ys[:2], xs[:2], [1.0, 1.0], 1e-6, 3000)  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    infos = A.krr_cg_solve_batched(plans, ys, xs, [p.beta for p in probs], 1e-6, 3000)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t
+    t = time.perf_counter()
+    for k, p in enumerate(probs):
+        A.krr_cg_solve(plans[k], ys[k], xs[k], p.beta, 1e-6, 3000)
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t
+    ms = [dict(d_A=i.d_A, M=i.M, n=i.n, m=i.m, per_cell=i.per_cell)
+          for i in (plans[0].info(w) for w in range(plans[0].P))]
+    cols_info = [i for inf in infos for i in inf]
+    work = sum(i["iters"] * p.N * len(p.windows) for p, inf in zip(probs, infos) for i in inf)
+    for pl in plans:
+        pl.destroy()
+    return {"workload": "64 problems, N log-uniform in [5000, 200000], d=6 windows {0,1,2},"
+                        "{3,4},{5}, 4 RHS, ell in {0.1,0.2,0.4}, beta=1, tol 1e-6",
+            "sum_N": int(sum(p.N for p in probs)), "plan_seconds": round(plan_s, 3),
+            "solve_seconds_together": round(t_batch, 4),
+            "solve_seconds_one_by_one": round(t_seq, 4),
+            "speedup_together": round(t_seq / t_batch, 3),
+            "solves_per_s_together": round(len(probs) / t_batch, 2),
+            "point_window_products_per_s": work / t_batch,
+            "all_converged": all(i["converged"] for i in cols_info),
+            "max_true_relres": max(i["true_relres"] for i in cols_info),
+            "max_iters": max(i["iters"] for i in cols_info),
+            "first_problem_params": ms}
+
+
+def large_config(A, torch):
+    """The large configuration (N = 2e6, mixture in R^15, five windows of
+    three features, ell = 0.15, beta = 0.5) at M = 64, m = 6, n = 128:
+    float32 products (float64 CG and residuals) against the plain float64
+    path on the same GPU: matvecs/s and a CG solve to 1e-6."""
+    import workloads
+    p = workloads.large()
+    X = torch.from_numpy(p.X).cuda()
+    a = torch.from_numpy(np.ascontiguousarray(p.alpha[:, 0])).cuda()
+    y = torch.from_numpy(np.ascontiguousarray(p.y[:, 0])).cuda()
+    out = torch.empty_like(a)
+    res, xs = {}, {}
+    for name, prec in (("fp32_nfft", A.ANOVA_FP32_NFFT), ("fp64_plain", A.ANOVA_FP64)):
+        t = time.perf_counter()
+        plan = A.anova_fastsum_plan(X, p.windows, A.make_params(p.ell, prec, M=64, m=6, n=128))
+        torch.cuda.synchronize()
+        plan_s = time.perf_counter() - t
+        ms = time_matvecs(A, torch, plan, a, out, p.beta, 10, 2)
+        x = torch.empty_like(y)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        info = A.krr_cg_solve(plan, y, x, p.beta, 1e-6, 3000, allow_not_converged=True)
+        torch.cuda.synchronize()
+        xs[name] = x.cpu().numpy()
+        res[name] = {"matvecs_per_s": round(1e3 / ms, 2), "plan_seconds": round(plan_s, 3),
+                     "err_estimate": plan.err_estimate(), "cg_iters": info[0]["iters"],
+                     "cg_true_relres": info[0]["true_relres"],
+                     "cg_seconds": round(time.perf_counter() - t, 3),
+                     "per_cell": plan.info(0).per_cell}
+        plan.destroy()
+        print(f"# large {name}: {json.dumps(res[name])}", file=sys.stderr, flush=True)
+    res["solution_rel_diff"] = float(np.linalg.norm(xs["fp32_nfft"] - xs["fp64_plain"]) /
+                                     np.linalg.norm(xs["fp64_plain"]))
+    res["workload"] = ("N=2e6 mixture in R^15, 5 windows of 3 features, ell=0.15, beta=0.5, "
+                       "M=64 m=6 n=128, CG tol 1e-6")
     return res
 
 
@@ -353,6 +443,11 @@ def main():
     if not args.skip_fixed:
         split = precision_split(A, torch, X, p, a, out, plan, args.target)
         print(f"# precision split: {json.dumps(split)}", file=sys.stderr, flush=True)
+    batched = None
+    if not args.skip_batched:
+        batched = batched_config(A, torch)
+        print(f"# batched: {json.dumps(batched)}", file=sys.stderr, flush=True)
+    large = None if args.skip_large else large_config(A, torch)
     served = None if args.skip_serve else serving(args, A)
 
     res = {
@@ -371,6 +466,8 @@ def main():
                                   for kk, vv in v.items()} for k, v in per_launch.items()},
         "fixed_params": fixed,
         "precision_split": split,
+        "batched": batched,
+        "large": large,
         "serving": served,
         "cpu_baseline": cpu,
     }
