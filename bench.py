@@ -439,6 +439,20 @@ def main():
     else:
         err = None
 
+    # the measured parameter choice on the same points
+    t0 = time.perf_counter()
+    plan_t = A.anova_fastsum_plan(X, p.windows, A.make_params(p.ell, A.ANOVA_FP32_NFFT,
+                                                              target_err=args.target, tune=1))
+    torch.cuda.synchronize()
+    tuned = {"plan_seconds": round(time.perf_counter() - t0, 3),
+             "params": [dict(M=i.M, n=i.n, m=i.m, per_cell=i.per_cell)
+                        for i in (plan_t.info(l) for l in range(plan_t.P))],
+             "err_estimate": plan_t.err_estimate()}
+    tuned["matvecs_per_s"] = round(1e3 / time_matvecs(A, torch, plan_t, a, out, p.beta,
+                                                      args.steps, args.warmup), 2)
+    plan_t.destroy()
+    print(f"# measured parameter choice: {json.dumps(tuned)}", file=sys.stderr, flush=True)
+
     split = None
     if not args.skip_fixed:
         split = precision_split(A, torch, X, p, a, out, plan, args.target)
@@ -465,6 +479,7 @@ def main():
         "stages_per_launch": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
                                   for kk, vv in v.items()} for k, v in per_launch.items()},
         "fixed_params": fixed,
+        "tuned": tuned,
         "precision_split": split,
         "batched": batched,
         "large": large,

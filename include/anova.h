@@ -87,6 +87,13 @@ typedef struct {
                             scaling by 1/h; 1: scale only, x~ = x/h (Sec. 4.2) */
     int32_t residual;    /* anova_residual: how CG recomputes its residual
                             on a FP32_NFFT plan (ignored for FP64 plans) */
+    int32_t tune;        /* 0: choose (M, m, n) by the cost model;
+                            1: measured: build the cheapest candidates that
+                            meet target_err (model cost within 8x, at most 4
+                            per window) on these points and keep the one
+                            whose product runs fastest on this device (the
+                            plan then launches kernels and takes several
+                            times longer) */
 } anova_params;
 
 /* Residual product of CG on FP32_NFFT plans.  The float32 product's rounding
@@ -140,7 +147,8 @@ typedef struct {
  * Errors: ANOVA_E_INVALID for out == NULL, X == NULL, N < 1, N > 2^31-1,
  * d < 1, ldx < d, P < 1, P > 64, d_A not in {1,2,3}, a feature index out of
  * range or repeated inside one window, a non-finite eta or X, ell <= 0,
- * odd M, n not a power of two or n < M, m out of range, residual not an anova_residual.
+ * odd M, n not a power of two or n < M, m out of range, residual not an anova_residual,
+ * tune not 0 or 1.
  * ANOVA_E_ACCURACY when fixed parameters miss target_err.
  */
 anova_status anova_fastsum_plan(anova_plan_t *out, const double *X, int64_t N, int32_t d,

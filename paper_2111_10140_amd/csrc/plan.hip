@@ -223,9 +223,14 @@ struct Choice {
     double h;
     int M, n, m;
     double e_img, e_trunc, e_win, e_round;
+    double cost;  // model cost: N (2m)^dA + 4 n^dA log2(n) dA
 };
 
-Choice choose(const anova_params &prm, double D, int dA, double budget, int64_t N) {
+// Every (n, M, m) meeting the error budget, one per FFT length n (the
+// smallest M, then the smallest m), cheapest model cost first.  Fixed
+// parameters give one candidate.
+std::vector<Choice> candidates(const anova_params &prm, double D, int dA, double budget,
+                               int64_t N) {
     Choice c{};
     const int prec = prm.precision;
     // period
@@ -237,12 +242,17 @@ Choice choose(const anova_params &prm, double D, int dA, double budget, int64_t 
         if (c.h <= 0) c.h = 1.0;
     }
     c.e_img = est_images(c.h, D, prm.ell, dA);
+    auto model_cost = [&](int n, int m) {
+        return (double)N * std::pow(2.0 * m, dA) +
+               4.0 * std::pow((double)n, dA) * std::log2((double)n) * dA;
+    };
+    std::vector<Choice> out;
     const bool fixed = prm.M > 0 && prm.m > 0 && prm.n > 0;
     if (fixed) {
         c.M = prm.M; c.n = prm.n; c.m = prm.m;
+        c.cost = model_cost(c.n, c.m);
+        out.push_back(c);
     } else {
-        // search: cheapest (n, M, m) meeting the budget; unspecified fields free
-        double best = std::numeric_limits<double>::infinity();
         const double rest = std::max(budget - c.e_img, budget * 0.5);
         for (int n = 8; n <= 256; n *= 2) {
             if (prm.n > 0 && n != prm.n) continue;
@@ -262,23 +272,25 @@ Choice choose(const anova_params &prm, double D, int dA, double budget, int64_t 
                 if (2 * m > n) break;
                 const double ew = est_window(M, n, m, prm.ell, c.h, dA);
                 if (ew > 0.65 * avail) continue;
-                double cost = (double)N * std::pow(2.0 * m, dA) +
-                              4.0 * std::pow((double)n, dA) * std::log2((double)n) * dA;
-                if (cost < best) {
-                    best = cost;
-                    c.M = M; c.n = n; c.m = m;
-                }
+                Choice k = c;
+                k.M = M; k.n = n; k.m = m;
+                k.cost = model_cost(n, m);
+                out.push_back(k);
                 break;
             }
         }
-        if (!std::isfinite(best))
+        if (out.empty())
             throw Error{ANOVA_E_ACCURACY,
                         "no (M, n, m) with n <= 256 and m <= 8 meets target_err for this window"};
+        std::stable_sort(out.begin(), out.end(),
+                         [](const Choice &x, const Choice &y) { return x.cost < y.cost; });
     }
-    c.e_trunc = est_trunc(c.M, c.h, prm.ell, dA);
-    c.e_win = est_window(c.M, c.n, c.m, prm.ell, c.h, dA);
-    c.e_round = est_round(prec, c.n, c.m, dA);
-    return c;
+    for (Choice &k : out) {
+        k.e_trunc = est_trunc(k.M, k.h, prm.ell, dA);
+        k.e_win = est_window(k.M, k.n, k.m, prm.ell, k.h, dA);
+        k.e_round = est_round(prec, k.n, k.m, dA);
+    }
+    return out;
 }
 
 
@@ -550,6 +562,7 @@ void validate(const double *X, int64_t N, int32_t d, int64_t ldx, const anova_wi
     ANOVA_REQUIRE(prm->center == 0 || prm->center == 1, "center must be 0 or 1");
     ANOVA_REQUIRE(prm->residual == ANOVA_RESIDUAL_FP64 || prm->residual == ANOVA_RESIDUAL_SAME,
                   "residual must be ANOVA_RESIDUAL_FP64 or ANOVA_RESIDUAL_SAME");
+    ANOVA_REQUIRE(prm->tune == 0 || prm->tune == 1, "tune must be 0 or 1");
     for (int l = 0; l < P; ++l) {
         const anova_window &w = win[l];
         ANOVA_REQUIRE(w.d_A >= 1 && w.d_A <= 3, "window d_A must be 1, 2 or 3");
@@ -631,6 +644,69 @@ size_t anova::plan_device_bytes(const anova_plan_s *p) {
     return b;
 }
 
+// Parameters and error estimates of one choice into a window.
+static void apply_choice(WindowPlan &w, const Choice &c, const anova_params &prm) {
+    w.h = c.h; w.M = c.M; w.n = c.n; w.m = c.m;
+    w.kb_b = kPi * w.m * (2.0 - (double)w.M / w.n);
+    const double ae = std::fabs(w.eta);
+    w.err_images = ae * c.e_img;
+    w.err_trunc = ae * c.e_trunc;
+    w.err_window = ae * c.e_win;
+    w.err_round = ae * c.e_round;
+    w.err_total = w.err_images + w.err_trunc + w.err_window + w.err_round;
+    w.ell = prm.ell;
+}
+
+static void build_for(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int prec) {
+    if (prec == ANOVA_FP64)
+        build_window<double, NodeF64>(w, Xh, N, ldx, prec);
+    else
+        build_window<float, NodeF32>(w, Xh, N, ldx, prec);
+}
+
+// Device time of one product of a one-window plan (the best of 3 after a
+// warm-up), on a stream of its own.
+static double time_window(anova_plan_s &one, const double *alpha, double *out) {
+    hipStream_t s = nullptr;
+    ANOVA_HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    float best = std::numeric_limits<float>::infinity();
+    try {
+        Batch b;
+        BatchProblem bp;
+        bp.plan = &one;
+        bp.alpha = alpha;
+        bp.out = out;
+        bp.nrhs = 1;
+        bp.ld = one.N;
+        bp.beta = 1.0;
+        b.build({bp});
+        ANOVA_HIP_CHECK(hipEventCreate(&e0));
+        ANOVA_HIP_CHECK(hipEventCreate(&e1));
+        b.run(s);
+        for (int r = 0; r < 3; ++r) {
+            ANOVA_HIP_CHECK(hipEventRecord(e0, s));
+            b.run(s);
+            ANOVA_HIP_CHECK(hipEventRecord(e1, s));
+            ANOVA_HIP_CHECK(hipEventSynchronize(e1));
+            float ms = 0.0f;
+            ANOVA_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+            best = std::min(best, ms);
+        }
+        ANOVA_HIP_CHECK(hipStreamSynchronize(s));
+    } catch (...) {
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        (void)hipStreamSynchronize(s);
+        (void)hipStreamDestroy(s);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(s);
+    return best;
+}
+
 // Plan from validated arguments and host points Xh (rows ldx apart).
 static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, int32_t d,
                               int64_t ldx, const anova_window *win, int32_t P,
@@ -650,6 +726,7 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
         const double target = prm->target_err > 0 ? prm->target_err
                               : (prm->precision == ANOVA_FP64 ? 1e-9 : 1e-4);
         const double budget = target / eta_abs;
+        DevBuf tune_alpha, tune_out;  // measured choice: a vector of ones and its product
         for (int l = 0; l < P; ++l) {
             WindowPlan &w = p->win[l];
             w.dA = win[l].d_A;
@@ -667,21 +744,40 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
                 D = std::max(D, hi - lo);
             }
             w.extent = D;
-            const Choice c = choose(*prm, D, w.dA, budget, N);
-            ANOVA_REQUIRE(c.h > D || (D == 0 && c.h > 0), "h must exceed the extent of the points");
-            w.h = c.h; w.M = c.M; w.n = c.n; w.m = c.m;
-            w.kb_b = kPi * w.m * (2.0 - (double)w.M / w.n);
-            const double ae = std::fabs(w.eta);
-            w.err_images = ae * c.e_img;
-            w.err_trunc = ae * c.e_trunc;
-            w.err_window = ae * c.e_win;
-            w.err_round = ae * c.e_round;
-            w.err_total = w.err_images + w.err_trunc + w.err_window + w.err_round;
-            w.ell = prm->ell;
-            if (prm->precision == ANOVA_FP64)
-                build_window<double, NodeF64>(w, Xh, N, ldx, prm->precision);
-            else
-                build_window<float, NodeF32>(w, Xh, N, ldx, prm->precision);
+            const std::vector<Choice> cands = candidates(*prm, D, w.dA, budget, N);
+            for (const Choice &c : cands)
+                ANOVA_REQUIRE(c.h > D || (D == 0 && c.h > 0),
+                              "h must exceed the extent of the points");
+            if (prm->tune == 0 || cands.size() == 1) {
+                apply_choice(w, cands.front(), *prm);
+                build_for(w, Xh, N, ldx, prm->precision);
+                continue;
+            }
+            // measured choice: build the cheapest candidates (model cost
+            // within 8x of the cheapest, at most 4) on these points and keep
+            // the one whose product runs fastest
+            if (!tune_alpha.ptr) {
+                upload(tune_alpha, std::vector<double>((size_t)N, 1.0));
+                tune_out.alloc((size_t)N * sizeof(double));
+            }
+            double best_t = std::numeric_limits<double>::infinity();
+            for (size_t k = 0; k < cands.size() && k < 4; ++k) {
+                if (cands[k].cost > 8.0 * cands.front().cost) break;
+                anova_plan_s one;
+                one.N = N; one.d = d; one.P = 1; one.precision = prm->precision;
+                one.ell = prm->ell; one.device = p->device;
+                one.win.resize(1);
+                WindowPlan &v = one.win[0];
+                v.dA = w.dA; v.eta = w.eta; v.extent = w.extent;
+                for (int t = 0; t < 3; ++t) { v.feat[t] = w.feat[t]; v.center[t] = w.center[t]; }
+                apply_choice(v, cands[k], *prm);
+                build_for(v, Xh, N, ldx, prm->precision);
+                const double t = time_window(one, tune_alpha.as<double>(), tune_out.as<double>());
+                if (t < best_t) {
+                    best_t = t;
+                    w = std::move(v);
+                }
+            }
         }
         if (prm->precision == ANOVA_FP32_NFFT && prm->residual == ANOVA_RESIDUAL_FP64) {
             // the same windows and parameters in float64, for CG's residuals

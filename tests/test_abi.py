@@ -55,7 +55,7 @@ def test_invalid_arguments_return_status(lib):
 
 
 @pytest.mark.parametrize("field,value,needle", [
-    ("ell", 0.0, "ell"), ("M", 7, "M"), ("n", 48, "n"), ("m", 9, "m"), ("residual", 2, "residual"),
+    ("ell", 0.0, "ell"), ("M", 7, "M"), ("n", 48, "n"), ("m", 9, "m"), ("residual", 2, "residual"), ("tune", 3, "tune"),
     ("precision", 5, "precision"), ("center", 2, "center"),
 ])
 def test_invalid_params_rejected_before_device_work(lib, field, value, needle):

@@ -264,3 +264,25 @@ def test_host_plan_equals_device_plan(A):
         A.anova_matvec(ph, a, o2, 1.0)
         torch.cuda.synchronize()
         assert torch.equal(o1, o2)
+
+
+@pytest.mark.parametrize("precision", [F32, F64])
+def test_measured_parameter_choice(A, precision):
+    # tune=1 builds several candidate (M, n, m) per window on the points and
+    # keeps the fastest; whatever it keeps must meet the same accuracy
+    import torch
+    p = workloads.random_problem(60000, 9, [(0, 1, 2), (3, 4, 5), (6, 7), (8,)], 0.2, seed=35)
+    target = 1e-4 if precision == F32 else 1e-8
+    plan = A.anova_fastsum_plan(dev_rows(p.X), p.windows,
+                                A.make_params(p.ell, precision, target_err=target, tune=1))
+    print([(plan.info(l).M, plan.info(l).n, plan.info(l).m, plan.info(l).per_cell)
+           for l in range(plan.P)])
+    assert plan.err_estimate() <= target
+    a = dev_cols(p.alpha[:, 0])
+    out = torch.empty_like(a)
+    A.anova_matvec(plan, a, out, p.beta)
+    torch.cuda.synchronize()
+    rows = np.random.default_rng(5).choice(p.N, 300, replace=False)
+    ref = oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, p.alpha[:, 0], rows=rows)
+    E = float(np.max(np.abs(to_np(out)[rows] - ref)) / np.abs(p.alpha[:, 0]).sum())
+    assert E <= plan.err_estimate() and E <= target
