@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--serve-budget-gb", type=float, default=32.0,
                     help="device memory the live requests may hold together")
     ap.add_argument("--skip-batched", action="store_true")
+    ap.add_argument("--skip-tuned", action="store_true")
     ap.add_argument("--skip-large", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run 5 device-to-device copies of 1 GiB (counter calibration)")
@@ -440,18 +441,20 @@ def main():
         err = None
 
     # the measured parameter choice on the same points
-    t0 = time.perf_counter()
-    plan_t = A.anova_fastsum_plan(X, p.windows, A.make_params(p.ell, A.ANOVA_FP32_NFFT,
-                                                              target_err=args.target, tune=1))
-    torch.cuda.synchronize()
-    tuned = {"plan_seconds": round(time.perf_counter() - t0, 3),
-             "params": [dict(M=i.M, n=i.n, m=i.m, per_cell=i.per_cell)
-                        for i in (plan_t.info(l) for l in range(plan_t.P))],
-             "err_estimate": plan_t.err_estimate()}
-    tuned["matvecs_per_s"] = round(1e3 / time_matvecs(A, torch, plan_t, a, out, p.beta,
-                                                      args.steps, args.warmup), 2)
-    plan_t.destroy()
-    print(f"# measured parameter choice: {json.dumps(tuned)}", file=sys.stderr, flush=True)
+    tuned = None
+    if not args.skip_tuned:
+        t0 = time.perf_counter()
+        plan_t = A.anova_fastsum_plan(X, p.windows, A.make_params(p.ell, A.ANOVA_FP32_NFFT,
+                                                                  target_err=args.target, tune=1))
+        torch.cuda.synchronize()
+        tuned = {"plan_seconds": round(time.perf_counter() - t0, 3),
+                 "params": [dict(M=i.M, n=i.n, m=i.m, per_cell=i.per_cell)
+                            for i in (plan_t.info(l) for l in range(plan_t.P))],
+                 "err_estimate": plan_t.err_estimate()}
+        tuned["matvecs_per_s"] = round(1e3 / time_matvecs(A, torch, plan_t, a, out, p.beta,
+                                                          args.steps, args.warmup), 2)
+        plan_t.destroy()
+        print(f"# measured parameter choice: {json.dumps(tuned)}", file=sys.stderr, flush=True)
 
     split = None
     if not args.skip_fixed:

@@ -301,6 +301,8 @@ int cell_tile(int dA);
 int cell_threads_per_cell(int dA);
 bool cell_width_supported(int dA, int W);
 int combine_span();
+int permute_span();
+int fold_tiles_per_block(int tile, int dA);
 int block_threads();
 
 // plan helpers (plan.hip)

@@ -181,7 +181,7 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
     add_stage(
         kStagePermute, [](const WinInst &) { return std::make_tuple(0, 0, 0, 0, 0, 0); },
         [](const WinInst &w, int &b) {
-            b = (w.N + 4 * block_threads() - 1) / (4 * block_threads());
+            b = (w.N + permute_span() - 1) / permute_span();
             return true;
         },
         [](BatchGroup &, const WinInst &) {});
@@ -214,7 +214,8 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
     add_stage(
         kStageFold, [](const WinInst &w) { return std::make_tuple(w.dA, 0, 0, 0, 0, 0); },
         [](const WinInst &w, int &b) {
-            b = w.n_tiles;
+            const int tpb = fold_tiles_per_block(w.tile, w.dA);
+            b = (w.n_tiles + tpb - 1) / tpb;
             return true;
         },
         [](BatchGroup &g, const WinInst &w) { g.dA = w.dA; });

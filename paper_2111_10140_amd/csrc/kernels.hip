@@ -477,8 +477,11 @@ __global__ __launch_bounds__(kBlock) void gather_cell_kernel(const WinInst *__re
         for (int b = 0; b < WY; ++b)
 #pragma unroll
             for (int i = 0; i < W; ++i) g[c][b][i] = g_lds[((lz + c) * L + ly + b) * L + lx + i];
+    // the next point's record loads while the current one is interpolated
+    NodeF32 rec_n = nodes[c0];
     for (int j = c0; j < c1; j += S) {
-        const NodeF32 rec = nodes[j];
+        const NodeF32 rec = rec_n;
+        if (j + S < c1) rec_n = nodes[j + S];
         float wx[W], wy[W], wz[W];
         wp.eval(rec.f[0], wx);
         if constexpr (DA >= 2) wp.eval(rec.f[1], wy);
@@ -581,6 +584,12 @@ __global__ __launch_bounds__(kBlock) void gather_pt_kernel(const WinInst *__rest
 // The window's coefficients in its sorted point order, as[j] = alpha[perm[j]],
 // written to the instance's value buffer (the gather overwrites it later).
 // Blocks: ceil(N / (4 kBlock)) per instance.
+// Elements per thread of the permutation and combine kernels: their loads
+// land at random positions, so each thread first issues all its index loads,
+// then all its gathers, keeping several misses in flight.
+constexpr int kPermutePerThread = 8;
+constexpr int kPermuteSpan = kPermutePerThread * kBlock;
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void permute_kernel(const WinInst *__restrict__ insts,
                                                          const int32_t *__restrict__ members,
@@ -591,8 +600,21 @@ __global__ __launch_bounds__(kBlock) void permute_kernel(const WinInst *__restri
     const int32_t *__restrict__ perm = wi.perm;
     const double *__restrict__ alpha = wi.alpha;
     T *__restrict__ as = static_cast<T *>(wi.tmp);
-    const int j0 = loc.lb * 4 * kBlock, j1 = min(wi.N, j0 + 4 * kBlock);
-    for (int j = j0 + threadIdx.x; j < j1; j += kBlock) as[j] = static_cast<T>(alpha[perm[j]]);
+    const int j0 = loc.lb * kPermuteSpan + threadIdx.x;
+    int idx[kPermutePerThread];
+    double v[kPermutePerThread];
+#pragma unroll
+    for (int e = 0; e < kPermutePerThread; ++e) {
+        const int j = j0 + e * kBlock;
+        idx[e] = j < wi.N ? perm[j] : -1;
+    }
+#pragma unroll
+    for (int e = 0; e < kPermutePerThread; ++e) v[e] = idx[e] >= 0 ? alpha[idx[e]] : 0.0;
+#pragma unroll
+    for (int e = 0; e < kPermutePerThread; ++e) {
+        const int j = j0 + e * kBlock;
+        if (j < wi.N) as[j] = static_cast<T>(v[e]);
+    }
 }
 
 // ------------------------------------------------------------------ tile sum
@@ -639,15 +661,21 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
     const int n = wi.n, tile = wi.tile, tpd = wi.tpd, vol = wi.vol;
     const int L = tile + wi.width - 1;
     const int L2 = DA >= 2 ? L * L : L;
-    const int d = loc.lb;
-    const int ox = (d % tpd) * tile;
-    const int oy = ((d / tpd) % tpd) * tile;
-    const int oz = (d / (tpd * tpd)) * tile;
     int cells = tile;
     if (DA >= 2) cells *= tile;
     if (DA == 3) cells *= tile;
+    // small tiles: several per workgroup (one thread per cell)
+    const int tpb = cells >= kBlock ? 1 : kBlock / cells;
+    const int sub = cells >= kBlock ? 0 : (int)threadIdx.x / cells;
+    const int d = loc.lb * tpb + sub;
+    if (sub >= tpb || d >= wi.n_tiles) return;
+    const int ox = (d % tpd) * tile;
+    const int oy = ((d / tpd) % tpd) * tile;
+    const int oz = (d / (tpd * tpd)) * tile;
     const int p0 = wi.fold_start[d], p1 = wi.fold_start[d + 1];
-    for (int c = threadIdx.x; c < cells; c += kBlock) {
+    const int c0 = cells >= kBlock ? (int)threadIdx.x : (int)threadIdx.x % cells;
+    const int cstep = cells >= kBlock ? kBlock : cells;
+    for (int c = c0; c < cells; c += cstep) {
         const int cx = c % tile;
         const int cy = DA >= 2 ? (c / tile) % tile : 0;
         const int cz = DA == 3 ? c / (tile * tile) : 0;
@@ -770,24 +798,43 @@ __global__ __launch_bounds__(kBlock) void convolve_kernel(const WinInst *__restr
 // order (accumulate: out_i += the sum instead).  tmp_l holds window l's
 // interpolated values in its sorted point order; iperm_l maps the caller's
 // point index to that order.  Blocks: ceil(N / kCombineSpan) per instance.
-constexpr int kCombineSpan = kBlock;
+constexpr int kCombinePerThread = 4;
+constexpr int kCombineSpan = kCombinePerThread * kBlock;
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void combine_kernel(const CombInst *__restrict__ cis,
                                                          const CombineWin *__restrict__ wins,
                                                          const int32_t *__restrict__ prefix,
                                                          int cnt) {
+    constexpr int E = kCombinePerThread;
     const int q = __builtin_amdgcn_readfirstlane(find_member(prefix, cnt, blockIdx.x));
     const CombInst ci = cis[q];
-    const int i0 = (blockIdx.x - prefix[q]) * kCombineSpan;
-    const int i1 = min(ci.N, i0 + kCombineSpan);
-    for (int i = i0 + threadIdx.x; i < i1; i += kBlock) {
-        double s = ci.accumulate ? ci.out[i] : ci.beta * ci.alpha[i];
-        for (int l = 0; l < ci.P; ++l) {
-            const CombineWin cw = wins[ci.win0 + l];
-            s += cw.eta * (double)static_cast<const T *>(cw.tmp)[cw.iperm[i]];
+    const int i0 = (blockIdx.x - prefix[q]) * kCombineSpan + threadIdx.x;
+    double s[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = i0 + e * kBlock;
+        s[e] = i < ci.N ? (ci.accumulate ? ci.out[i] : ci.beta * ci.alpha[i]) : 0.0;
+    }
+    for (int l = 0; l < ci.P; ++l) {
+        const CombineWin cw = wins[ci.win0 + l];
+        const T *__restrict__ tmp = static_cast<const T *>(cw.tmp);
+        int idx[E];
+        T v[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const int i = i0 + e * kBlock;
+            idx[e] = i < ci.N ? cw.iperm[i] : -1;
         }
-        ci.out[i] = s;
+#pragma unroll
+        for (int e = 0; e < E; ++e) v[e] = idx[e] >= 0 ? tmp[idx[e]] : T(0);
+#pragma unroll
+        for (int e = 0; e < E; ++e) s[e] += cw.eta * (double)v[e];
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = i0 + e * kBlock;
+        if (i < ci.N) ci.out[i] = s[e];
     }
 }
 
@@ -931,6 +978,12 @@ int cell_threads_per_cell(int dA) {
 }
 bool cell_width_supported(int dA, int W) { return dA == 3 ? W <= 6 : (dA == 2 ? W <= 8 : W <= 16); }
 int combine_span() { return kCombineSpan; }
+int permute_span() { return kPermuteSpan; }
+int fold_tiles_per_block(int tile, int dA) {
+    int cells = tile;
+    for (int t = 1; t < dA; ++t) cells *= tile;
+    return cells >= kBlock ? 1 : kBlock / cells;
+}
 int block_threads() { return kBlock; }
 
 void run_group(const BatchGroup &g, int precision, const WinInst *insts, hipStream_t s) {

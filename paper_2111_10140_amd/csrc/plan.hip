@@ -223,60 +223,102 @@ struct Choice {
     double h;
     int M, n, m;
     double e_img, e_trunc, e_win, e_round;
-    double cost;  // model cost: N (2m)^dA + 4 n^dA log2(n) dA
+    double cost;     // model cost (see candidates)
+    int align = 0;   // > 0: tile edge the data is aligned to (per-cell kernels)
 };
 
 // Every (n, M, m) meeting the error budget, one per FFT length n (the
 // smallest M, then the smallest m), cheapest model cost first.  Fixed
 // parameters give one candidate.
+//
+// Model cost: N (2m)^dA + 4 n^dA log2(n) dA.  For float32 windows that
+// will run the per-cell kernels (support width supported and several points
+// per cell) there is also an aligned variant: a wave of those kernels covers
+// a slab of cells and runs as long as its fullest cell, so points that end
+// inside a tile leave lanes idle; the variant raises h so that the points
+// span a whole number of tiles (one tile fewer) with M and m chosen again
+// for that h, and puts the data's lower edge on a tile boundary (centre
+// chosen in make_plan).  It has the same or a higher model cost (the model
+// does not see lane efficiency, and fewer points per cell raise the
+// per-thread overheads), so only the measured choice (tune) takes it when
+// it runs faster.
 std::vector<Choice> candidates(const anova_params &prm, double D, int dA, double budget,
                                int64_t N) {
-    Choice c{};
     const int prec = prm.precision;
-    // period
+    double h0;
     if (prm.h > 0) {
-        c.h = prm.h;
+        h0 = prm.h;
     } else {
         const double r = std::max(budget * 0.1, 1e-300);
-        c.h = std::max(2.0 * D, D + prm.ell * std::sqrt(std::log(std::max(2.0 * dA / r, 1.0001))));
-        if (c.h <= 0) c.h = 1.0;
+        h0 = std::max(2.0 * D, D + prm.ell * std::sqrt(std::log(std::max(2.0 * dA / r, 1.0001))));
+        if (h0 <= 0) h0 = 1.0;
     }
-    c.e_img = est_images(c.h, D, prm.ell, dA);
-    auto model_cost = [&](int n, int m) {
-        return (double)N * std::pow(2.0 * m, dA) +
-               4.0 * std::pow((double)n, dA) * std::log2((double)n) * dA;
+    // the smallest (M, m) at FFT length n and period h, if any
+    auto search = [&](double h, int n, Choice &c) -> bool {
+        c = Choice{};
+        c.h = h;
+        c.n = n;
+        c.e_img = est_images(h, D, prm.ell, dA);
+        const double rest = std::max(budget - c.e_img, budget * 0.5);
+        const double avail = rest - est_round(prec, n, 8, dA);
+        if (avail <= 0) return false;
+        int M = prm.M;
+        if (M <= 0) {
+            for (M = 4; M <= n; M += 2)
+                if (est_trunc(M, h, prm.ell, dA) <= 0.35 * avail) break;
+            if (M > n) return false;
+        }
+        if (M > n) return false;
+        if (prm.M <= 0 && M * 5 > n * 4) return false;  // keep sigma = n/M >= 1.25
+        for (int m = 2; m <= 8; ++m) {
+            if (prm.m > 0 && m != prm.m) continue;
+            if (2 * m > n) break;
+            if (est_window(M, n, m, prm.ell, h, dA) > 0.65 * avail) continue;
+            c.M = M;
+            c.m = m;
+            return true;
+        }
+        return false;
+    };
+    const int T = cell_tile(dA);
+    auto per_cell_likely = [&](const Choice &c, double span) {
+        return prec == ANOVA_FP32_NFFT && c.n >= 2 * T && cell_width_supported(dA, 2 * c.m) &&
+               (double)N >= 3.0 * std::pow(std::max(span, 1.0), dA);
+    };
+    auto cost = [&](const Choice &c, double eff) {
+        return (double)N * std::pow(2.0 * c.m, dA) / eff +
+               4.0 * std::pow((double)c.n, dA) * std::log2((double)c.n) * dA;
     };
     std::vector<Choice> out;
     const bool fixed = prm.M > 0 && prm.m > 0 && prm.n > 0;
     if (fixed) {
-        c.M = prm.M; c.n = prm.n; c.m = prm.m;
-        c.cost = model_cost(c.n, c.m);
+        Choice c{};
+        c.h = h0; c.M = prm.M; c.n = prm.n; c.m = prm.m;
+        c.e_img = est_images(h0, D, prm.ell, dA);
+        c.cost = cost(c, 1.0);
         out.push_back(c);
     } else {
-        const double rest = std::max(budget - c.e_img, budget * 0.5);
         for (int n = 8; n <= 256; n *= 2) {
             if (prm.n > 0 && n != prm.n) continue;
-            const double er = est_round(prec, n, 8, dA);
-            const double avail = rest - er;
-            if (avail <= 0) continue;
-            int M = prm.M;
-            if (M <= 0) {
-                for (M = 4; M <= n; M += 2)
-                    if (est_trunc(M, c.h, prm.ell, dA) <= 0.35 * avail) break;
-                if (M > n) continue;
+            Choice c;
+            if (!search(h0, n, c)) continue;
+            const double span = n * D / h0;  // cells the points cover per dimension
+            if (!per_cell_likely(c, span) || D <= 0) {
+                c.cost = cost(c, 1.0);
+                out.push_back(c);
+                continue;
             }
-            if (M > n) continue;
-            if (prm.M <= 0 && M * 5 > n * 4) continue;  // keep sigma = n/M >= 1.25
-            for (int m = 2; m <= 8; ++m) {
-                if (prm.m > 0 && m != prm.m) continue;
-                if (2 * m > n) break;
-                const double ew = est_window(M, n, m, prm.ell, c.h, dA);
-                if (ew > 0.65 * avail) continue;
-                Choice k = c;
-                k.M = M; k.n = n; k.m = m;
-                k.cost = model_cost(n, m);
-                out.push_back(k);
-                break;
+            const int k1 = std::max(1, (int)std::ceil(span / T - 1e-9));
+            c.cost = cost(c, 1.0);
+            out.push_back(c);
+            if (k1 >= 2 && prm.h <= 0 && prm.center == 0) {
+                Choice a;
+                const double h1 = n * D / ((k1 - 1) * T * (1.0 - 4e-5));
+                if (search(h1, n, a) && per_cell_likely(a, n * D / h1)) {
+                    a.align = T;
+                    a.cost = cost(a, 1.0) * (1.0 + 1e-9);  // ties go to the plain variant
+                    out.push_back(a);
+                }
             }
         }
         if (out.empty())
@@ -644,6 +686,27 @@ size_t anova::plan_device_bytes(const anova_plan_s *p) {
     return b;
 }
 
+// Centre of each dimension: the bounding-box centre, or (aligned choices)
+// the point that puts the lowest coordinate just above a tile boundary, so
+// that the points fill whole tiles of the per-cell kernels; with
+// center = 1 the plain scaling x/h.
+static void set_centers(WindowPlan &w, const Choice &c, const double *lo, const double *hi,
+                        const anova_params &prm) {
+    for (int t = 0; t < w.dA; ++t) {
+        if (prm.center == 1) {
+            w.center[t] = 0.0;
+        } else if (c.align > 0) {
+            const double T = c.align, n = c.n;
+            const double span = n * (hi[t] - lo[t]) / c.h;
+            const double k0 = std::floor((0.5 * n - 0.5 * span) / T);
+            // t(lo) = n (lo - centre) / h + n/2 = T k0 + 1e-5 T
+            w.center[t] = lo[t] - (T * k0 + 1e-5 * T - 0.5 * n) * c.h / n;
+        } else {
+            w.center[t] = 0.5 * (lo[t] + hi[t]);
+        }
+    }
+}
+
 // Parameters and error estimates of one choice into a window.
 static void apply_choice(WindowPlan &w, const Choice &c, const anova_params &prm) {
     w.h = c.h; w.M = c.M; w.n = c.n; w.m = c.m;
@@ -731,17 +794,16 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
             WindowPlan &w = p->win[l];
             w.dA = win[l].d_A;
             w.eta = win[l].eta;
-            double D = 0.0;
+            double D = 0.0, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
             for (int t = 0; t < w.dA; ++t) {
                 w.feat[t] = win[l].feat[t];
-                double lo = Xh[w.feat[t]], hi = lo;
+                lo[t] = hi[t] = Xh[w.feat[t]];
                 for (int64_t i = 1; i < N; ++i) {
                     const double v = Xh[(size_t)i * ldx + w.feat[t]];
-                    lo = std::min(lo, v);
-                    hi = std::max(hi, v);
+                    lo[t] = std::min(lo[t], v);
+                    hi[t] = std::max(hi[t], v);
                 }
-                w.center[t] = prm->center == 1 ? 0.0 : 0.5 * (lo + hi);
-                D = std::max(D, hi - lo);
+                D = std::max(D, hi[t] - lo[t]);
             }
             w.extent = D;
             const std::vector<Choice> cands = candidates(*prm, D, w.dA, budget, N);
@@ -749,6 +811,7 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
                 ANOVA_REQUIRE(c.h > D || (D == 0 && c.h > 0),
                               "h must exceed the extent of the points");
             if (prm->tune == 0 || cands.size() == 1) {
+                set_centers(w, cands.front(), lo, hi, *prm);
                 apply_choice(w, cands.front(), *prm);
                 build_for(w, Xh, N, ldx, prm->precision);
                 continue;
@@ -769,7 +832,8 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
                 one.win.resize(1);
                 WindowPlan &v = one.win[0];
                 v.dA = w.dA; v.eta = w.eta; v.extent = w.extent;
-                for (int t = 0; t < 3; ++t) { v.feat[t] = w.feat[t]; v.center[t] = w.center[t]; }
+                for (int t = 0; t < 3; ++t) v.feat[t] = w.feat[t];
+                set_centers(v, cands[k], lo, hi, *prm);
                 apply_choice(v, cands[k], *prm);
                 build_for(v, Xh, N, ldx, prm->precision);
                 const double t = time_window(one, tune_alpha.as<double>(), tune_out.as<double>());
