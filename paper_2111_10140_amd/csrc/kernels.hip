@@ -115,10 +115,9 @@ struct WinPoly {
     }
 };
 
-__device__ __forceinline__ int wrap_index(int g, int n) {
-    g %= n;
-    return g < 0 ? g + n : g;
-}
+// Periodic index on a grid of n points: n is a power of two (the plan
+// requires it), so the two's-complement mask also wraps negative g.
+__device__ __forceinline__ int wrap_index(int g, int n) { return g & (n - 1); }
 
 // ------------------------------------------------------------------ fixed point
 // LDS float atomics are slow on this chip while 64-bit integer LDS atomics
@@ -680,16 +679,38 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
         const int cy = DA >= 2 ? (c / tile) % tile : 0;
         const int cz = DA == 3 ? c / (tile * tile) : 0;
         double s = 0.0;
-        for (int p = p0; p < p1; ++p) {
-            const int2 pr = wi.fold_pairs[p];
-            const T *reg = src + (size_t)pr.x * vol;
-            const int bx = pr.y & 1023, by = (pr.y >> 10) & 1023, bz = (pr.y >> 20) & 1023;
-            const int ex0 = (bx + cx) % n;
-            const int ey0 = DA >= 2 ? (by + cy) % n : 0;
-            const int ez0 = DA == 3 ? (bz + cz) % n : 0;
-            for (int ez = ez0; ez < (DA == 3 ? L : 1); ez += n)
-                for (int ey = ey0; ey < (DA >= 2 ? L : 1); ey += n)
-                    for (int ex = ex0; ex < L; ex += n) s += (double)reg[ez * L2 + ey * L + ex];
+        if (L <= n) {
+            // each region element lands on one grid point: at most one read
+            // per region; four regions' reads in flight, added in order
+            for (int p = p0; p < p1; p += 4) {
+                T v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    v[u] = T(0);
+                    if (p + u < p1) {
+                        const int2 pr = wi.fold_pairs[p + u];
+                        const int ex = (((pr.y & 1023) + cx) & (n - 1));
+                        const int ey = DA >= 2 ? ((((pr.y >> 10) & 1023) + cy) & (n - 1)) : 0;
+                        const int ez = DA == 3 ? ((((pr.y >> 20) & 1023) + cz) & (n - 1)) : 0;
+                        if (ex < L && ey < L && ez < L)
+                            v[u] = src[(size_t)pr.x * vol + ez * L2 + ey * L + ex];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) s += (double)v[u];
+            }
+        } else {
+            for (int p = p0; p < p1; ++p) {
+                const int2 pr = wi.fold_pairs[p];
+                const T *reg = src + (size_t)pr.x * vol;
+                const int bx = pr.y & 1023, by = (pr.y >> 10) & 1023, bz = (pr.y >> 20) & 1023;
+                const int ex0 = (bx + cx) & (n - 1);
+                const int ey0 = DA >= 2 ? (by + cy) & (n - 1) : 0;
+                const int ez0 = DA == 3 ? (bz + cz) & (n - 1) : 0;
+                for (int ez = ez0; ez < (DA == 3 ? L : 1); ez += n)
+                    for (int ey = ey0; ey < (DA >= 2 ? L : 1); ey += n)
+                        for (int ex = ex0; ex < L; ex += n) s += (double)reg[ez * L2 + ey * L + ex];
+            }
         }
         size_t g = (size_t)(ox + cx);
         if (DA >= 2) g += (size_t)n * (size_t)(oy + cy);
@@ -721,12 +742,12 @@ __global__ __launch_bounds__(kBlock) void convolve_kernel(const WinInst *__restr
     const C *__restrict__ tw = static_cast<const C *>(wi.twiddle);
     int nlines = 1;
     for (int t = 1; t < wi.dA; ++t) nlines *= n;
-    int s = 1;
-    for (int t = 0; t < axis; ++t) s *= n;
+    const int ls = LOGN * axis;  // stride s = n^axis = 2^ls
+    const int s = 1 << ls;
     const int q0 = loc.lb * NP;
     const bool contiguous = (s == 1);
     auto base_of = [&](int r) -> size_t {
-        const size_t hi = (size_t)(r / s), lo = (size_t)(r % s);
+        const size_t hi = (size_t)(r >> ls), lo = (size_t)(r & (s - 1));
         return hi * (size_t)s * n + lo;
     };
     for (int e = threadIdx.x; e < NP * n; e += kBlock) {
