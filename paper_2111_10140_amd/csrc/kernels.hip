@@ -115,6 +115,12 @@ struct WinPoly {
     }
 };
 
+// The three fractional offsets of a float32 node record (its packed cell
+// word is not needed by the per-cell kernels).
+__device__ __forceinline__ float3 node_offsets(const NodeF32 *__restrict__ p) {
+    return *reinterpret_cast<const float3 *>(p);
+}
+
 // Periodic index on a grid of n points: n is a power of two (the plan
 // requires it), so the two's-complement mask also wraps negative g.
 __device__ __forceinline__ int wrap_index(int g, int n) { return g & (n - 1); }
@@ -336,25 +342,25 @@ __global__ __launch_bounds__(kBlock) void spread_cell_kernel(const WinInst *__re
             for (int i = 0; i < W; ++i) acc[c][b][i] = 0.0f;
     const int c1 = pe;
     int j = pb + split;
-    // software pipeline: the next point's record and coefficient load while
+    // software pipeline: the next point's offsets and coefficient load while
     // the current one is accumulated
-    NodeF32 rec_n{};
+    float3 r_n{};
     float a_n = 0.0f;
     if (j < c1) {
-        rec_n = nodes[j];
+        r_n = node_offsets(nodes + j);
         a_n = as[j];
     }
     for (; j < c1; j += S) {
-        const NodeF32 rec = rec_n;
+        const float3 r = r_n;
         const float a = a_n;
         if (j + S < c1) {
-            rec_n = nodes[j + S];
+            r_n = node_offsets(nodes + j + S);
             a_n = as[j + S];
         }
         float wx[W], wy[W], wz[W];
-        wp.eval(rec.f[0], wx);
-        if constexpr (DA >= 2) wp.eval(rec.f[1], wy);
-        if constexpr (DA == 3) wp.eval(rec.f[2], wz);
+        wp.eval(r.x, wx);
+        if constexpr (DA >= 2) wp.eval(r.y, wy);
+        if constexpr (DA == 3) wp.eval(r.z, wz);
 #pragma unroll
         for (int c = 0; c < WZ; ++c) {
             const float wc = DA == 3 ? a * wz[c] : a;
@@ -476,15 +482,15 @@ __global__ __launch_bounds__(kBlock) void gather_cell_kernel(const WinInst *__re
         for (int b = 0; b < WY; ++b)
 #pragma unroll
             for (int i = 0; i < W; ++i) g[c][b][i] = g_lds[((lz + c) * L + ly + b) * L + lx + i];
-    // the next point's record loads while the current one is interpolated
-    NodeF32 rec_n = nodes[c0];
+    // the next point's offsets load while the current one is interpolated
+    float3 r_n = node_offsets(nodes + c0);
     for (int j = c0; j < c1; j += S) {
-        const NodeF32 rec = rec_n;
-        if (j + S < c1) rec_n = nodes[j + S];
+        const float3 r = r_n;
+        if (j + S < c1) r_n = node_offsets(nodes + j + S);
         float wx[W], wy[W], wz[W];
-        wp.eval(rec.f[0], wx);
-        if constexpr (DA >= 2) wp.eval(rec.f[1], wy);
-        if constexpr (DA == 3) wp.eval(rec.f[2], wz);
+        wp.eval(r.x, wx);
+        if constexpr (DA >= 2) wp.eval(r.y, wy);
+        if constexpr (DA == 3) wp.eval(r.z, wz);
         float acc = 0.0f;
 #pragma unroll
         for (int c = 0; c < WZ; ++c) {
