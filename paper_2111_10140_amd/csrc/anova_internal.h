@@ -125,6 +125,7 @@ struct WindowPlan {
     bool dense = false;          // per-cell register accumulation (see kernels.hip)
     int chunks = 1;              // dense regime: most workgroups of one tile
     std::vector<int32_t> chunk_start;  // dense regime: first workgroup of each non-empty tile
+    std::vector<int32_t> tile_order;   // dense regime: non-empty tiles in launch order
     int64_t n_points = 0;
     int64_t n_regions = 0;       // spread regions per launch (sub-problems, or tiles x chunks)
     // device data

@@ -484,6 +484,20 @@ void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int p
         std::vector<int32_t> ne;
         for (int64_t t = 0; t < ntiles; ++t)
             if (start[t + 1] > start[t]) ne.push_back((int32_t)t);
+        // heaviest tiles first (by their fullest cell, which sets a
+        // workgroup's duration), so that the last workgroups to start are
+        // short ones and the launch's tail stays small; ties by tile id
+        {
+            std::vector<int64_t> heavy(ntiles, 0);
+            for (int32_t t : ne)
+                for (int64_t c = 0; c < cells_per_tile; ++c) {
+                    const int64_t k = (int64_t)t * cells_per_tile + c;
+                    heavy[t] = std::max(heavy[t], kstart[k + 1] - kstart[k]);
+                }
+            std::stable_sort(ne.begin(), ne.end(),
+                             [&](int32_t a, int32_t b) { return heavy[a] > heavy[b]; });
+        }
+        w.tile_order = ne;
         upload(w.tiles_ne, ne);
         // workgroups (chunks) per tile: a thread handles its cell's share of
         // one chunk, so a workgroup takes as long as its fullest cell; tiles
@@ -533,8 +547,10 @@ void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int p
                 src_sub.push_back((int32_t)q);
             }
         src_sub.push_back((int32_t)subs.size());
-        if (w.dense)  // chunk regions of tile k: chunk_start[k] .. chunk_start[k+1] - 1
+        if (w.dense) {  // chunk regions of tile k: chunk_start[k] .. chunk_start[k+1] - 1
             src_sub = w.chunk_start;
+            src_tiles = w.tile_order;  // k-th non-empty tile in launch order
+        }
         upload(w.src_sub, src_sub);
         std::vector<int32_t> fstart;
         std::vector<int2> pairs;
