@@ -72,20 +72,19 @@ def alg_bytes(stage: str, N: int, G: int, elem: int, P: int = 3) -> float:
     tile_sum, fold : one write of each grid value (the tile regions they read
               are traffic of this implementation, not of the method);
     convolve (one axis pass): one read and one write of the grid;
-    gather  : node record + one value written per point, one read of each
-              grid value;
+    gather  : node record, the permutation index 4 B and one value written
+              (in the caller's order) per point, one read of each grid value;
     combine (all windows): alpha read and output write 16 B per point, plus
-              the inverse permutation and the window's value per point and
-              window."""
+              each window's value per point."""
     node = 16 if elem == 4 else 32
     if stage == "permute":
         return N * (4 + 8 + elem)
     if stage == "spread":
         return N * (node + elem) + G * elem
     if stage == "gather":
-        return N * (node + elem) + G * elem
+        return N * (node + 4 + elem) + G * elem
     if stage == "combine":
-        return N * (16 + P * (4 + elem))
+        return N * (16 + P * elem)
     if stage == "convolve":
         return 2.0 * G * elem
     return float(G * elem)  # tile_sum, fold

@@ -303,8 +303,8 @@ anova_status anova_stage_gather(anova_plan_t plan, int32_t l, const void *grid, 
  * (regions of one tile added, where a tile holds several), 3 fold (tile
  * regions added into the grid with periodic wrap), 4 convolve (FFT, multiply,
  * inverse FFT; one launch per axis), 5 gather (interpolation at the points,
- * sorted order), 6 combine (weighted sum over windows plus the shift, in the
- * caller's order).  anova_plan_stage_times synchronises, writes the
+ * written in the caller's order), 6 combine (weighted sum over windows plus
+ * the shift).  anova_plan_stage_times synchronises, writes the
  * accumulated milliseconds and launch counts per kind (host arrays of 7) and
  * resets the counters.  Enabling adds a few microseconds of
  * event overhead per launch; disabled by default.

@@ -96,8 +96,7 @@ struct alignas(16) SubProblem {
 
 // Per-window operand of the combine kernel (device array, one per window).
 struct CombineWin {
-    const void *tmp;         // window's interpolated values, sorted order (float/double)
-    const int32_t *iperm;    // caller's point index -> sorted position
+    const void *tmp;         // window's interpolated values, caller's order (float/double)
     double eta;
 };
 
@@ -131,7 +130,6 @@ struct WindowPlan {
     // device data
     DevBuf nodes;    // NodeF32 or NodeF64, sorted by tile (N entries)
     DevBuf perm;     // int32: sorted position -> caller's point index
-    DevBuf iperm;    // int32: caller's point index -> sorted position
     DevBuf subs;     // SubProblem[n_sub]
     DevBuf poly;     // window polynomial table [2m][poly_deg+1] (float or double)
     DevBuf bconv;    // per-axis multiplier, n entries (float or double)

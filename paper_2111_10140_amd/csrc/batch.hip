@@ -133,7 +133,7 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
                 wi.dA = w.dA;
                 wi.width = 2 * w.m;
                 insts.push_back(wi);
-                cwins.push_back(CombineWin{nullptr, w.iperm.as<int32_t>(), w.eta});
+                cwins.push_back(CombineWin{nullptr, w.eta});
                 ++nw;
             }
             ci.P = nw;

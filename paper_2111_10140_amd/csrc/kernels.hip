@@ -504,7 +504,7 @@ __global__ __launch_bounds__(kBlock) void gather_cell_kernel(const WinInst *__re
             }
             acc = DA == 3 ? fmaf(sc, wz[c], acc) : sc;
         }
-        tmp[j] = acc;
+        tmp[wi.perm[j]] = acc;  // caller order
     }
 }
 
@@ -581,7 +581,7 @@ __global__ __launch_bounds__(kBlock) void gather_pt_kernel(const WinInst *__rest
                 }
             }
         }
-        tmp[j] = acc;
+        tmp[wi.perm[j]] = acc;  // caller order
     }
 }
 
@@ -821,10 +821,12 @@ __global__ __launch_bounds__(kBlock) void convolve_kernel(const WinInst *__restr
 }
 
 // ------------------------------------------------------------------ combine
-// out_i = beta alpha_i + sum_l eta_l tmp_l[iperm_l[i]] in float64, windows in
-// order (accumulate: out_i += the sum instead).  tmp_l holds window l's
-// interpolated values in its sorted point order; iperm_l maps the caller's
-// point index to that order.  Blocks: ceil(N / kCombineSpan) per instance.
+// out_i = beta alpha_i + sum_l eta_l tmp_l[i] in float64, windows in order
+// (accumulate: out_i += the sum instead).  tmp_l holds window l's
+// interpolated values in the caller's point order (the gather kernels write
+// them there: scattered writes, which the caches merge, cost less than the
+// line-sized random reads of reading them back through the inverse
+// permutation).  Blocks: ceil(N / kCombineSpan) per instance.
 constexpr int kCombinePerThread = 4;
 constexpr int kCombineSpan = kCombinePerThread * kBlock;
 
@@ -846,15 +848,12 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(const CombInst *__restr
     for (int l = 0; l < ci.P; ++l) {
         const CombineWin cw = wins[ci.win0 + l];
         const T *__restrict__ tmp = static_cast<const T *>(cw.tmp);
-        int idx[E];
         T v[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int i = i0 + e * kBlock;
-            idx[e] = i < ci.N ? cw.iperm[i] : -1;
+            v[e] = i < ci.N ? tmp[i] : T(0);
         }
-#pragma unroll
-        for (int e = 0; e < E; ++e) v[e] = idx[e] >= 0 ? tmp[idx[e]] : T(0);
 #pragma unroll
         for (int e = 0; e < E; ++e) s[e] += cw.eta * (double)v[e];
     }

@@ -532,11 +532,6 @@ void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int p
     w.n_regions = w.dense ? (int64_t)w.chunk_start.back() : w.n_sub;
     upload(w.nodes, nodes);
     upload(w.perm, perm);
-    {
-        std::vector<int32_t> iperm(N);
-        for (int64_t j = 0; j < N; ++j) iperm[perm[j]] = (int32_t)j;
-        upload(w.iperm, iperm);
-    }
     upload(w.subs, subs);
     // per non-empty tile: its sub-problems, and the fold lists over tiles
     {
@@ -694,7 +689,7 @@ size_t anova::plan_device_bytes(const anova_plan_s *p) {
     size_t b = 0;
     for (const std::vector<WindowPlan> *ws : {&p->win, &p->win64})
       for (const WindowPlan &w : *ws)
-        for (const DevBuf *d : {&w.nodes, &w.perm, &w.iperm, &w.subs, &w.poly, &w.bconv, &w.twiddle,
+        for (const DevBuf *d : {&w.nodes, &w.perm, &w.subs, &w.poly, &w.bconv, &w.twiddle,
                                 &w.src_sub, &w.cell_start, &w.tiles_ne, &w.fold_pairs,
                                 &w.fold_start})
             b += d->bytes;
