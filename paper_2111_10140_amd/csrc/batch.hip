@@ -177,10 +177,12 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
             pending[it->second].blocks.push_back(b);
         }
     };
-    // permute: coefficients into each window's sorted order
+    // permute: coefficients into each window's sorted order (per-point
+    // kernels only: the per-cell spread reads them through the permutation)
     add_stage(
         kStagePermute, [](const WinInst &) { return std::make_tuple(0, 0, 0, 0, 0, 0); },
         [](const WinInst &w, int &b) {
+            if (w.cell_start != nullptr) return false;
             b = (w.N + permute_span() - 1) / permute_span();
             return true;
         },

@@ -113,6 +113,13 @@ struct WinPoly {
             for (int a = 0; a < W; ++a) w[a] = w[a] * z + c[a][k];
         }
     }
+    // weight of offset a alone, at the mapped argument z = 2f - 1
+    __device__ __forceinline__ T eval_one(T z, int a) const {
+        T v = c[a][D];
+#pragma unroll
+        for (int k = D - 1; k >= 0; --k) v = v * z + c[a][k];
+        return v;
+    }
 };
 
 // The three fractional offsets of a float32 node record (its packed cell
@@ -324,7 +331,6 @@ __global__ __launch_bounds__(kBlock) void spread_cell_kernel(const WinInst *__re
     const Located loc = locate(insts, members, prefix, cnt);
     const WinInst &wi = *loc.w;
     const NodeF32 *__restrict__ nodes = static_cast<const NodeF32 *>(wi.nodes);
-    const float *__restrict__ as = static_cast<const float *>(wi.tmp);  // sorted coefficients
     WinPoly<float, W> wp;
     wp.load(static_cast<const float *>(wi.poly));
     int tk, chunk, K;
@@ -342,28 +348,36 @@ __global__ __launch_bounds__(kBlock) void spread_cell_kernel(const WinInst *__re
             for (int i = 0; i < W; ++i) acc[c][b][i] = 0.0f;
     const int c1 = pe;
     int j = pb + split;
-    // software pipeline: the next point's offsets and coefficient load while
-    // the current one is accumulated
+    // software pipeline: the next point's offsets and coefficient (read in
+    // the caller's order through the permutation, whose index loads one
+    // point earlier still) load while the current one is accumulated, so
+    // the scattered coefficient reads overlap the arithmetic
+    const int32_t *__restrict__ perm = wi.perm;
+    const double *__restrict__ alpha = wi.alpha;
     float3 r_n{};
     float a_n = 0.0f;
+    int p_n = 0;
     if (j < c1) {
         r_n = node_offsets(nodes + j);
-        a_n = as[j];
+        a_n = (float)alpha[perm[j]];
     }
+    if (j + S < c1) p_n = perm[j + S];
     for (; j < c1; j += S) {
         const float3 r = r_n;
         const float a = a_n;
         if (j + S < c1) {
             r_n = node_offsets(nodes + j + S);
-            a_n = as[j + S];
+            a_n = (float)alpha[p_n];
         }
-        float wx[W], wy[W], wz[W];
+        if (j + 2 * S < c1) p_n = perm[j + 2 * S];
+        // z weights plane by plane: fewer live registers
+        float wx[W], wy[W];
         wp.eval(r.x, wx);
         if constexpr (DA >= 2) wp.eval(r.y, wy);
-        if constexpr (DA == 3) wp.eval(r.z, wz);
+        const float zz = 2.0f * r.z - 1.0f;
 #pragma unroll
         for (int c = 0; c < WZ; ++c) {
-            const float wc = DA == 3 ? a * wz[c] : a;
+            const float wc = DA == 3 ? a * wp.eval_one(zz, c) : a;
 #pragma unroll
             for (int b = 0; b < WY; ++b) {
                 const float wbc = DA >= 2 ? wc * wy[b] : wc;
