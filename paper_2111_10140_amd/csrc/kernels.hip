@@ -1005,10 +1005,11 @@ void convolve_group(const BatchGroup &g, const WinInst *insts, hipStream_t s) {
 }  // namespace
 
 int convolve_lines_per_block(int n, int nq) {
-    // enough butterflies per stage to occupy the block, but at least ~256
-    // workgroups when the grid has that many line pairs
+    // enough butterflies per stage to occupy the block, but at least ~64
+    // workgroups per grid when it has that many line pairs (the launches
+    // cover every window, so several grids share them)
     const int per_block = std::max(1, 512 / n);
-    return std::max(1, std::min(per_block, (nq + 255) / 256));
+    return std::max(1, std::min(per_block, (nq + 63) / 64));
 }
 int cell_tile(int dA) { return dA == 3 ? 4 : (dA == 2 ? 16 : 64); }
 int cell_threads_per_cell(int dA) {
