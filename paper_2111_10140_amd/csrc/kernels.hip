@@ -137,22 +137,24 @@ __device__ __forceinline__ int wrap_index(int g, int n) { return g & (n - 1); }
 // run at full rate, and integer sums are exact: a contribution v is rounded
 // to an integer at the workgroup's scale 2^S, chosen from the largest |alpha|
 // of its points so that no contribution exceeds 2^30 (float32 path, rounding
-// 2^-31 of max|alpha|) or 2^52 (float64 path) in magnitude; the int64 sum of
+// 2^-31 of max|alpha|) or 2^50 (float64 path, rounding 2^-51) in magnitude
+// (window weights are at most 1); the int64 sum of
 // at most 1024 such terms (a sub-problem's points, or the register sums of a
 // tile's threads, each already scaled below 2^30) cannot overflow, and it
 // does not depend on the order of the additions.
 __device__ __forceinline__ long long round_to_ll(float x) {  // |x| < 2^31
     return (long long)__float2int_rn(x);
 }
-__device__ __forceinline__ long long round_to_ll(double x) {  // |x| < 2^62
-    x = rint(x);
-    const double hi = floor(x * 0x1p-32);  // exact: |hi| < 2^30
-    const double lo = x - hi * 0x1p32;     // exact, in [0, 2^32)
-    return (long long)((unsigned long long)(long long)(int)hi << 32) + (long long)(unsigned)lo;
+__device__ __forceinline__ long long round_to_ll(double x) {  // |x| < 2^51
+    // x + 1.5 * 2^52 lies in (2^52, 2^53), where the spacing of doubles is 1:
+    // the addition rounds x to the nearest integer (ties to even) and the
+    // low mantissa bits then hold it, offset by those of 1.5 * 2^52
+    const double t = x + 0x1.8p52;
+    return __double_as_longlong(t) - __double_as_longlong(0x1.8p52);
 }
 template <typename T> struct FixedBits;
 template <> struct FixedBits<float> { static constexpr int value = 30; };
-template <> struct FixedBits<double> { static constexpr int value = 52; };
+template <> struct FixedBits<double> { static constexpr int value = 50; };
 
 __device__ __forceinline__ float block_max(float v, float *sh) {
     for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));

@@ -161,7 +161,11 @@ double est_window(int M, int n, int m, double ell, double h, int dA) {
 
 double est_round(int precision, int n, int m, int dA) {
     const double eps = precision == ANOVA_FP64 ? 1.1e-16 : 6.0e-8;
-    return eps * 8.0 * (dA * std::log2((double)n) + 2.0 * m);
+    // plus the fixed-point spreading: each of the (2m)^dA contributions of a
+    // point is rounded at 2^-51 (float64) or 2^-31 (float32) of the largest
+    // |alpha| of its workgroup, at most ||alpha||_1
+    const double fix = std::pow(2.0 * m, dA) * (precision == ANOVA_FP64 ? 0x1p-51 : 0x1p-31);
+    return eps * 8.0 * (dA * std::log2((double)n) + 2.0 * m) + fix;
 }
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
