@@ -84,3 +84,34 @@ def test_invalid_windows_rejected(lib, wins, needle):
                                 ctypes.byref(prm), None)
     assert st == _lib.ANOVA_E_INVALID
     assert needle in _lib.anova_last_error()
+
+
+def test_newer_entry_points_validate_before_device_work(lib):
+    from paper_2111_10140_amd import _lib
+    i64 = ctypes.c_int64
+    h = ctypes.c_void_p()
+    wins = _lib.make_windows([((0, 1, 2), 1.0)])
+    prm = _lib.make_params(0.2)
+    # host-memory plan: NULL points, bad sizes
+    assert lib.anova_fastsum_plan_host(ctypes.byref(h), None, 10, 3, 3, wins, 1,
+                                       ctypes.byref(prm)) == _lib.ANOVA_E_INVALID
+    X = (ctypes.c_double * 30)()
+    assert lib.anova_fastsum_plan_host(ctypes.byref(h), X, 10, 3, 2, wins, 1,
+                                       ctypes.byref(prm)) == _lib.ANOVA_E_INVALID  # ldx < d
+    assert lib.anova_fastsum_plan_host(None, X, 10, 3, 3, wins, 1,
+                                       ctypes.byref(prm)) == _lib.ANOVA_E_INVALID
+    # footprint of no plan, solve handles without a plan or list
+    a, b = i64(), i64()
+    assert lib.anova_plan_footprint(None, 1, ctypes.byref(a), ctypes.byref(b)) == _lib.ANOVA_E_INVALID
+    sv = ctypes.c_void_p()
+    assert lib.krr_cg_start(ctypes.byref(sv), None, None, None, 1, 10, 1.0, 1e-6, 10,
+                            None) == _lib.ANOVA_E_INVALID
+    assert lib.krr_cg_start(None, None, None, None, 1, 10, 1.0, 1e-6, 10,
+                            None) == _lib.ANOVA_E_INVALID
+    assert lib.krr_cg_iterate(None, 0, 1, None) == _lib.ANOVA_E_INVALID
+    assert lib.krr_cg_poll(None, None, None, None) == _lib.ANOVA_E_INVALID
+    assert lib.krr_cg_finish(None, None, None) == _lib.ANOVA_E_INVALID
+    assert lib.krr_cg_destroy(None) == _lib.ANOVA_OK  # NULL is a no-op
+    assert lib.krr_cg_solve_batched(0, None, None, None, None, None, None, 1e-6, 10, None,
+                                    None) == _lib.ANOVA_E_INVALID
+    assert lib.anova_plan_destroy(None) == _lib.ANOVA_OK
