@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--serve-n-hi", type=int, default=500_000)
     ap.add_argument("--serve-budget-gb", type=float, default=32.0,
                     help="device memory the live requests may hold together")
+    ap.add_argument("--serve-round", type=int, default=4,
+                    help="CG iterations per scheduling round of the serving loop")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-tuned", action="store_true")
     ap.add_argument("--skip-large", action="store_true")
@@ -147,10 +149,10 @@ def stage_profile(A, torch, plan, a, out, beta, steps):
     return t
 
 
-def serve_stream(Server, ex, reqs, arrivals, budget, max_live):
+def serve_stream(Server, ex, reqs, arrivals, budget, max_live, round_iters=4):
     """Feed requests to a server at the given arrival offsets (seconds) in
     real time; returns the server once every request is done."""
-    srv = Server(ex, budget=budget, max_live=max_live, iters_per_round=4, planners=4)
+    srv = Server(ex, budget=budget, max_live=max_live, iters_per_round=round_iters, planners=4)
     order = sorted(range(len(reqs)), key=lambda k: arrivals[k])
     t0 = time.perf_counter()
     k = 0
@@ -296,14 +298,15 @@ def serving(args, A):
     reqs = workloads.serving_stream(R, rate=1.0, n_hi=args.serve_n_hi)  # unit-rate arrivals
     ex = HipExecutor(A.ANOVA_FP32_NFFT, target_err=1e-4)
     budget = int(args.serve_budget_gb * (1 << 30))
-    closed = serve_stream(Server, ex, reqs, [0.0] * R, budget, 64)
+    closed = serve_stream(Server, ex, reqs, [0.0] * R, budget, 64, args.serve_round)
     cap = closed.stats(0.0)["solves_per_s"]
     print(f"# serving: capacity {cap:.2f} solves/s (closed loop, {R} requests)", file=sys.stderr,
           flush=True)
-    seq = serve_stream(Server, ex, reqs, [0.0] * R, budget, 1)
+    seq = serve_stream(Server, ex, reqs, [0.0] * R, budget, 1, args.serve_round)
     seq_rate = seq.stats(0.0)["solves_per_s"]
     rate = args.serve_load * cap
-    srv = serve_stream(Server, ex, reqs, [r.arrival / rate for r in reqs], budget, 64)
+    srv = serve_stream(Server, ex, reqs, [r.arrival / rate for r in reqs], budget, 64,
+                       args.serve_round)
     st = srv.stats(0.1)
     statuses = {}
     for r in srv.results.values():
@@ -320,6 +323,7 @@ def serving(args, A):
         "mean_ms": round(st["mean_s"] * 1e3, 2), "solves_per_s": round(st["solves_per_s"], 3),
         "latency_from": "arrival (queueing, planning, CG, result copy); first 10% excluded",
         "peak_live": st["peak_live"], "budget_gb": args.serve_budget_gb,
+        "iters_per_round": args.serve_round,
         "peak_reserved_gb": round(st["peak_reserved_bytes"] / 2**30, 3),
         "statuses": statuses, "cg_iters_median": int(np.median(iters)) if iters else None,
     }

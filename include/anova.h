@@ -225,6 +225,17 @@ anova_status krr_cg_start(anova_cg_t *out, anova_plan_t plan, const double *y, d
                           void *stream);
 anova_status krr_cg_iterate(anova_cg_t *solves, int32_t count, int32_t iters, void *stream);
 anova_status krr_cg_poll(anova_cg_t solve, int32_t *active, krr_cg_info *info, void *stream);
+/*
+ * Asynchronous poll of a list: enqueues on `stream`, after the work already
+ * there, the count of still-iterating columns of every listed solve into
+ * dev_counts (device, count int32) and a copy of it to host_counts (host,
+ * count int32; pinned memory keeps the copy asynchronous; read it once the
+ * stream has passed this point).  Nothing synchronises, so a caller can
+ * launch the next iterations before reading the counts.
+ * Errors: ANOVA_E_INVALID for an empty list, a NULL solve or array.
+ */
+anova_status krr_cg_active(anova_cg_t *solves, int32_t count, int32_t *dev_counts,
+                           int32_t *host_counts, void *stream);
 anova_status krr_cg_finish(anova_cg_t solve, krr_cg_info *info, void *stream);
 anova_status krr_cg_destroy(anova_cg_t solve);
 

@@ -100,6 +100,7 @@ def load():
                                  dbl, i32, ctypes.POINTER(krr_cg_info), VP],
         "anova_plan_stage_times": [VP, ctypes.POINTER(dbl), ctypes.POINTER(i64)],
         "anova_plan_footprint": [VP, i32, ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "krr_cg_active": [ctypes.POINTER(VP), i32, VP, VP, VP],
         "anova_fastsum_plan_host": [ctypes.POINTER(VP), VP, i64, i32, i64,
                                     ctypes.POINTER(anova_window), i32, ctypes.POINTER(anova_params)],
     }
@@ -372,6 +373,21 @@ class Solve:
 def krr_cg_iterate(solves: Sequence["Solve"], iters: int, stream=None) -> None:
     arr = (VP * len(solves))(*[s.handle for s in solves])
     _check(load().krr_cg_iterate(arr, len(solves), int(iters), _stream(stream)))
+
+
+def krr_cg_active(solves: Sequence["Solve"], dev_counts, host_counts, stream=None) -> None:
+    """Enqueue the still-iterating column count of each solve into
+    dev_counts (CUDA int32) and copy it to host_counts (pinned CPU int32);
+    read host_counts after synchronising on an event recorded afterwards."""
+    import torch
+    if dev_counts.dtype != torch.int32 or host_counts.dtype != torch.int32:
+        raise TypeError("count arrays must be int32")
+    n = len(solves)
+    if dev_counts.numel() < n or host_counts.numel() < n or not dev_counts.is_cuda:
+        raise ValueError("count arrays too small or not on the device/host")
+    arr = (VP * n)(*[s.handle for s in solves])
+    _check(load().krr_cg_active(arr, n, dev_counts.data_ptr(), host_counts.data_ptr(),
+                                _stream(stream)))
 
 
 def krr_cg_solve_batched(plans, ys, alphas, betas, tol: float, maxit: int, stream=None,

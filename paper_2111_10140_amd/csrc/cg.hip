@@ -281,6 +281,18 @@ __global__ __launch_bounds__(kRedBlock) void cg_update_p_kernel(const CgCol *__r
         cr.col.p[i] = cr.col.r[i] + sc.b * cr.col.p[i];
 }
 
+// Still-iterating columns of each solve of a list (solve s owns columns
+// solve_cols[s] .. solve_cols[s+1]-1), one thread per solve.
+__global__ __launch_bounds__(kRedBlock) void cg_active_kernel(const CgCol *__restrict__ cols,
+                                                             const int32_t *__restrict__ solve_cols,
+                                                             int count, int32_t *__restrict__ out) {
+    const int s = blockIdx.x * kRedBlock + threadIdx.x;
+    if (s >= count) return;
+    int a = 0;
+    for (int c = solve_cols[s]; c < solve_cols[s + 1]; ++c) a += cols[c].sc->active ? 1 : 0;
+    out[s] = a;
+}
+
 // ---------------------------------------------------------------- column lists
 struct ColList {
     std::vector<CgCol> cols;
@@ -338,6 +350,7 @@ struct StepGraph {
     std::vector<uint64_t> ids;
     std::vector<anova_cg_s *> solves;
     ColList list;
+    DevBuf d_solve_cols;  // int32 [count + 1]: first column of each solve in `list`
     Batch pq, xq;  // q = A p, q = A x over every solve in the list
     hipStream_t cap = nullptr;
     hipGraphExec_t g_plain = nullptr, g_replace = nullptr;
@@ -417,9 +430,11 @@ static StepGraph &step_graph(anova_cg_s *const *solves, int count) {
     G->ids = ids;
     G->solves.assign(solves, solves + count);
     std::vector<BatchProblem> pq_probs, xq_probs;
+    std::vector<int32_t> solve_cols(1, 0);
     for (int i = 0; i < count; ++i) {
         anova_cg_s *sv = solves[i];
         G->list.cols.insert(G->list.cols.end(), sv->own.cols.begin(), sv->own.cols.end());
+        solve_cols.push_back((int32_t)G->list.cols.size());
         pq_probs.push_back(product(sv, sv->p.as<double>(), false));
         BatchProblem bx = product(sv, sv->x, true);
         bx.ld = sv->ld;      // x columns follow the caller's leading dimension
@@ -427,6 +442,7 @@ static StepGraph &step_graph(anova_cg_s *const *solves, int count) {
         xq_probs.push_back(bx);
     }
     G->list.upload_lists();
+    upload(G->d_solve_cols, solve_cols);
     G->pq.build(pq_probs);
     G->xq.build(xq_probs);
     ANOVA_HIP_CHECK(hipStreamCreateWithFlags(&G->cap, hipStreamNonBlocking));
@@ -580,6 +596,25 @@ extern "C" anova_status krr_cg_poll(anova_cg_t sv, int32_t *active, krr_cg_info 
         for (auto &c : hs) a += c.active ? 1 : 0;
         if (active) *active = a;
         if (info) fill_info(sv, hs, nullptr, info);
+        return ANOVA_OK;
+    });
+}
+
+extern "C" anova_status krr_cg_active(anova_cg_t *solves, int32_t count, int32_t *dev_counts,
+                                      int32_t *host_counts, void *stream) {
+    return guarded_cg([&] {
+        ANOVA_REQUIRE(solves != nullptr && count >= 1, "empty solve list");
+        ANOVA_REQUIRE(dev_counts != nullptr && host_counts != nullptr, "NULL count array");
+        for (int i = 0; i < count; ++i) ANOVA_REQUIRE(solves[i] != nullptr, "NULL solve");
+        std::lock_guard<std::mutex> lock(g_step_mu);
+        StepGraph &G = step_graph(solves, count);
+        hipStream_t s = (hipStream_t)stream;
+        hipLaunchKernelGGL(cg_active_kernel, dim3((count + kRedBlock - 1) / kRedBlock),
+                           dim3(kRedBlock), 0, s, G.list.d_cols.as<CgCol>(),
+                           G.d_solve_cols.as<int32_t>(), count, dev_counts);
+        ANOVA_HIP_CHECK(hipGetLastError());
+        ANOVA_HIP_CHECK(hipMemcpyAsync(host_counts, dev_counts, sizeof(int32_t) * count,
+                                       hipMemcpyDeviceToHost, s));
         return ANOVA_OK;
     });
 }

@@ -160,6 +160,7 @@ class Server:
         self.peak_live = 0
         self.rounds = 0
         self._next = 0
+        self._inflight = None  # (requests, poll handle) of the last launched round
         self._pool = None
         if planners > 0:
             import concurrent.futures
@@ -300,25 +301,48 @@ class Server:
                 continue
             self._place(req, state, exact)
 
-    def step(self) -> None:
-        """One round: launch iterations of the live list, admit waiting
-        requests while the device works, then retire finished ones."""
-        self.rounds += 1
-        if self.live:
-            self.ex.iterate([r.state for r in self.live], self.iters_per_round)
-        self._admit()
-        still = []
-        for r in self.live:
-            if r.state is None or self.ex.active(r.state) > 0:
-                still.append(r)
-                continue
+    def _retire(self, finished) -> None:
+        for r in finished:
             try:
                 alpha, info, status = self.ex.finish(r.state)
                 self._done(r, status, alpha, info, "")
             except Exception as e:
                 self._done(r, "ERROR", None, [], str(e))
             self._release(r)
-        self.live = still
+        gone = set(id(r) for r in finished)
+        self.live = [r for r in self.live if id(r) not in gone]
+
+    def step(self) -> None:
+        """One round: launch iterations of the live list, admit waiting
+        requests while the device works, then retire finished ones.
+
+        With an executor that polls asynchronously (active_async), the
+        still-iterating counts are enqueued behind each round's iterations
+        and read one round later, after the next round has been launched, so
+        the device does not wait for the host between rounds; a request that
+        has just finished may take part in one more round (its columns are
+        frozen, the round changes nothing of it)."""
+        self.rounds += 1
+        asynchronous = hasattr(self.ex, "active_async")
+        launched = None
+        if self.live:
+            states = [r.state for r in self.live]
+            self.ex.iterate(states, self.iters_per_round)
+            if asynchronous:
+                launched = (list(self.live), self.ex.active_async(states))
+        self._admit()
+        if asynchronous:
+            prev, self._inflight = self._inflight, launched
+            if prev is None:
+                return
+            reqs, handle = prev
+            counts = self.ex.active_wait(handle)
+            live_ids = set(id(r) for r in self.live)
+            finished = [r for r, a in zip(reqs, counts)
+                        if id(r) in live_ids and r.state is not None and a == 0]
+        else:
+            finished = [r for r in self.live if r.state is not None and self.ex.active(r.state) == 0]
+        self._retire(finished)
         if not self.live and self.planning:
             # nothing to iterate: wait for the oldest plan instead of spinning
             import concurrent.futures
@@ -407,6 +431,31 @@ class HipExecutor:
 
     def active(self, st) -> int:
         return st["solve"].poll(stream=self.stream)[0]
+
+    def active_async(self, states):
+        """Enqueue the still-iterating column counts of the listed solves
+        behind the launched iterations (two alternating buffer pairs, so a
+        round's counts are not overwritten before they are read)."""
+        torch = self.torch
+        n = len(states)
+        self._ring = getattr(self, "_ring", [None, None])
+        self._slot = 1 - getattr(self, "_slot", 1)
+        buf = self._ring[self._slot]
+        if buf is None or buf[0].numel() < n:
+            cap = max(64, 2 * n)
+            buf = (torch.empty(cap, dtype=torch.int32, device="cuda"),
+                   torch.empty(cap, dtype=torch.int32, pin_memory=True),
+                   torch.cuda.Event())
+            self._ring[self._slot] = buf
+        dev, host, ev = buf
+        self.A.krr_cg_active([s["solve"] for s in states], dev, host, stream=self.stream)
+        ev.record(self.stream)
+        return (host, ev, n)
+
+    def active_wait(self, handle):
+        host, ev, n = handle
+        ev.synchronize()
+        return host[:n].tolist()
 
     def finish(self, st):
         sv = st["solve"]

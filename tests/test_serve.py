@@ -209,3 +209,31 @@ def test_close_cancels_pending():
     srv.close()
     assert all(srv.result(h).status == "CANCELLED" for h in hs)
     assert srv.reserved == 0 and not ex.live_states
+
+
+class AsyncPollExecutor(FakeExecutor):
+    """Polls one round late, like the device executor's asynchronous poll."""
+
+    def active_async(self, states):
+        return [self.active(s) for s in states]
+
+    def active_wait(self, handle):
+        return handle
+
+
+def test_asynchronous_poll_retires_one_round_late():
+    ex = AsyncPollExecutor()
+    srv = Server(ex, budget=10_000, max_live=4, iters_per_round=2, clock=Clock())
+    hs = [submit(srv, 10 + k, need=2 + 3 * k) for k in range(6)]
+    while srv.busy():
+        srv.step()
+        assert srv.reserved <= srv.budget
+    assert all(srv.result(h).status == "OK" for h in hs)
+    assert srv.reserved == 0 and not ex.live_states
+    # a cancelled live request is not retired again from a stale poll
+    h = submit(srv, 10, need=50)
+    srv.step()
+    srv.step()
+    assert srv.cancel(h)
+    srv.step()
+    assert srv.result(h).status == "CANCELLED" and not ex.live_states
