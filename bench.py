@@ -64,27 +64,30 @@ def parse():
     return ap.parse_args()
 
 
-def alg_bytes(stage: str, N: int, G: int, elem: int, P: int = 3) -> float:
+def alg_bytes(stage: str, N: int, G: int, elem: int, P: int = 3, per_cell: bool = True) -> float:
     """Algorithmic HBM bytes of a stage for one window (the combine: for the
     whole product).  elem = 4 B (float32 NFFT) or 8 B (float64):
-    permute : permutation index 4 B, the gathered float64 coefficient 8 B and
-              the sorted coefficient written (elem) per point;
-    spread  : node record (16 B f32 / 32 B f64) + sorted coefficient per
-              point, one write of each grid value;
+    permute (per-point kernels only): permutation index 4 B, the gathered
+              float64 coefficient 8 B and the sorted coefficient written;
+    spread  : per-cell (float32): the point's three offsets 12 B, its
+              permutation index 4 B and float64 coefficient 8 B; per-point:
+              node record (16 B f32 / 32 B f64) + sorted coefficient; one
+              write of each grid value;
     tile_sum, fold : one write of each grid value (the tile regions they read
               are traffic of this implementation, not of the method);
     convolve (one axis pass): one read and one write of the grid;
-    gather  : node record, the permutation index 4 B and one value written
-              (in the caller's order) per point, one read of each grid value;
+    gather  : the offsets (12 B per-cell, the node record per-point), the
+              permutation index 4 B and one value written (in the caller's
+              order) per point, one read of each grid value;
     combine (all windows): alpha read and output write 16 B per point, plus
               each window's value per point."""
     node = 16 if elem == 4 else 32
     if stage == "permute":
         return N * (4 + 8 + elem)
     if stage == "spread":
-        return N * (node + elem) + G * elem
+        return (N * (12 + 4 + 8) if per_cell else N * (node + elem)) + G * elem
     if stage == "gather":
-        return N * (node + 4 + elem) + G * elem
+        return N * ((12 if per_cell else node) + 4 + elem) + G * elem
     if stage == "combine":
         return N * (16 + P * elem)
     if stage == "convolve":
@@ -379,7 +382,7 @@ def main():
         if cnt:
             # one launch group covers all P windows (combine: the whole product)
             avg_ms = tot / cnt
-            b = alg_bytes(k, N, G, 4, P) * (1 if k == "combine" else P)
+            b = alg_bytes(k, N, G, 4, P, bool(infos[0].per_cell)) * (1 if k == "combine" else P)
             per_launch[k] = dict(avg_us=avg_ms * 1e3, launches=cnt, alg_bytes=b,
                                  gbs=b / (avg_ms * 1e-3) / 1e9)
     W = 2 * infos[0].m
