@@ -122,7 +122,7 @@ struct WindowPlan {
     int64_t n_tiles = 0, n_nonempty = 0, n_sub = 0;
     int poly_deg = 0;
     bool dense = false;          // per-cell register accumulation (see kernels.hip)
-    int chunks = 1;              // dense regime: most workgroups of one tile
+    int chunks = 1;              // dense regime: workgroups per tile
     std::vector<int32_t> chunk_start;  // dense regime: first workgroup of each non-empty tile
     std::vector<int32_t> tile_order;   // dense regime: non-empty tiles in launch order
     int64_t n_points = 0;
@@ -203,8 +203,9 @@ struct WinInst {
     void *priv;                 // spread regions
     void *treg;                 // per-tile region sums
     void *grid;                 // n^dA grid
-    void *tmp;                  // interpolated values, sorted order
-    int32_t n, tile, tpd, chunks;
+    void *tmp;                  // sorted coefficients (per-point spread), then
+                                // interpolated values in the caller's order
+    int32_t n, tile, tpd, pad0;
     int32_t vol, n_sub, n_nonempty, n_tiles;
     int32_t n_regions, N, dA, width;
 };

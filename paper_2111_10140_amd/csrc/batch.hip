@@ -123,7 +123,6 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
                 wi.n = w.n;
                 wi.tile = w.tile;
                 wi.tpd = w.tiles_per_dim;
-                wi.chunks = w.chunks;
                 wi.vol = (int32_t)w.region_elems();
                 wi.n_sub = (int32_t)w.n_sub;
                 wi.n_nonempty = (int32_t)w.n_nonempty;

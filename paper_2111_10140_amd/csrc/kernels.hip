@@ -17,11 +17,13 @@
 // covers all instances of one kernel signature, and each workgroup finds its
 // instance by a binary search over the per-instance block counts.
 //
-// Points are sorted by grid tile at plan time.  Spreading accumulates a tile
-// region (tile + halo of 2m-1 points) per workgroup in LDS with integer
-// atomics and stores it with plain stores; a fold kernel adds the regions
-// into the grid in a fixed order.  No floating-point atomics are used, so a
-// product is bitwise reproducible.
+// Points are sorted by grid tile at plan time.  Spreading forms one tile
+// region (tile + halo of 2m-1 points) per workgroup -- per cell from
+// registers with fixed-order sums (per-cell kernels), or in LDS with integer
+// atomics (per-point kernels) -- and stores it with plain stores; a fold
+// kernel adds the regions into the grid in a fixed order.  No floating-point
+// atomics are used, so a product is bitwise reproducible.  Gathering writes
+// each point's value at its position in the caller's order.
 #include <type_traits>
 
 #include "anova_internal.h"
@@ -603,7 +605,8 @@ __global__ __launch_bounds__(kBlock) void gather_pt_kernel(const WinInst *__rest
 
 // ------------------------------------------------------------------ permute
 // The window's coefficients in its sorted point order, as[j] = alpha[perm[j]],
-// written to the instance's value buffer (the gather overwrites it later).
+// written to the instance's value buffer (the gather overwrites it later);
+// per-point windows only (the per-cell spread reads alpha[perm[j]] itself).
 // Blocks: ceil(N / (4 kBlock)) per instance.
 // Elements per thread of the permutation and combine kernels: their loads
 // land at random positions, so each thread first issues all its index loads,

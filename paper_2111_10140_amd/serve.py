@@ -30,7 +30,7 @@ from __future__ import annotations
 import collections
 import math
 import time
-from dataclasses import dataclass, field
+from dataclasses import dataclass
 from typing import Any, Callable, Deque, Dict, List, Optional, Sequence
 
 import numpy as np
