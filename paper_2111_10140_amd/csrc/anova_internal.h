@@ -300,6 +300,7 @@ int convolve_lines_per_block(int n, int nq);
 int cell_tile(int dA);
 int cell_threads_per_cell(int dA);
 bool cell_width_supported(int dA, int W);
+int cell_point_splits(int dA, int W);
 int combine_span();
 int permute_span();
 int fold_tiles_per_block(int tile, int dA);

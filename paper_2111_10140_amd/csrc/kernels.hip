@@ -526,6 +526,390 @@ __global__ __launch_bounds__(kBlock) void gather_cell_kernel(const WinInst *__re
     }
 }
 
+// ------------------------------------------------------------------ per-cell, wide supports
+// Supports too wide for one thread's registers (d_A = 3, W = 8 or 12, float
+// 32): SX x SY x SZ adjacent lanes of a cell each own one block of its
+// support (a half, or all, of the offsets along each axis), every lane of
+// the cell walks all of the cell's points, and the z planes of a block may
+// go in several passes over the points so that a pass's sums fit in
+// registers.
+//
+// The window is even, so the polynomial of offset W-1-a at z = 2f-1 equals
+// that of offset a at -z.  A lane owning the upper half of an axis indexes
+// its offsets mirrored (register i holds offset W-1-i) and evaluates the
+// lower-half polynomials at -z: every lane then evaluates the same W/2
+// polynomials, whose coefficients sit in scalar registers.
+//
+// Such a lane holds up to 216 sums, so one workgroup of two waves takes a
+// tile's 64 cells in groups, heaviest cells first; a wave's cells then hold
+// about as many points each, and several workgroups share a compute unit,
+// so one waiting for its fullest cell leaves the unit to the others.
+// Spreading adds each cell's sums into the tile region with int64
+// fixed-point LDS atomics at one scale per workgroup, fixed before the
+// first point; gathering adds the block partials of a point over the
+// cell's lanes in a fixed order.
+template <int W> struct WideSplit;
+// NPS / NPG: z passes of the spreading / gathering kernel
+template <> struct WideSplit<8> { static constexpr int SX = 2, SY = 2, SZ = 1, NPS = 1, NPG = 1; };
+template <> struct WideSplit<12> { static constexpr int SX = 2, SY = 2, SZ = 2, NPS = 1, NPG = 2; };
+constexpr int kWideTile = 4, kWideCells = 64, kWideThreads = 128;
+
+template <int W>
+constexpr int wide_lanes() { return WideSplit<W>::SX * WideSplit<W>::SY * WideSplit<W>::SZ; }
+template <int W>
+constexpr int wide_group_cells() { return kWideThreads / wide_lanes<W>(); }
+
+// Lower-half window polynomials, uniform across the workgroup.
+template <int W>
+struct HalfPoly {
+    static constexpr int D = PolyDeg<float>::value, H = W / 2;
+    float c[H][D + 1];
+    __device__ __forceinline__ void load(const float *__restrict__ poly) {
+#pragma unroll
+        for (int a = 0; a < H; ++a)
+#pragma unroll
+            for (int k = 0; k <= D; ++k) c[a][k] = uniform(poly[a * (D + 1) + k]);
+    }
+    __device__ __forceinline__ float at(float z, int a) const {
+        float v = c[a][D];
+#pragma unroll
+        for (int k = D - 1; k >= 0; --k) v = v * z + c[a][k];
+        return v;
+    }
+};
+
+// One axis of a lane's block: NA offsets, register i <-> support offset
+// offset(s, i), weighted by a lower-half polynomial at z or -z.
+template <int W, int SA>
+struct WideAxis {
+    static constexpr int NA = W / SA;
+    // SA == 2: half s of the axis, mirrored when s == 1
+    // SA == 1: the whole axis, lower half at z, upper half mirrored at -z
+    __device__ __forceinline__ static int offset(int s, int i) {
+        if constexpr (SA == 2) return s ? W - 1 - i : i;
+        else return i;
+    }
+    __device__ __forceinline__ static void weights(const HalfPoly<W> &hp, float z, int s,
+                                                   float (&w)[NA]) {
+        if constexpr (SA == 2) {
+            const float zs = s ? -z : z;
+#pragma unroll
+            for (int i = 0; i < NA; ++i) w[i] = hp.at(zs, i);
+        } else {
+#pragma unroll
+            for (int i = 0; i < W / 2; ++i) w[i] = hp.at(z, i);
+#pragma unroll
+            for (int i = W / 2; i < W; ++i) w[i] = hp.at(-z, W - 1 - i);
+        }
+    }
+    __device__ __forceinline__ static float weight(const HalfPoly<W> &hp, float z, int s, int i) {
+        if constexpr (SA == 2) return hp.at(s ? -z : z, i);
+        else return i < W / 2 ? hp.at(z, i) : hp.at(-z, W - 1 - i);
+    }
+};
+
+__device__ __forceinline__ float block_max_wide(float v, float *sh) {
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    float r = sh[0];
+    for (int i = 1; i < kWideThreads / 64; ++i) r = fmaxf(r, sh[i]);
+    return r;
+}
+
+// The chunk's share of each cell of the tile (first point, count) and the
+// cells by count, heaviest first (ties by cell index).
+struct WideCells {
+    int pb[kWideCells], cnt[kWideCells], order[kWideCells];
+};
+__device__ __forceinline__ void wide_cells(const WinInst &wi, int key0, int chunk, int K,
+                                           WideCells &cs) {
+    const int t = threadIdx.x;
+    if (t < kWideCells) {
+        int pb, pe;
+        chunk_range(wi.cell_start[key0 + t], wi.cell_start[key0 + t + 1], chunk, K, pb, pe);
+        cs.pb[t] = pb;
+        cs.cnt[t] = pe - pb;
+    }
+    __syncthreads();
+    if (t < kWideCells) {
+        const int c = cs.cnt[t];
+        int r = 0;
+        for (int u = 0; u < kWideCells; ++u) {
+            const int cu = cs.cnt[u];
+            r += (cu > c || (cu == c && u < t)) ? 1 : 0;
+        }
+        cs.order[r] = t;
+    }
+    __syncthreads();
+}
+
+// A lane's block of the support (sx, sy, sz) and, for group g, its cell.
+template <int W>
+struct WideLane {
+    int sub, sx, sy, sz;
+    __device__ __forceinline__ WideLane() {
+        constexpr int SY = WideSplit<W>::SY, SZ = WideSplit<W>::SZ;
+        sub = (int)(threadIdx.x % wide_lanes<W>());
+        sz = sub % SZ;
+        sy = (sub / SZ) % SY;
+        sx = sub / (SZ * SY);
+    }
+    // the two waves take the heavier half of a group in turn
+    __device__ __forceinline__ int slot(int g) const {
+        constexpr int CPG = wide_group_cells<W>();
+        const int wave = (int)(threadIdx.x / 64);
+        return g * CPG + ((wave + g) & 1) * (CPG / 2) + (int)(threadIdx.x % 64) / wide_lanes<W>();
+    }
+};
+
+template <int W>
+__global__ __launch_bounds__(kWideThreads, 2) void spread_wide_kernel(
+    const WinInst *__restrict__ insts, const int32_t *__restrict__ members,
+    const int32_t *__restrict__ prefix, int cnt) {
+    using SP = WideSplit<W>;
+    using AX = WideAxis<W, SP::SX>;
+    using AY = WideAxis<W, SP::SY>;
+    using AZ = WideAxis<W, SP::SZ>;
+    constexpr int NT = kWideThreads, TPC = wide_lanes<W>();
+    constexpr int NG = kWideCells / wide_group_cells<W>();
+    constexpr int WX = AX::NA, WY = AY::NA, PZ = AZ::NA / SP::NPS;
+    constexpr int T = kWideTile, L = T + W - 1, VOL = L * L * L;
+    __shared__ unsigned long long acc_lds[VOL];
+    __shared__ float4 stage[NT];
+    __shared__ WideCells cs;
+    __shared__ float red[NT / 64];
+    const Located loc = locate(insts, members, prefix, cnt);
+    const WinInst &wi = *loc.w;
+    const NodeF32 *__restrict__ nodes = static_cast<const NodeF32 *>(wi.nodes);
+    const int32_t *__restrict__ perm = wi.perm;
+    const double *__restrict__ alpha = wi.alpha;
+    HalfPoly<W> hp;
+    hp.load(static_cast<const float *>(wi.poly));
+    for (int e = threadIdx.x; e < VOL; e += NT) acc_lds[e] = 0ull;
+    int tk, chunk, K;
+    locate_chunk(wi.src_sub, wi.n_nonempty, loc.lb, tk, chunk, K);
+    const int key0 = wi.tiles_ne[tk] * kWideCells;
+    wide_cells(wi, key0, chunk, K, cs);  // its barriers also order the zero fill
+    // the scale, from the largest |coefficient| over the tile's points (a
+    // superset of the chunk's) and the largest count of one cell: every
+    // register sum of a cell then rounds below 2^30 (weights are at most 1),
+    // and an int64 region value adds at most one such sum per lane
+    float amax = 0.0f;
+    {
+        const int t0 = wi.cell_start[key0], t1 = wi.cell_start[key0 + kWideCells];
+        for (int j = t0 + (int)threadIdx.x; j < t1; j += 4 * NT) {
+            int pi[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) pi[u] = j + u * NT < t1 ? perm[j + u * NT] : -1;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (pi[u] >= 0) amax = fmaxf(amax, abs_for_max(alpha[pi[u]]));
+        }
+    }
+    amax = block_max_wide(amax, red);
+    float *out = static_cast<float *>(wi.priv) + (size_t)loc.lb * VOL;
+    if (!(amax > 0.0f && amax <= 3.0e38f)) {  // all zero, or not finite
+        const float fill = amax > 0.0f ? NAN : 0.0f;
+        for (int e = threadIdx.x; e < VOL; e += NT) out[e] = fill;
+        return;
+    }
+    int ex2, ct;
+    (void)frexpf(amax * 1.0000002f, &ex2);
+    (void)frexpf(fmaxf((float)cs.cnt[cs.order[0]], 1.0f), &ct);
+    const int Sx = 30 - ex2 - ct;
+    const WideLane<W> ln;
+    float4 *stg = stage + (threadIdx.x - ln.sub);
+#pragma unroll 1
+    for (int g = 0; g < NG; ++g) {
+        const int cell = cs.order[ln.slot(g)];
+        const int pb = cs.pb[cell], pe = pb + cs.cnt[cell];
+        if (pb >= pe) continue;  // the lanes of a cell go on together
+        const int lx = cell % T, ly = (cell / T) % T, lz = cell / (T * T);
+#pragma unroll  // constant pass: the polynomial index stays static
+        for (int pass = 0; pass < SP::NPS; ++pass) {
+            float acc[PZ][WY][WX];
+#pragma unroll
+            for (int c = 0; c < PZ; ++c)
+#pragma unroll
+                for (int b = 0; b < WY; ++b)
+#pragma unroll
+                    for (int i = 0; i < WX; ++i) acc[c][b][i] = 0.0f;
+            // the cell's points go through LDS in rounds of TPC, lane s of
+            // the cell loading point s of the next round while the cell works
+            // through the current one; the lanes of a cell share a wave,
+            // whose LDS accesses complete in order
+            float4 nx = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            int jl = pb + ln.sub;
+            if (jl < pe) {
+                const float3 r = node_offsets(nodes + jl);
+                nx = make_float4(r.x, r.y, r.z, (float)alpha[perm[jl]]);
+            }
+            for (int q0 = pb; q0 < pe; q0 += TPC) {
+                stg[ln.sub] = nx;
+                jl += TPC;
+                if (jl < pe) {
+                    const float3 r = node_offsets(nodes + jl);
+                    nx = make_float4(r.x, r.y, r.z, (float)alpha[perm[jl]]);
+                }
+                const int kn = min(TPC, pe - q0);
+                for (int k = 0; k < kn; ++k) {
+                    const float4 p = stg[k];
+                    float wx[WX], wy[WY];
+                    AX::weights(hp, 2.0f * p.x - 1.0f, ln.sx, wx);
+                    AY::weights(hp, 2.0f * p.y - 1.0f, ln.sy, wy);
+                    const float zz = 2.0f * p.z - 1.0f;
+#pragma unroll
+                    for (int c = 0; c < PZ; ++c) {
+                        const float wc = p.w * AZ::weight(hp, zz, ln.sz, pass * PZ + c);
+#pragma unroll
+                        for (int b = 0; b < WY; ++b) {
+                            const float wbc = wc * wy[b];
+#pragma unroll
+                            for (int i = 0; i < WX; ++i)
+                                acc[c][b][i] = fmaf(wbc, wx[i], acc[c][b][i]);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < PZ; ++c) {
+                const int z = lz + AZ::offset(ln.sz, pass * PZ + c);
+#pragma unroll
+                for (int b = 0; b < WY; ++b) {
+                    unsigned long long *row = acc_lds + (z * L + ly + AY::offset(ln.sy, b)) * L + lx;
+#pragma unroll
+                    for (int i = 0; i < WX; ++i) {
+                        const float v = acc[c][b][i];
+                        if (v != 0.0f)
+                            atomicAdd(&row[AX::offset(ln.sx, i)],
+                                      (unsigned long long)round_to_ll(ldexpf(v, Sx)));
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const double inv = ldexp(1.0, -Sx);
+    for (int e = threadIdx.x; e < VOL; e += NT) out[e] = (float)((double)(long long)acc_lds[e] * inv);
+}
+
+// Sum over the adjacent lanes of a cell, the same bits in every lane.
+template <int TPC>
+__device__ __forceinline__ float cell_lanes_sum(float v) {
+    static_assert(TPC == 4 || TPC == 8, "4 or 8 lanes per cell");
+    v = quad_step1(v);
+    v = quad_step2(v);
+    if constexpr (TPC == 8) v += __shfl_xor(v, 4, 64);
+    return v;
+}
+
+template <int W>
+__global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
+    const WinInst *__restrict__ insts, const int32_t *__restrict__ members,
+    const int32_t *__restrict__ prefix, int cnt) {
+    using SP = WideSplit<W>;
+    using AX = WideAxis<W, SP::SX>;
+    using AY = WideAxis<W, SP::SY>;
+    using AZ = WideAxis<W, SP::SZ>;
+    constexpr int NT = kWideThreads, TPC = wide_lanes<W>();
+    constexpr int NG = kWideCells / wide_group_cells<W>();
+    constexpr int WX = AX::NA, WY = AY::NA, PZ = AZ::NA / SP::NPG;
+    constexpr int T = kWideTile, L = T + W - 1, L2 = L * L, VOL = L2 * L;
+    constexpr int m = W / 2;
+    __shared__ float g_lds[VOL];
+    __shared__ float4 stage[NT];
+    __shared__ WideCells cs;
+    const Located loc = locate(insts, members, prefix, cnt);
+    const WinInst &wi = *loc.w;
+    const NodeF32 *__restrict__ nodes = static_cast<const NodeF32 *>(wi.nodes);
+    const float *__restrict__ grid = static_cast<const float *>(wi.grid);
+    float *__restrict__ tmp = static_cast<float *>(wi.tmp);
+    const int32_t *__restrict__ perm = wi.perm;
+    HalfPoly<W> hp;
+    hp.load(static_cast<const float *>(wi.poly));
+    const int n = wi.n, tpd = wi.tpd;
+    int tk, chunk, K;
+    locate_chunk(wi.src_sub, wi.n_nonempty, loc.lb, tk, chunk, K);
+    const int tile_id = wi.tiles_ne[tk];
+    const int ox = (tile_id % tpd) * T;
+    const int oy = ((tile_id / tpd) % tpd) * T;
+    const int oz = (tile_id / (tpd * tpd)) * T;
+    for (int e = threadIdx.x; e < VOL; e += NT) {
+        size_t gi = (size_t)wrap_index(ox - m + 1 + e % L, n);
+        gi += (size_t)n * (size_t)wrap_index(oy - m + 1 + (e / L) % L, n);
+        gi += (size_t)n * (size_t)n * (size_t)wrap_index(oz - m + 1 + e / L2, n);
+        g_lds[e] = grid[gi];
+    }
+    wide_cells(wi, tile_id * kWideCells, chunk, K, cs);  // its barriers also order the fill
+    const WideLane<W> ln;
+    const bool lead = ln.sub == 0;
+    float4 *stg = stage + (threadIdx.x - ln.sub);
+#pragma unroll 1
+    for (int g = 0; g < NG; ++g) {
+        const int cell = cs.order[ln.slot(g)];
+        const int pb = cs.pb[cell], pe = pb + cs.cnt[cell];
+        if (pb >= pe) continue;  // the lanes of a cell go on together
+        const int lx = cell % T, ly = (cell / T) % T, lz = cell / (T * T);
+#pragma unroll  // constant pass: the polynomial index stays static
+        for (int pass = 0; pass < SP::NPG; ++pass) {
+            float gv[PZ][WY][WX];
+#pragma unroll
+            for (int c = 0; c < PZ; ++c) {
+                const int z = lz + AZ::offset(ln.sz, pass * PZ + c);
+#pragma unroll
+                for (int b = 0; b < WY; ++b) {
+                    const float *row = g_lds + (z * L + ly + AY::offset(ln.sy, b)) * L + lx;
+#pragma unroll
+                    for (int i = 0; i < WX; ++i) gv[c][b][i] = row[AX::offset(ln.sx, i)];
+                }
+            }
+            // points through LDS in rounds of TPC, as in the spreading kernel
+            // (offsets and the point's index in the caller's order)
+            float4 nx = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            int jl = pb + ln.sub;
+            if (jl < pe) {
+                const float3 r = node_offsets(nodes + jl);
+                nx = make_float4(r.x, r.y, r.z, __int_as_float(perm[jl]));
+            }
+            for (int q0 = pb; q0 < pe; q0 += TPC) {
+                stg[ln.sub] = nx;
+                jl += TPC;
+                if (jl < pe) {
+                    const float3 r = node_offsets(nodes + jl);
+                    nx = make_float4(r.x, r.y, r.z, __int_as_float(perm[jl]));
+                }
+                const int kn = min(TPC, pe - q0);
+                for (int k = 0; k < kn; ++k) {
+                    const float4 p = stg[k];
+                    float *dst = tmp + __float_as_int(p.w);
+                    // a later pass adds to what the same lane wrote in the pass before
+                    const float prev = pass > 0 && lead ? *dst : 0.0f;
+                    float wx[WX], wy[WY];
+                    AX::weights(hp, 2.0f * p.x - 1.0f, ln.sx, wx);
+                    AY::weights(hp, 2.0f * p.y - 1.0f, ln.sy, wy);
+                    const float zz = 2.0f * p.z - 1.0f;
+                    float part = 0.0f;
+#pragma unroll
+                    for (int c = 0; c < PZ; ++c) {
+                        float sc = 0.0f;
+#pragma unroll
+                        for (int b = 0; b < WY; ++b) {
+                            float sr = 0.0f;
+#pragma unroll
+                            for (int i = 0; i < WX; ++i) sr = fmaf(gv[c][b][i], wx[i], sr);
+                            sc = fmaf(sr, wy[b], sc);
+                        }
+                        part = fmaf(sc, AZ::weight(hp, zz, ln.sz, pass * PZ + c), part);
+                    }
+                    const float v = cell_lanes_sum<TPC>(part);
+                    if (lead) *dst = prev + v;  // caller order
+                }
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ gather, per point
 template <typename T, int DA, int W>
 __global__ __launch_bounds__(kBlock) void gather_pt_kernel(const WinInst *__restrict__ insts,
@@ -685,6 +1069,7 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
     const int n = wi.n, tile = wi.tile, tpd = wi.tpd, vol = wi.vol;
     const int L = tile + wi.width - 1;
     const int L2 = DA >= 2 ? L * L : L;
+
     int cells = tile;
     if (DA >= 2) cells *= tile;
     if (DA == 3) cells *= tile;
@@ -919,9 +1304,20 @@ template <typename T, int DA, int W>
 void gather_pt_launch(const BatchGroup &g, const WinInst *insts, hipStream_t s) {
     launch_k(gather_pt_kernel<T, DA, W>, g, region_elems(DA, g.tile, W) * sizeof(T), insts, s);
 }
+template <typename K>
+void launch_nt(K kernel, int nt, const BatchGroup &g, const WinInst *insts, hipStream_t s) {
+    if (g.blocks <= 0) return;
+    hipLaunchKernelGGL(kernel, dim3((unsigned)g.blocks), dim3(nt), 0, s, insts, g.members,
+                       g.prefix, g.cnt);
+    ANOVA_HIP_CHECK(hipGetLastError());
+}
 template <int DA, int W>
 void spread_cell_launch(const BatchGroup &g, const WinInst *insts, hipStream_t s) {
-    if constexpr (cell_supported<DA, W>()) {
+    if constexpr (DA == 3 && (W == 8 || W == 12)) {
+        if (g.tile != kWideTile)
+            throw Error{ANOVA_E_INVALID, "wide per-cell kernels take 4^3-cell tiles"};
+        launch_nt(spread_wide_kernel<W>, kWideThreads, g, insts, s);
+    } else if constexpr (cell_supported<DA, W>()) {
         constexpr int TILE = CellTileOf<DA>::value;
         constexpr int S = kBlock / CellShape<DA, TILE>::cells;
         launch_k(spread_cell_kernel<DA, W, TILE, S>, g, 0, insts, s);
@@ -931,7 +1327,11 @@ void spread_cell_launch(const BatchGroup &g, const WinInst *insts, hipStream_t s
 }
 template <int DA, int W>
 void gather_cell_launch(const BatchGroup &g, const WinInst *insts, hipStream_t s) {
-    if constexpr (cell_supported<DA, W>()) {
+    if constexpr (DA == 3 && (W == 8 || W == 12)) {
+        if (g.tile != kWideTile)
+            throw Error{ANOVA_E_INVALID, "wide per-cell kernels take 4^3-cell tiles"};
+        launch_nt(gather_wide_kernel<W>, kWideThreads, g, insts, s);
+    } else if constexpr (cell_supported<DA, W>()) {
         constexpr int TILE = CellTileOf<DA>::value;
         constexpr int S = kBlock / CellShape<DA, TILE>::cells;
         launch_k(gather_cell_kernel<DA, W, TILE, S>, g, 0, insts, s);
@@ -1022,7 +1422,15 @@ int cell_threads_per_cell(int dA) {
     const int cells = dA == 3 ? t * t * t : (dA == 2 ? t * t : t);
     return kBlock / cells;
 }
-bool cell_width_supported(int dA, int W) { return dA == 3 ? W <= 6 : (dA == 2 ? W <= 8 : W <= 16); }
+bool cell_width_supported(int dA, int W) {
+    return dA == 3 ? (W <= 6 || W == 8 || W == 12) : (dA == 2 ? W <= 8 : W <= 16);
+}
+int cell_point_splits(int dA, int W) {
+    // lanes of a cell that split its points (the wide 3-D kernels split the
+    // support instead: every lane of a cell walks all of its points)
+    if (dA == 3) return W <= 6 ? 4 : 1;
+    return dA == 2 ? 1 : 4;
+}
 int combine_span() { return kCombineSpan; }
 int permute_span() { return kPermuteSpan; }
 int fold_tiles_per_block(int tile, int dA) {

@@ -423,8 +423,7 @@ void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int p
     // cell -> per-cell register accumulation with a fixed small tile
     const int W = 2 * m;
     const int dense_tile = dA == 3 ? 4 : (dA == 2 ? 16 : 64);
-    const bool dense_ok = prec == ANOVA_FP32_NFFT && n >= dense_tile &&
-                          (dA == 3 ? W <= 6 : (dA == 2 ? W <= 8 : W <= 16));
+    const bool dense_ok = prec == ANOVA_FP32_NFFT && n >= dense_tile && cell_width_supported(dA, W);
     w.dense = dense_ok && (double)N >= 3.0 * (double)std::max<size_t>(nocc, 1);
     // tile edge: power of two dividing n whose region (tile + 2m - 1)^dA of
     // 64-bit spreading accumulators fits in 64 KB of LDS
@@ -510,7 +509,7 @@ void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int p
         // cell (4 threads per cell in 3-D), and at least ~512 workgroups
         // when the points allow
         const double per_cell = (double)N / (double)std::max<size_t>(nocc, 1);
-        const int S = dA == 3 ? 4 : (dA == 2 ? 1 : 4);
+        const int S = cell_point_splits(dA, 2 * m);
         int K = (int)std::lround(per_cell / (12.0 * S));
         K = std::max(K, (int)((512 + ne.size() - 1) / std::max<size_t>(ne.size(), 1)));
         K = std::min(K, std::max(1, (int)(per_cell / S)));

@@ -166,14 +166,19 @@ def test_operator_symmetry(A):
     assert abs(v @ Ku - u @ Kv) <= 1e-5 * np.abs(u).sum() * np.abs(v).sum() / p.N
 
 
-def test_stage_spread_matches_adjoint_ndft(A):
+@pytest.mark.parametrize("precision,N,tol,per_cell", [
+    (F64, 700, 1e-9, 0),      # per-point kernel, float64
+    (F32, 20000, 2e-5, 1),    # wide per-cell kernel (W = 12), tile-blocked regions
+])
+def test_stage_spread_matches_adjoint_ndft(A, precision, N, tol, per_cell):
     # the spread grid, transformed by numpy's FFT and divided by the window
     # transform, reproduces the adjoint NDFT (eq. adjnfft) at x~ = x/h
     import torch
-    p = workloads.random_problem(700, 3, [(0, 1, 2)], 0.1, seed=18, eta=[1.0])
+    p = workloads.random_problem(N, 3, [(0, 1, 2)], 0.1, seed=18, eta=[1.0])
     M, n, m, h = 16, 32, 6, 1.0
     plan = A.anova_fastsum_plan(dev_rows(p.X), p.windows,
-                                A.make_params(p.ell, F64, M=M, n=n, m=m, h=h, center=1))
+                                A.make_params(p.ell, precision, M=M, n=n, m=m, h=h, center=1))
+    assert plan.info(0).per_cell == per_cell
     g = A.grid_tensor(plan, 0)
     a = p.alpha[:, 0]
     A.anova_stage_spread(plan, 0, dev_cols(a), g)
@@ -190,7 +195,7 @@ def test_stage_spread_matches_adjoint_ndft(A):
     ref = oracle.fastsum.adjoint_ndft(a, p.X / h, M)
     err = np.max(np.abs(Yk - ref)) / np.abs(a).sum()
     print(f"adjoint NDFT stage error {err:.3e}")
-    assert err <= 1e-9
+    assert err <= tol
 
 
 def test_feature_grouped_full_size_sampled_rows(A):
@@ -211,6 +216,9 @@ def test_feature_grouped_full_size_sampled_rows(A):
     ([(0, 1)], 2, dict(M=12, n=16, m=4)),
     ([(0,)], 1, dict(M=48, n=64, m=8)),
     ([(0, 1, 2), (3, 4), (5,)], 6, dict(M=12, n=16, m=3)),
+    ([(0, 1, 2)], 3, dict(M=12, n=16, m=4)),
+    ([(0, 1, 2)], 3, dict(M=12, n=16, m=6)),
+    ([(0, 1, 2), (3, 4, 5)], 6, dict(M=12, n=16, m=6)),
 ])
 def test_per_cell_regime(A, windows, d, kw):
     # many points per grid cell: the per-cell register-accumulating kernels
@@ -227,7 +235,7 @@ def test_per_cell_regime(A, windows, d, kw):
 
 def test_matvec_is_deterministic(A):
     # integer accumulation and fixed-order folds: repeated products agree bitwise
-    for kw in [dict(M=12, n=16, m=3), dict(M=64, n=128, m=6)]:
+    for kw in [dict(M=12, n=16, m=3), dict(M=12, n=16, m=6), dict(M=64, n=128, m=6)]:
         p = workloads.random_problem(30000, 3, [(0, 1, 2)], 0.3, seed=40, eta=[1.0])
         plan = make_plan(A, p, F32, **kw)
         a = p.alpha[:, 0]
