@@ -303,7 +303,6 @@ bool cell_width_supported(int dA, int W);
 int cell_point_splits(int dA, int W);
 int combine_span();
 int permute_span();
-int fold_tiles_per_block(int tile, int dA);
 int block_threads();
 
 // plan helpers (plan.hip)

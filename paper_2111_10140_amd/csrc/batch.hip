@@ -215,8 +215,7 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
     add_stage(
         kStageFold, [](const WinInst &w) { return std::make_tuple(w.dA, 0, 0, 0, 0, 0); },
         [](const WinInst &w, int &b) {
-            const int tpb = fold_tiles_per_block(w.tile, w.dA);
-            b = (w.n_tiles + tpb - 1) / tpb;
+            b = w.n_tiles;  // one workgroup per tile
             return true;
         },
         [](BatchGroup &g, const WinInst &w) { g.dA = w.dA; });

@@ -1056,11 +1056,18 @@ __global__ __launch_bounds__(kBlock) void tile_sum_kernel(const WinInst *__restr
 // dimension the region indices of grid point o + c are the values in [0, L)
 // congruent to b + c mod n, b the tile origin's offset in the region).
 // Writes every grid point, so no zero fill is needed.
+constexpr int kFoldBatch = 8;  // region reads in flight per thread
+constexpr int kDies = 8;       // accelerator dies (XCDs), one L2 each
+
+// One workgroup per tile of the grid.  A small tile's cells get S threads
+// each: thread s of a cell adds regions s, s + S, s + 2S, ... of the tile's
+// list, and the S partial sums are then added in order of s.
 template <typename T, int DA>
 __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict__ insts,
                                                       const int32_t *__restrict__ members,
                                                       const int32_t *__restrict__ prefix,
                                                       int cnt) {
+    __shared__ double part[kBlock];
     const Located loc = locate(insts, members, prefix, cnt);
     const WinInst &wi = *loc.w;
     const T *__restrict__ src =
@@ -1069,36 +1076,35 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
     const int n = wi.n, tile = wi.tile, tpd = wi.tpd, vol = wi.vol;
     const int L = tile + wi.width - 1;
     const int L2 = DA >= 2 ? L * L : L;
-
     int cells = tile;
     if (DA >= 2) cells *= tile;
     if (DA == 3) cells *= tile;
-    // small tiles: several per workgroup (one thread per cell)
-    const int tpb = cells >= kBlock ? 1 : kBlock / cells;
-    const int sub = cells >= kBlock ? 0 : (int)threadIdx.x / cells;
-    const int d = loc.lb * tpb + sub;
-    if (sub >= tpb || d >= wi.n_tiles) return;
+    // workgroups go to the chip's 8 dies (each with its own L2) in turn, so
+    // the tiles of one die form one contiguous slab and neighbouring tiles,
+    // which read the same regions, share an L2
+    const int nt = wi.n_tiles;
+    const int d = nt % kDies == 0 ? (loc.lb % kDies) * (nt / kDies) + loc.lb / kDies : loc.lb;
     const int ox = (d % tpd) * tile;
     const int oy = ((d / tpd) % tpd) * tile;
     const int oz = (d / (tpd * tpd)) * tile;
     const int p0 = wi.fold_start[d], p1 = wi.fold_start[d + 1];
-    const int c0 = cells >= kBlock ? (int)threadIdx.x : (int)threadIdx.x % cells;
-    const int cstep = cells >= kBlock ? kBlock : cells;
-    for (int c = c0; c < cells; c += cstep) {
+    // sum over regions first, first + stride, ... of cell c
+    auto cell_sum = [&](int c, int first, int stride) {
         const int cx = c % tile;
         const int cy = DA >= 2 ? (c / tile) % tile : 0;
         const int cz = DA == 3 ? c / (tile * tile) : 0;
         double s = 0.0;
         if (L <= n) {
             // each region element lands on one grid point: at most one read
-            // per region; four regions' reads in flight, added in order
-            for (int p = p0; p < p1; p += 4) {
-                T v[4];
+            // per region; kFoldBatch regions' reads in flight, added in order
+            for (int p = first; p < p1; p += kFoldBatch * stride) {
+                T v[kFoldBatch];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
+                for (int u = 0; u < kFoldBatch; ++u) {
                     v[u] = T(0);
-                    if (p + u < p1) {
-                        const int2 pr = wi.fold_pairs[p + u];
+                    const int q = p + u * stride;
+                    if (q < p1) {
+                        const int2 pr = wi.fold_pairs[q];
                         const int ex = (((pr.y & 1023) + cx) & (n - 1));
                         const int ey = DA >= 2 ? ((((pr.y >> 10) & 1023) + cy) & (n - 1)) : 0;
                         const int ez = DA == 3 ? ((((pr.y >> 20) & 1023) + cz) & (n - 1)) : 0;
@@ -1107,10 +1113,10 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u) s += (double)v[u];
+                for (int u = 0; u < kFoldBatch; ++u) s += (double)v[u];
             }
         } else {
-            for (int p = p0; p < p1; ++p) {
+            for (int p = first; p < p1; p += stride) {
                 const int2 pr = wi.fold_pairs[p];
                 const T *reg = src + (size_t)pr.x * vol;
                 const int bx = pr.y & 1023, by = (pr.y >> 10) & 1023, bz = (pr.y >> 20) & 1023;
@@ -1122,10 +1128,27 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
                         for (int ex = ex0; ex < L; ex += n) s += (double)reg[ez * L2 + ey * L + ex];
             }
         }
-        size_t g = (size_t)(ox + cx);
-        if (DA >= 2) g += (size_t)n * (size_t)(oy + cy);
-        if (DA == 3) g += (size_t)n * (size_t)n * (size_t)(oz + cz);
-        grid[g] = static_cast<T>(s);
+        return s;
+    };
+    auto grid_index = [&](int c) {
+        size_t g = (size_t)(ox + c % tile);
+        if (DA >= 2) g += (size_t)n * (size_t)(oy + (c / tile) % tile);
+        if (DA == 3) g += (size_t)n * (size_t)n * (size_t)(oz + c / (tile * tile));
+        return g;
+    };
+    if (cells >= kBlock) {
+        for (int c = (int)threadIdx.x; c < cells; c += kBlock)
+            grid[grid_index(c)] = static_cast<T>(cell_sum(c, p0, 1));
+        return;
+    }
+    const int S = kBlock / cells;  // cells is a power of two below kBlock
+    const int c = (int)threadIdx.x % cells, split = (int)threadIdx.x / cells;
+    part[threadIdx.x] = cell_sum(c, p0 + split, S);
+    __syncthreads();
+    if (split == 0) {
+        double s = part[c];
+        for (int k = 1; k < S; ++k) s += part[k * cells + c];
+        grid[grid_index(c)] = static_cast<T>(s);
     }
 }
 
@@ -1433,11 +1456,6 @@ int cell_point_splits(int dA, int W) {
 }
 int combine_span() { return kCombineSpan; }
 int permute_span() { return kPermuteSpan; }
-int fold_tiles_per_block(int tile, int dA) {
-    int cells = tile;
-    for (int t = 1; t < dA; ++t) cells *= tile;
-    return cells >= kBlock ? 1 : kBlock / cells;
-}
 int block_threads() { return kBlock; }
 
 void run_group(const BatchGroup &g, int precision, const WinInst *insts, hipStream_t s) {
