@@ -139,6 +139,9 @@ struct WindowPlan {
     DevBuf tiles_ne;    // dense regime: int32 ids of the non-empty tiles
     DevBuf fold_pairs;  // int2 {non-empty tile k, packed region offsets}, grouped by tile
     DevBuf fold_start;  // int32 [n_tiles + 1] offsets into fold_pairs
+    DevBuf fold_tiles;  // int32 fold workgroup order: tiles with regions (die-grouped, -1
+                        // padded to fold_act entries), then the tiles without
+    int32_t fold_act = 0, fold_len = 0;
     int64_t n_pairs = 0;
     size_t region_elems() const {
         size_t L = (size_t)tile + 2 * m - 1, v = L;
@@ -196,6 +199,7 @@ struct WinInst {
     const int32_t *src_sub;     // regions of each non-empty tile
     const int2 *fold_pairs;
     const int32_t *fold_start;
+    const int32_t *fold_tiles;
     const void *poly;
     const void *bconv;
     const void *twiddle;
@@ -208,6 +212,7 @@ struct WinInst {
     int32_t n, tile, tpd, pad0;
     int32_t vol, n_sub, n_nonempty, n_tiles;
     int32_t n_regions, N, dA, width;
+    int32_t fold_act, fold_len;  // entries of fold_tiles: tiles with regions, all
 };
 
 // One output column of the combine kernel.
@@ -301,6 +306,7 @@ int cell_tile(int dA);
 int cell_threads_per_cell(int dA);
 bool cell_width_supported(int dA, int W);
 int cell_point_splits(int dA, int W);
+int fold_blocks(const WinInst &w);  // fold workgroups of an instance
 int combine_span();
 int permute_span();
 int block_threads();

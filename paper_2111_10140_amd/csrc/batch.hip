@@ -115,6 +115,9 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
                 wi.src_sub = w.src_sub.as<int32_t>();
                 wi.fold_pairs = w.fold_pairs.as<int2>();
                 wi.fold_start = w.fold_start.as<int32_t>();
+                wi.fold_tiles = w.fold_tiles.as<int32_t>();
+                wi.fold_act = w.fold_act;
+                wi.fold_len = w.fold_len;
                 wi.poly = w.poly.ptr;
                 wi.bconv = w.bconv.ptr;
                 wi.twiddle = w.twiddle.ptr;
@@ -215,7 +218,7 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
     add_stage(
         kStageFold, [](const WinInst &w) { return std::make_tuple(w.dA, 0, 0, 0, 0, 0); },
         [](const WinInst &w, int &b) {
-            b = w.n_tiles;  // one workgroup per tile
+            b = fold_blocks(w);
             return true;
         },
         [](BatchGroup &g, const WinInst &w) { g.dA = w.dA; });

@@ -1057,11 +1057,14 @@ __global__ __launch_bounds__(kBlock) void tile_sum_kernel(const WinInst *__restr
 // congruent to b + c mod n, b the tile origin's offset in the region).
 // Writes every grid point, so no zero fill is needed.
 constexpr int kFoldBatch = 8;  // region reads in flight per thread
-constexpr int kDies = 8;       // accelerator dies (XCDs), one L2 each
+constexpr int kFoldZeroPasses = 4;  // zeroing workgroups: passes of the threads over tiles
 
-// One workgroup per tile of the grid.  A small tile's cells get S threads
-// each: thread s of a cell adds regions s, s + S, s + 2S, ... of the tile's
-// list, and the S partial sums are then added in order of s.
+// One workgroup per tile that receives regions, in the plan's order
+// (entries -1 are padding).  A small tile's cells get S threads each:
+// thread s of a cell adds regions s, s + S, s + 2S, ... of the tile's list,
+// and the S partial sums are then added in order of s.  The remaining
+// workgroups zero the tiles that receive no region, kFoldZeroPasses passes
+// of the threads over tiles each.
 template <typename T, int DA>
 __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict__ insts,
                                                       const int32_t *__restrict__ members,
@@ -1079,14 +1082,27 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
     int cells = tile;
     if (DA >= 2) cells *= tile;
     if (DA == 3) cells *= tile;
-    // workgroups go to the chip's 8 dies (each with its own L2) in turn, so
-    // the tiles of one die form one contiguous slab and neighbouring tiles,
-    // which read the same regions, share an L2
-    const int nt = wi.n_tiles;
-    const int d = nt % kDies == 0 ? (loc.lb % kDies) * (nt / kDies) + loc.lb / kDies : loc.lb;
-    const int ox = (d % tpd) * tile;
-    const int oy = ((d / tpd) % tpd) * tile;
-    const int oz = (d / (tpd * tpd)) * tile;
+    auto grid_index = [&](int d, int c) {
+        size_t g = (size_t)((d % tpd) * tile + c % tile);
+        if (DA >= 2) g += (size_t)n * (size_t)(((d / tpd) % tpd) * tile + (c / tile) % tile);
+        if (DA == 3)
+            g += (size_t)n * (size_t)n * (size_t)((d / (tpd * tpd)) * tile + c / (tile * tile));
+        return g;
+    };
+    if (loc.lb >= wi.fold_act) {
+        const int per = cells >= kBlock ? 1 : kBlock / cells;  // tiles per pass of the threads
+        const int first = wi.fold_act + (loc.lb - wi.fold_act) * per * kFoldZeroPasses;
+        const int last = min(first + per * kFoldZeroPasses, wi.fold_len);
+        const int c0 = cells >= kBlock ? (int)threadIdx.x : (int)threadIdx.x % cells;
+        const int cstep = cells >= kBlock ? kBlock : cells;
+        for (int e = first + (cells >= kBlock ? 0 : (int)threadIdx.x / cells); e < last; e += per) {
+            const int dz = wi.fold_tiles[e];
+            for (int c = c0; c < cells; c += cstep) grid[grid_index(dz, c)] = T(0);
+        }
+        return;
+    }
+    const int d = wi.fold_tiles[loc.lb];
+    if (d < 0) return;  // padding (the whole workgroup)
     const int p0 = wi.fold_start[d], p1 = wi.fold_start[d + 1];
     // sum over regions first, first + stride, ... of cell c
     auto cell_sum = [&](int c, int first, int stride) {
@@ -1130,15 +1146,9 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
         }
         return s;
     };
-    auto grid_index = [&](int c) {
-        size_t g = (size_t)(ox + c % tile);
-        if (DA >= 2) g += (size_t)n * (size_t)(oy + (c / tile) % tile);
-        if (DA == 3) g += (size_t)n * (size_t)n * (size_t)(oz + c / (tile * tile));
-        return g;
-    };
     if (cells >= kBlock) {
         for (int c = (int)threadIdx.x; c < cells; c += kBlock)
-            grid[grid_index(c)] = static_cast<T>(cell_sum(c, p0, 1));
+            grid[grid_index(d, c)] = static_cast<T>(cell_sum(c, p0, 1));
         return;
     }
     const int S = kBlock / cells;  // cells is a power of two below kBlock
@@ -1148,7 +1158,7 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
     if (split == 0) {
         double s = part[c];
         for (int k = 1; k < S; ++k) s += part[k * cells + c];
-        grid[grid_index(c)] = static_cast<T>(s);
+        grid[grid_index(d, c)] = static_cast<T>(s);
     }
 }
 
@@ -1447,6 +1457,12 @@ int cell_threads_per_cell(int dA) {
 }
 bool cell_width_supported(int dA, int W) {
     return dA == 3 ? (W <= 6 || W == 8 || W == 12) : (dA == 2 ? W <= 8 : W <= 16);
+}
+int fold_blocks(const WinInst &w) {
+    int cells = w.tile;
+    for (int t = 1; t < w.dA; ++t) cells *= w.tile;
+    const int per = (cells >= kBlock ? 1 : kBlock / cells) * kFoldZeroPasses;
+    return w.fold_act + (w.fold_len - w.fold_act + per - 1) / per;
 }
 int cell_point_splits(int dA, int W) {
     // lanes of a cell that split its points (the wide 3-D kernels split the

@@ -556,6 +556,24 @@ void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int p
         w.n_pairs = (int64_t)pairs.size();
         upload(w.fold_pairs, pairs);
         upload(w.fold_start, fstart);
+        // fold workgroup order: workgroups go to the chip's 8 dies in turn,
+        // so the tiles that receive regions are split into 8 runs by tile
+        // id, workgroup b taking entry b / 8 of run b % 8: each die folds
+        // one slab of neighbouring tiles, which read the same regions
+        // through its L2; the tiles that receive none follow, to be zeroed
+        std::vector<int32_t> act, idle;
+        for (int64_t t = 0; t < w.n_tiles; ++t)
+            (fstart[t + 1] > fstart[t] ? act : idle).push_back((int32_t)t);
+        const int64_t run = ((int64_t)act.size() + 7) / 8;
+        std::vector<int32_t> order(8 * run, -1);
+        for (int64_t b = 0; b < 8 * run; ++b) {
+            const int64_t pos = (b % 8) * run + b / 8;
+            if (pos < (int64_t)act.size()) order[b] = act[pos];
+        }
+        w.fold_act = (int32_t)order.size();
+        order.insert(order.end(), idle.begin(), idle.end());
+        w.fold_len = (int32_t)order.size();
+        upload(w.fold_tiles, order);
     }
     // window polynomial table at the precision's fixed degree; its error
     // perturbs every weight, counted (per dimension, spread and gather) in
@@ -694,7 +712,7 @@ size_t anova::plan_device_bytes(const anova_plan_s *p) {
       for (const WindowPlan &w : *ws)
         for (const DevBuf *d : {&w.nodes, &w.perm, &w.subs, &w.poly, &w.bconv, &w.twiddle,
                                 &w.src_sub, &w.cell_start, &w.tiles_ne, &w.fold_pairs,
-                                &w.fold_start})
+                                &w.fold_start, &w.fold_tiles})
             b += d->bytes;
     if (p->mv_batch) b += p->mv_batch->device_bytes();
     return b;
