@@ -123,6 +123,7 @@ struct WindowPlan {
     int poly_deg = 0;
     bool dense = false;          // per-cell register accumulation (see kernels.hip)
     int chunks = 1;              // dense regime: workgroups per tile
+    int launch_windows = 1;      // windows whose launches share the device (the plan's)
     std::vector<int32_t> chunk_start;  // dense regime: first workgroup of each non-empty tile
     std::vector<int32_t> tile_order;   // dense regime: non-empty tiles in launch order
     int64_t n_points = 0;
@@ -306,6 +307,7 @@ int cell_tile(int dA);
 int cell_threads_per_cell(int dA);
 bool cell_width_supported(int dA, int W);
 int cell_point_splits(int dA, int W);
+int cell_resident_blocks(int dA, int W);  // per-cell spreading workgroups held at once
 int fold_blocks(const WinInst &w);  // fold workgroups of an instance
 int combine_span();
 int permute_span();

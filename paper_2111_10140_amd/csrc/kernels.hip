@@ -24,6 +24,9 @@
 // kernel adds the regions into the grid in a fixed order.  No floating-point
 // atomics are used, so a product is bitwise reproducible.  Gathering writes
 // each point's value at its position in the caller's order.
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 #include "anova_internal.h"
@@ -1392,6 +1395,21 @@ void gather_cell_launch(const BatchGroup &g, const WinInst *insts, hipStream_t s
         default: throw Error{ANOVA_E_INVALID, "d_A out of range"};                      \
     }
 
+template <int DA, int W>
+int spread_cell_blocks_per_cu() {
+    int nb = 0;
+    if constexpr (DA == 3 && (W == 8 || W == 12)) {
+        ANOVA_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, reinterpret_cast<const void *>(spread_wide_kernel<W>), kWideThreads, 0));
+    } else if constexpr (cell_supported<DA, W>()) {
+        constexpr int TILE = CellTileOf<DA>::value;
+        constexpr int S = kBlock / CellShape<DA, TILE>::cells;
+        ANOVA_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, reinterpret_cast<const void *>(spread_cell_kernel<DA, W, TILE, S>), kBlock, 0));
+    }
+    return nb;
+}
+
 template <typename T>
 void spread_group(const BatchGroup &g, const WinInst *insts, hipStream_t s) {
     if (g.cell) {
@@ -1463,6 +1481,22 @@ int fold_blocks(const WinInst &w) {
     for (int t = 1; t < w.dA; ++t) cells *= w.tile;
     const int per = (cells >= kBlock ? 1 : kBlock / cells) * kFoldZeroPasses;
     return w.fold_act + (w.fold_len - w.fold_act + per - 1) / per;
+}
+int cell_resident_blocks(int dA, int W) {
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int>, int> cache;
+    int dev = 0;
+    ANOVA_HIP_CHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    const auto key = std::make_tuple(dev, dA, W);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int nb = 0, cus = 0;
+    ANOVA_DA_SWITCH(dA, ANOVA_W_SWITCH(W, (nb = spread_cell_blocks_per_cu<DA_, W_>())));
+    ANOVA_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int r = std::max(1, nb) * std::max(1, cus);
+    cache[key] = r;
+    return r;
 }
 int cell_point_splits(int dA, int W) {
     // lanes of a cell that split its points (the wide 3-D kernels split the

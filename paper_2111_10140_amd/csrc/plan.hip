@@ -222,6 +222,31 @@ std::vector<double> fit_window_polys(int m, double b, int deg, double &err_out) 
     return coef;
 }
 
+// ------------------------------------------------------------- per-cell launch model
+// A per-cell launch of B workgroups runs in ceil(B / R) rounds of the R
+// workgroups the device holds at once; a round lasts as long as its
+// workgroups' largest per-lane share of one cell's points (a chunk of K
+// takes 1/K of every cell of its tile, split over S lanes) plus a fixed part
+// per workgroup (set-up, flush and region sum, about four points' worth,
+// as measured on the 3-D m = 3 kernels).  Returns
+// the K in 1..256 with the shortest modelled time (ties: fewer chunks).
+static int best_chunks(int64_t tiles, int64_t maxcnt, int S, int64_t R, double &time) {
+    int bestK = 1;
+    double best = std::numeric_limits<double>::infinity();
+    const int kmax = (int)std::max<int64_t>(1, std::min<int64_t>(256, maxcnt / std::max(S, 1)));
+    for (int K = 1; K <= kmax; ++K) {
+        const int64_t rounds = (tiles * K + R - 1) / R;
+        const int64_t share = ((int64_t)S * K);
+        const double t = (double)rounds * (double)((maxcnt + share - 1) / share + 4);
+        if (t < best) {
+            best = t;
+            bestK = K;
+        }
+    }
+    time = best;
+    return bestK;
+}
+
 // ------------------------------------------------------------- parameter choice
 struct Choice {
     double h;
@@ -247,7 +272,7 @@ struct Choice {
 // per-thread overheads), so only the measured choice (tune) takes it when
 // it runs faster.
 std::vector<Choice> candidates(const anova_params &prm, double D, int dA, double budget,
-                               int64_t N) {
+                               int64_t N, int share) {
     const int prec = prm.precision;
     double h0;
     if (prm.h > 0) {
@@ -264,23 +289,29 @@ std::vector<Choice> candidates(const anova_params &prm, double D, int dA, double
         c.n = n;
         c.e_img = est_images(h, D, prm.ell, dA);
         const double rest = std::max(budget - c.e_img, budget * 0.5);
-        const double avail = rest - est_round(prec, n, 8, dA);
-        if (avail <= 0) return false;
-        int M = prm.M;
-        if (M <= 0) {
-            for (M = 4; M <= n; M += 2)
-                if (est_trunc(M, h, prm.ell, dA) <= 0.35 * avail) break;
-            if (M > n) return false;
-        }
-        if (M > n) return false;
-        if (prm.M <= 0 && M * 5 > n * 4) return false;  // keep sigma = n/M >= 1.25
+        if (prm.M > n) return false;
+        // the smallest m, then the smallest M (sigma = n/M >= 1.25 unless M
+        // is given), whose truncation, window and rounding estimates
+        // together fit what the images leave: truncation falls and the
+        // window error grows with M, so the M that fit form one run
         for (int m = 2; m <= 8; ++m) {
             if (prm.m > 0 && m != prm.m) continue;
             if (2 * m > n) break;
-            if (est_window(M, n, m, prm.ell, h, dA) > 0.65 * avail) continue;
-            c.M = M;
-            c.m = m;
-            return true;
+            const double avail = rest - est_round(prec, n, m, dA);
+            if (avail <= 0) continue;
+            const int M0 = prm.M > 0 ? prm.M : 4;
+            const int M1 = prm.M > 0 ? prm.M : (4 * n) / 5;
+            for (int M = M0; M <= M1; M += 2) {
+                const double et = est_trunc(M, h, prm.ell, dA);
+                if (et > avail) continue;
+                if (et + est_window(M, n, m, prm.ell, h, dA) > avail) {
+                    if (et < 1e-3 * avail) break;  // only the window error grows from here
+                    continue;
+                }
+                c.M = M;
+                c.m = m;
+                return true;
+            }
         }
         return false;
     };
@@ -320,7 +351,25 @@ std::vector<Choice> candidates(const anova_params &prm, double D, int dA, double
                 const double h1 = n * D / ((k1 - 1) * T * (1.0 - 4e-5));
                 if (search(h1, n, a) && per_cell_likely(a, n * D / h1)) {
                     a.align = T;
-                    a.cost = cost(a, 1.0) * (1.0 + 1e-9);  // ties go to the plain variant
+                    // the launch model on uniformly spread points: the
+                    // centred points end inside edge tiles, whose idle lanes
+                    // still take a workgroup's time; the aligned ones fill
+                    // k1 - 1 tiles per dimension
+                    const double lo = 0.5 * n - 0.5 * span;
+                    const int64_t tp = (int64_t)std::floor((lo + span) / T - 1e-9) -
+                                       (int64_t)std::floor(lo / T) + 1;
+                    auto launch_time = [&](const Choice &x, int64_t tiles_dim, double sp) {
+                        const double avg = (double)N / std::pow(std::max(sp, 1.0), dA);
+                        const int64_t maxcnt = (int64_t)std::ceil(avg + 3.0 * std::sqrt(avg));
+                        const int64_t tiles = (int64_t)std::pow((double)tiles_dim, dA) * share;
+                        double t = 0.0;
+                        best_chunks(tiles, maxcnt, cell_point_splits(dA, 2 * x.m),
+                                    cell_resident_blocks(dA, 2 * x.m), t);
+                        return t * std::pow(2.0 * x.m, dA);
+                    };
+                    const bool better = launch_time(a, k1 - 1, n * D / h1) < launch_time(c, tp, span);
+                    // placed just before or after the plain variant
+                    a.cost = c.cost * (better ? 1.0 - 1e-9 : 1.0 + 1e-9);
                     out.push_back(a);
                 }
             }
@@ -505,15 +554,15 @@ void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int p
         // workgroups (chunks) per tile: a thread handles its cell's share of
         // one chunk, so a workgroup takes as long as its fullest cell; tiles
         // at the edge of the data still hold full cells, so every tile gets
-        // the same count: about 12 points per thread of an average occupied
-        // cell (4 threads per cell in 3-D), and at least ~512 workgroups
-        // when the points allow
-        const double per_cell = (double)N / (double)std::max<size_t>(nocc, 1);
-        const int S = cell_point_splits(dA, 2 * m);
-        int K = (int)std::lround(per_cell / (12.0 * S));
-        K = std::max(K, (int)((512 + ne.size() - 1) / std::max<size_t>(ne.size(), 1)));
-        K = std::min(K, std::max(1, (int)(per_cell / S)));
-        K = std::max(1, std::min(K, 256));
+        // the same count, the one the launch model (best_chunks) finds
+        // fastest for this window's tiles and fullest cell, with the plan's
+        // windows sharing the device
+        int64_t maxcnt = 0;
+        for (int64_t k = 0; k < nkeys; ++k) maxcnt = std::max(maxcnt, kstart[k + 1] - kstart[k]);
+        double model_time = 0.0;
+        const int K = best_chunks((int64_t)ne.size() * std::max(1, w.launch_windows), maxcnt,
+                                  cell_point_splits(dA, 2 * m), cell_resident_blocks(dA, 2 * m),
+                                  model_time);
         std::vector<int32_t> cstart(ne.size() + 1);
         for (size_t k = 0; k <= ne.size(); ++k) cstart[k] = (int32_t)(k * K);
         w.chunk_start = cstart;
@@ -761,21 +810,26 @@ static void build_for(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, i
 
 // Device time of one product of a one-window plan (the best of 3 after a
 // warm-up), on a stream of its own.
-static double time_window(anova_plan_s &one, const double *alpha, double *out) {
+// Product time of a one-window plan launched `copies` times together, as the
+// plan's windows share their launches (out: copies columns of one.N).
+static double time_window(anova_plan_s &one, const double *alpha, double *out, int copies) {
     hipStream_t s = nullptr;
     ANOVA_HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     hipEvent_t e0 = nullptr, e1 = nullptr;
     float best = std::numeric_limits<float>::infinity();
     try {
         Batch b;
-        BatchProblem bp;
-        bp.plan = &one;
-        bp.alpha = alpha;
-        bp.out = out;
-        bp.nrhs = 1;
-        bp.ld = one.N;
-        bp.beta = 1.0;
-        b.build({bp});
+        std::vector<BatchProblem> bps((size_t)std::max(copies, 1));
+        for (size_t k = 0; k < bps.size(); ++k) {
+            BatchProblem &bp = bps[k];
+            bp.plan = &one;
+            bp.alpha = alpha;
+            bp.out = out + (size_t)k * (size_t)one.N;
+            bp.nrhs = 1;
+            bp.ld = one.N;
+            bp.beta = 1.0;
+        }
+        b.build(bps);
         ANOVA_HIP_CHECK(hipEventCreate(&e0));
         ANOVA_HIP_CHECK(hipEventCreate(&e1));
         b.run(s);
@@ -838,7 +892,8 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
                 D = std::max(D, hi[t] - lo[t]);
             }
             w.extent = D;
-            const std::vector<Choice> cands = candidates(*prm, D, w.dA, budget, N);
+            w.launch_windows = P;
+            const std::vector<Choice> cands = candidates(*prm, D, w.dA, budget, N, P);
             for (const Choice &c : cands)
                 ANOVA_REQUIRE(c.h > D || (D == 0 && c.h > 0),
                               "h must exceed the extent of the points");
@@ -850,10 +905,11 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
             }
             // measured choice: build the cheapest candidates (model cost
             // within 8x of the cheapest, at most 4) on these points and keep
-            // the one whose product runs fastest
+            // the one whose product runs fastest, timed with P copies of the
+            // window in each launch as the plan's P windows will be
             if (!tune_alpha.ptr) {
                 upload(tune_alpha, std::vector<double>((size_t)N, 1.0));
-                tune_out.alloc((size_t)N * sizeof(double));
+                tune_out.alloc((size_t)N * (size_t)P * sizeof(double));
             }
             double best_t = std::numeric_limits<double>::infinity();
             for (size_t k = 0; k < cands.size() && k < 4; ++k) {
@@ -864,11 +920,13 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
                 one.win.resize(1);
                 WindowPlan &v = one.win[0];
                 v.dA = w.dA; v.eta = w.eta; v.extent = w.extent;
+                v.launch_windows = w.launch_windows;  // chunks as in the full plan
                 for (int t = 0; t < 3; ++t) v.feat[t] = w.feat[t];
                 set_centers(v, cands[k], lo, hi, *prm);
                 apply_choice(v, cands[k], *prm);
                 build_for(v, Xh, N, ldx, prm->precision);
-                const double t = time_window(one, tune_alpha.as<double>(), tune_out.as<double>());
+                const double t =
+                    time_window(one, tune_alpha.as<double>(), tune_out.as<double>(), P);
                 if (t < best_t) {
                     best_t = t;
                     w = std::move(v);
