@@ -97,33 +97,37 @@ __device__ __forceinline__ void window_weights(const T *__restrict__ poly, T f, 
 
 // The window polynomials held in registers for a whole kernel (the kernels
 // store to global memory inside their loops, so reading the table through a
-// pointer there would be reloaded after every store).
+// pointer there would be reloaded after every store).  The window is even,
+// so the polynomial of offset W-1-a at z equals that of offset a at -z:
+// only the lower half is held, and split into its even and odd parts in z,
+// p(z) = E(z^2) + z O(z^2), it gives both weights of the pair (a, W-1-a),
+// E + zO and E - zO, for about half the multiply-adds of two evaluations.
 template <typename T, int W>
 struct WinPoly {
-    static constexpr int D = PolyDeg<T>::value;
-    T c[W][D + 1];
+    static constexpr int D = PolyDeg<T>::value, H = W / 2;
+    static_assert(W % 2 == 0, "supports of 2m points");
+    T c[H][D + 1];
     __device__ __forceinline__ void load(const T *__restrict__ poly) {
 #pragma unroll
-        for (int a = 0; a < W; ++a)
+        for (int a = 0; a < H; ++a)
 #pragma unroll
             for (int k = 0; k <= D; ++k) c[a][k] = uniform(poly[a * (D + 1) + k]);
     }
-    __device__ __forceinline__ void eval(T f, T (&w)[W]) const {
-        const T z = T(2) * f - T(1);
+    // weights of offsets a and W-1-a at z (z2 = z * z)
+    __device__ __forceinline__ void pair(T z, T z2, int a, T &lo, T &hi) const {
+        constexpr int KE = D - D % 2, KO = D - 1 + D % 2;  // highest even / odd power
+        T e = c[a][KE], o = c[a][KO];
 #pragma unroll
-        for (int a = 0; a < W; ++a) w[a] = c[a][D];
+        for (int k = KE - 2; k >= 0; k -= 2) e = e * z2 + c[a][k];
 #pragma unroll
-        for (int k = D - 1; k >= 0; --k) {
-#pragma unroll
-            for (int a = 0; a < W; ++a) w[a] = w[a] * z + c[a][k];
-        }
+        for (int k = KO - 2; k >= 1; k -= 2) o = o * z2 + c[a][k];
+        lo = e + z * o;
+        hi = e - z * o;
     }
-    // weight of offset a alone, at the mapped argument z = 2f - 1
-    __device__ __forceinline__ T eval_one(T z, int a) const {
-        T v = c[a][D];
+    __device__ __forceinline__ void eval(T f, T (&w)[W]) const {
+        const T z = T(2) * f - T(1), z2 = z * z;
 #pragma unroll
-        for (int k = D - 1; k >= 0; --k) v = v * z + c[a][k];
-        return v;
+        for (int a = 0; a < H; ++a) pair(z, z2, a, w[a], w[W - 1 - a]);
     }
 };
 
@@ -381,15 +385,23 @@ __global__ __launch_bounds__(kBlock) void spread_cell_kernel(const WinInst *__re
         float wx[W], wy[W];
         wp.eval(r.x, wx);
         if constexpr (DA >= 2) wp.eval(r.y, wy);
-        const float zz = 2.0f * r.z - 1.0f;
+        const float zz = 2.0f * r.z - 1.0f, zz2 = zz * zz;
+        // z planes in mirror pairs (c, W-1-c), two weights per evaluation:
+        // fewer live registers than all W at once
 #pragma unroll
-        for (int c = 0; c < WZ; ++c) {
-            const float wc = DA == 3 ? a * wp.eval_one(zz, c) : a;
+        for (int c2 = 0; c2 < (WZ + 1) / 2; ++c2) {
+            float wlo = 1.0f, whi = 1.0f;
+            if constexpr (DA == 3) wp.pair(zz, zz2, c2, wlo, whi);
 #pragma unroll
-            for (int b = 0; b < WY; ++b) {
-                const float wbc = DA >= 2 ? wc * wy[b] : wc;
+            for (int h = 0; h < (DA == 3 ? 2 : 1); ++h) {
+                const int c = h == 0 ? c2 : WZ - 1 - c2;
+                const float wc = a * (h == 0 ? wlo : whi);
 #pragma unroll
-                for (int i = 0; i < W; ++i) acc[c][b][i] = fmaf(wbc, wx[i], acc[c][b][i]);
+                for (int b = 0; b < WY; ++b) {
+                    const float wbc = DA >= 2 ? wc * wy[b] : wc;
+#pragma unroll
+                    for (int i = 0; i < W; ++i) acc[c][b][i] = fmaf(wbc, wx[i], acc[c][b][i]);
+                }
             }
         }
     }
