@@ -134,6 +134,7 @@ struct WindowPlan {
     DevBuf subs;     // SubProblem[n_sub]
     DevBuf poly;     // window polynomial table [2m][poly_deg+1] (float or double)
     DevBuf bconv;    // per-axis multiplier, n entries (float or double)
+    DevBuf ctaps;    // its inverse transform: real, even circular-convolution taps, n entries
     DevBuf twiddle;  // n/2 complex exp(-2 pi i j / n) (float2 or double2)
     DevBuf src_sub;     // int32 [n_nonempty + 1]: spread regions of the k-th non-empty tile
     DevBuf cell_start;  // dense regime: int32 [cells + 1] sorted-point offsets per (tile, cell)
@@ -203,6 +204,7 @@ struct WinInst {
     const int32_t *fold_tiles;
     const void *poly;
     const void *bconv;
+    const void *ctaps;
     const void *twiddle;
     const double *alpha;        // input column, caller's order
     void *priv;                 // spread regions
@@ -307,6 +309,7 @@ int cell_tile(int dA);
 int cell_threads_per_cell(int dA);
 bool cell_width_supported(int dA, int W);
 int cell_point_splits(int dA, int W);
+bool convolve_direct(int n, int dA);  // small grids: circular convolution by taps, planes then z
 int cell_resident_blocks(int dA, int W);  // per-cell spreading workgroups held at once
 int fold_blocks(const WinInst &w);  // fold workgroups of an instance
 int combine_span();

@@ -120,6 +120,7 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
                 wi.fold_len = w.fold_len;
                 wi.poly = w.poly.ptr;
                 wi.bconv = w.bconv.ptr;
+                wi.ctaps = w.ctaps.ptr;
                 wi.twiddle = w.twiddle.ptr;
                 wi.alpha = ci.alpha;
                 wi.grid = bp.grid_override;  // patched below when owned
@@ -222,12 +223,18 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
             return true;
         },
         [](BatchGroup &g, const WinInst &w) { g.dA = w.dA; });
-    // convolve, one pass per axis
-    for (int axis = 0; axis < 3; ++axis) {
+    // convolve: per axis by FFT, or (small grids of 2 or 3 dimensions) by
+    // direct taps, axes 0 and 1 by planes, then axis 2
+    for (int pass = 0; pass < 3; ++pass) {
         add_stage(
             kStageConvolve, [](const WinInst &w) { return std::make_tuple(w.n, w.dA, 0, 0, 0, 0); },
-            [axis](const WinInst &w, int &b) {
-                if (axis >= w.dA) return false;
+            [pass](const WinInst &w, int &b) {
+                if (pass >= w.dA) return false;
+                if (convolve_direct(w.n, w.dA)) {
+                    if (pass == 1) return false;  // done with axis 0
+                    b = pass == 0 && w.dA == 2 ? 1 : w.n;  // planes, or columns of one y
+                    return true;
+                }
                 int nlines = 1;
                 for (int t = 1; t < w.dA; ++t) nlines *= w.n;
                 const int nq = (nlines + 1) / 2;
@@ -235,9 +242,9 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
                 b = (nq + np - 1) / np;
                 return true;
             },
-            [axis](BatchGroup &g, const WinInst &w) {
+            [pass](BatchGroup &g, const WinInst &w) {
                 g.n = w.n;
-                g.axis = axis;
+                g.axis = convolve_direct(w.n, w.dA) ? (pass == 0 ? -1 : -2) : pass;
                 // instances of one group share n and d_A, hence the line count
                 int nlines = 1;
                 for (int t = 1; t < w.dA; ++t) nlines *= w.n;

@@ -1178,11 +1178,66 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
 }
 
 // ------------------------------------------------------------------ convolve
+// Forward FFT, multiplication by the real, even per-axis multiplier and
+// inverse FFT of NP complex lines of length n held in LDS (src; dst is
+// scratch): radix-2 Stockham.  Because the multiplier is real and even,
+// filtering x + i y equals filtering x and y separately, so each complex
+// line carries two real lines.  Returns the buffer that holds the result.
+template <typename T, int LOGN>
+__device__ __forceinline__ typename Cplx<T>::type *filter_lines(typename Cplx<T>::type *src,
+                                                                typename Cplx<T>::type *dst,
+                                                                int NP, const T *__restrict__ bconv,
+                                                                const typename Cplx<T>::type *__restrict__ tw) {
+    using C = typename Cplx<T>::type;
+    constexpr int n = 1 << LOGN;
+    // forward transform, X_k = sum_u x_u exp(-2 pi i k u / n)
+    for (int Ns = 1; Ns < n; Ns <<= 1) {
+        for (int e = threadIdx.x; e < NP * (n / 2); e += blockDim.x) {
+            const int ql = e >> (LOGN - 1), j = e & (n / 2 - 1);
+            const int k = j & (Ns - 1);
+            const C a = src[ql * n + j];
+            const C b0 = src[ql * n + j + n / 2];
+            const C w = tw[k * (n / (2 * Ns))];
+            C b;
+            b.x = b0.x * w.x - b0.y * w.y;
+            b.y = b0.x * w.y + b0.y * w.x;
+            const int idx = ((j - k) << 1) + k;
+            dst[ql * n + idx] = C{a.x + b.x, a.y + b.y};
+            dst[ql * n + idx + Ns] = C{a.x - b.x, a.y - b.y};
+        }
+        __syncthreads();
+        C *t = src; src = dst; dst = t;
+    }
+    for (int e = threadIdx.x; e < NP * n; e += blockDim.x) {
+        const T f = bconv[e & (n - 1)];
+        C v = src[e];
+        v.x *= f; v.y *= f;
+        src[e] = v;
+    }
+    __syncthreads();
+    // inverse transform (conjugate twiddles, no 1/n: folded into the multiplier)
+    for (int Ns = 1; Ns < n; Ns <<= 1) {
+        for (int e = threadIdx.x; e < NP * (n / 2); e += blockDim.x) {
+            const int ql = e >> (LOGN - 1), j = e & (n / 2 - 1);
+            const int k = j & (Ns - 1);
+            const C a = src[ql * n + j];
+            const C b0 = src[ql * n + j + n / 2];
+            const C w = tw[k * (n / (2 * Ns))];
+            C b;
+            b.x = b0.x * w.x + b0.y * w.y;
+            b.y = b0.y * w.x - b0.x * w.y;
+            const int idx = ((j - k) << 1) + k;
+            dst[ql * n + idx] = C{a.x + b.x, a.y + b.y};
+            dst[ql * n + idx + Ns] = C{a.x - b.x, a.y - b.y};
+        }
+        __syncthreads();
+        C *t = src; src = dst; dst = t;
+    }
+    return src;
+}
+
 // One pass along `axis` (element stride n^axis) of the n^d_A real grid of
-// each instance: two real lines form one complex line; radix-2 Stockham FFT
-// in LDS, multiplication by the real, even per-axis multiplier, inverse FFT.
-// Because the multiplier is real and even, filtering x + i y equals
-// filtering x and y separately.  NP complex lines per workgroup.
+// each instance, NP complex lines (2 NP real lines) per workgroup.
 template <typename T, int LOGN>
 __global__ __launch_bounds__(kBlock) void convolve_kernel(const WinInst *__restrict__ insts,
                                                           const int32_t *__restrict__ members,
@@ -1218,57 +1273,75 @@ __global__ __launch_bounds__(kBlock) void convolve_kernel(const WinInst *__restr
         bufA[ql * n + u] = v;
     }
     __syncthreads();
-    C *src = bufA, *dst = bufB;
-    // forward transform, X_k = sum_u x_u exp(-2 pi i k u / n)
-    for (int Ns = 1; Ns < n; Ns <<= 1) {
-        for (int e = threadIdx.x; e < NP * (n / 2); e += kBlock) {
-            const int ql = e >> (LOGN - 1), j = e & (n / 2 - 1);
-            const int k = j & (Ns - 1);
-            const C a = src[ql * n + j];
-            const C b0 = src[ql * n + j + n / 2];
-            const C w = tw[k * (n / (2 * Ns))];
-            C b;
-            b.x = b0.x * w.x - b0.y * w.y;
-            b.y = b0.x * w.y + b0.y * w.x;
-            const int idx = ((j - k) << 1) + k;
-            dst[ql * n + idx] = C{a.x + b.x, a.y + b.y};
-            dst[ql * n + idx + Ns] = C{a.x - b.x, a.y - b.y};
-        }
-        __syncthreads();
-        C *t = src; src = dst; dst = t;
-    }
-    for (int e = threadIdx.x; e < NP * n; e += kBlock) {
-        const T f = bconv[e & (n - 1)];
-        C v = src[e];
-        v.x *= f; v.y *= f;
-        src[e] = v;
-    }
-    __syncthreads();
-    // inverse transform (conjugate twiddles, no 1/n: folded into the multiplier)
-    for (int Ns = 1; Ns < n; Ns <<= 1) {
-        for (int e = threadIdx.x; e < NP * (n / 2); e += kBlock) {
-            const int ql = e >> (LOGN - 1), j = e & (n / 2 - 1);
-            const int k = j & (Ns - 1);
-            const C a = src[ql * n + j];
-            const C b0 = src[ql * n + j + n / 2];
-            const C w = tw[k * (n / (2 * Ns))];
-            C b;
-            b.x = b0.x * w.x + b0.y * w.y;
-            b.y = b0.y * w.x - b0.x * w.y;
-            const int idx = ((j - k) << 1) + k;
-            dst[ql * n + idx] = C{a.x + b.x, a.y + b.y};
-            dst[ql * n + idx + Ns] = C{a.x - b.x, a.y - b.y};
-        }
-        __syncthreads();
-        C *t = src; src = dst; dst = t;
-    }
+    const C *res = filter_lines<T, LOGN>(bufA, bufB, NP, bconv, tw);
     for (int e = threadIdx.x; e < NP * n; e += kBlock) {
         int ql, u;
         if (contiguous) { ql = e / n; u = e % n; } else { u = e / NP; ql = e % NP; }
         const int r0 = 2 * (q0 + ql), r1 = r0 + 1;
-        const C v = src[ql * n + u];
+        const C v = res[ql * n + u];
         if (r0 < nlines) grid[base_of(r0) + (size_t)u * s] = v.x;
         if (r1 < nlines) grid[base_of(r1) + (size_t)u * s] = v.y;
+    }
+}
+
+// Small grids (n <= 32, d_A >= 2): a pass along one axis is the circular
+// convolution with the real, even taps c_d = sum_k b_k cos(2 pi k d / n) of
+// the multiplier b (its inverse transform, from the plan), n multiply-adds
+// per value and no FFT stages.  The plane kernel does axes 0 and 1 of one
+// n x n plane (plane z = workgroup index in 3-D, the whole grid in 2-D)
+// with the plane in LDS between the passes; the axis-2 kernel takes the n
+// columns of one y (workgroup index) along z.
+template <typename T, int LOGN>
+__global__ __launch_bounds__(kBlock) void convolve_plane_kernel(const WinInst *__restrict__ insts,
+                                                                const int32_t *__restrict__ members,
+                                                                const int32_t *__restrict__ prefix,
+                                                                int cnt) {
+    constexpr int n = 1 << LOGN, NN = n * n;
+    __shared__ T a[NN], b[NN], c[n];
+    const Located loc = locate(insts, members, prefix, cnt);
+    const WinInst &wi = *loc.w;
+    T *__restrict__ plane = static_cast<T *>(wi.grid) + (size_t)loc.lb * NN;
+    const T *__restrict__ taps = static_cast<const T *>(wi.ctaps);
+    for (int e = threadIdx.x; e < NN; e += kBlock) a[e] = plane[e];
+    for (int e = threadIdx.x; e < n; e += kBlock) c[e] = taps[e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < NN; e += kBlock) {  // along x
+        const int x = e & (n - 1), row = e - x;
+        T acc = T(0);
+#pragma unroll
+        for (int u = 0; u < n; ++u) acc += c[(x - u) & (n - 1)] * a[row + u];
+        b[e] = acc;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < NN; e += kBlock) {  // along y
+        const int x = e & (n - 1), y = e >> LOGN;
+        T acc = T(0);
+#pragma unroll
+        for (int v = 0; v < n; ++v) acc += c[(y - v) & (n - 1)] * b[v * n + x];
+        plane[e] = acc;
+    }
+}
+
+template <typename T, int LOGN>
+__global__ __launch_bounds__(kBlock) void convolve_z_kernel(const WinInst *__restrict__ insts,
+                                                            const int32_t *__restrict__ members,
+                                                            const int32_t *__restrict__ prefix,
+                                                            int cnt) {
+    constexpr int n = 1 << LOGN, NN = n * n;
+    __shared__ T a[NN], c[n];  // a[z][x]
+    const Located loc = locate(insts, members, prefix, cnt);
+    const WinInst &wi = *loc.w;
+    T *__restrict__ col = static_cast<T *>(wi.grid) + (size_t)loc.lb * n;  // y = workgroup
+    const T *__restrict__ taps = static_cast<const T *>(wi.ctaps);
+    for (int e = threadIdx.x; e < NN; e += kBlock) a[e] = col[(size_t)(e >> LOGN) * NN + (e & (n - 1))];
+    for (int e = threadIdx.x; e < n; e += kBlock) c[e] = taps[e];
+    __syncthreads();
+    for (int e = threadIdx.x; e < NN; e += kBlock) {
+        const int x = e & (n - 1), z = e >> LOGN;
+        T acc = T(0);
+#pragma unroll
+        for (int v = 0; v < n; ++v) acc += c[(z - v) & (n - 1)] * a[v * n + x];
+        col[(size_t)z * NN + x] = acc;
     }
 }
 
@@ -1279,6 +1352,7 @@ __global__ __launch_bounds__(kBlock) void convolve_kernel(const WinInst *__restr
 // them there: scattered writes, which the caches merge, cost less than the
 // line-sized random reads of reading them back through the inverse
 // permutation).  Blocks: ceil(N / kCombineSpan) per instance.
+constexpr int kConvolveDirectMax = 32;  // largest n convolved by direct taps
 constexpr int kCombinePerThread = 4;
 constexpr int kCombineSpan = kCombinePerThread * kBlock;
 
@@ -1453,6 +1527,24 @@ void fold_group(const BatchGroup &g, const WinInst *insts, hipStream_t s) {
 template <typename T>
 void convolve_group(const BatchGroup &g, const WinInst *insts, hipStream_t s) {
     if (g.blocks <= 0) return;
+    if (g.axis < 0) {  // direct passes: axes 0 and 1 by planes (-1), axis 2 (-2)
+#define ANOVA_DIRECT(LOGN)                                                                      \
+    if (g.axis == -1)                                                                           \
+        hipLaunchKernelGGL((convolve_plane_kernel<T, LOGN>), dim3((unsigned)g.blocks), dim3(kBlock), \
+                           0, s, insts, g.members, g.prefix, g.cnt);                            \
+    else                                                                                        \
+        hipLaunchKernelGGL((convolve_z_kernel<T, LOGN>), dim3((unsigned)g.blocks), dim3(kBlock),   \
+                           0, s, insts, g.members, g.prefix, g.cnt)
+        switch (g.n) {
+            case 8: ANOVA_DIRECT(3); break;
+            case 16: ANOVA_DIRECT(4); break;
+            case 32: ANOVA_DIRECT(5); break;
+            default: throw Error{ANOVA_E_INVALID, "direct convolution takes n <= 32"};
+        }
+#undef ANOVA_DIRECT
+        ANOVA_HIP_CHECK(hipGetLastError());
+        return;
+    }
     const size_t shm = 2 * (size_t)g.np * g.n * sizeof(typename Cplx<T>::type);
 #define ANOVA_CONV(LOGN)                                                                  \
     hipLaunchKernelGGL((convolve_kernel<T, LOGN>), dim3((unsigned)g.blocks), dim3(kBlock), \
@@ -1472,6 +1564,7 @@ void convolve_group(const BatchGroup &g, const WinInst *insts, hipStream_t s) {
 
 }  // namespace
 
+bool convolve_direct(int n, int dA) { return dA >= 2 && n <= kConvolveDirectMax; }
 int convolve_lines_per_block(int n, int nq) {
     // enough butterflies per stage to occupy the block, but at least ~64
     // workgroups per grid when it has that many line pairs (the launches

@@ -641,16 +641,28 @@ void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int p
     std::vector<T> coefT(coef.begin(), coef.end());
     upload(w.poly, coefT);
     // per-axis multiplier: b1_k / phihat(k/n)^2 for |k| < M/2, else 0
-    std::vector<T> bconv(n, T(0));
+    std::vector<double> bd(n, 0.0);
     const double i0b = bessel_i0(w.kb_b);
     const std::vector<double> bk = sampled_coeffs_1d(w.M, w.ell, w.h);
     for (int k = 0; k < n; ++k) {
         const int ks = k < n / 2 ? k : k - n;
         if (std::abs(ks) >= w.M / 2) continue;
         const double ph = kb_phihat((double)ks / n, m, w.kb_b) / i0b;
-        bconv[k] = static_cast<T>(bk[ks + w.M / 2] / (ph * ph));
+        bd[k] = bk[ks + w.M / 2] / (ph * ph);
     }
-    upload(w.bconv, bconv);
+    upload(w.bconv, std::vector<T>(bd.begin(), bd.end()));
+    // the same filter as circular-convolution taps (small grids): the
+    // multiplier is real and even, so its inverse transform is the real,
+    // even c_d = sum_k b_k cos(2 pi k d / n)
+    {
+        std::vector<T> taps(n);
+        for (int d = 0; d < n; ++d) {
+            double c = 0.0;
+            for (int k = 0; k < n; ++k) c += bd[k] * std::cos(2.0 * kPi * (double)((int64_t)k * d % n) / n);
+            taps[d] = static_cast<T>(c);
+        }
+        upload(w.ctaps, taps);
+    }
     // twiddles exp(-2 pi i j / n), j < n/2
     std::vector<T> tw(n);
     for (int j = 0; j < n / 2; ++j) {
@@ -759,7 +771,7 @@ size_t anova::plan_device_bytes(const anova_plan_s *p) {
     size_t b = 0;
     for (const std::vector<WindowPlan> *ws : {&p->win, &p->win64})
       for (const WindowPlan &w : *ws)
-        for (const DevBuf *d : {&w.nodes, &w.perm, &w.subs, &w.poly, &w.bconv, &w.twiddle,
+        for (const DevBuf *d : {&w.nodes, &w.perm, &w.subs, &w.poly, &w.bconv, &w.ctaps, &w.twiddle,
                                 &w.src_sub, &w.cell_start, &w.tiles_ne, &w.fold_pairs,
                                 &w.fold_start, &w.fold_tiles})
             b += d->bytes;
