@@ -306,7 +306,6 @@ void run_combine(const CombInst *cis, const CombineWin *wins, const int32_t *pre
                  int blocks, int precision, hipStream_t s);
 int convolve_lines_per_block(int n, int nq);
 int cell_tile(int dA);
-int cell_threads_per_cell(int dA);
 bool cell_width_supported(int dA, int W);
 int cell_point_splits(int dA, int W);
 bool convolve_direct(int n, int dA);  // small grids: circular convolution by taps, planes then z
@@ -314,7 +313,6 @@ int cell_resident_blocks(int dA, int W);  // per-cell spreading workgroups held 
 int fold_blocks(const WinInst &w);  // fold workgroups of an instance
 int combine_span();
 int permute_span();
-int block_threads();
 
 // plan helpers (plan.hip)
 void plan_matvec(anova_plan_s *p, const double *alpha, double *out, int nrhs, int64_t ld,

@@ -1573,11 +1573,6 @@ int convolve_lines_per_block(int n, int nq) {
     return std::max(1, std::min(per_block, (nq + 63) / 64));
 }
 int cell_tile(int dA) { return dA == 3 ? 4 : (dA == 2 ? 16 : 64); }
-int cell_threads_per_cell(int dA) {
-    const int t = cell_tile(dA);
-    const int cells = dA == 3 ? t * t * t : (dA == 2 ? t * t : t);
-    return kBlock / cells;
-}
 bool cell_width_supported(int dA, int W) {
     return dA == 3 ? (W <= 6 || W == 8 || W == 12) : (dA == 2 ? W <= 8 : W <= 16);
 }
@@ -1611,7 +1606,6 @@ int cell_point_splits(int dA, int W) {
 }
 int combine_span() { return kCombineSpan; }
 int permute_span() { return kPermuteSpan; }
-int block_threads() { return kBlock; }
 
 void run_group(const BatchGroup &g, int precision, const WinInst *insts, hipStream_t s) {
     const bool f64 = precision == ANOVA_FP64;
