@@ -199,6 +199,17 @@ def precision_split(A, torch, X, p, a, out, plan32, target):
     plan64.destroy()
     d = np.linalg.norm(xs["fp32_nfft"] - xs["fp64_plain"]) / np.linalg.norm(xs["fp64_plain"])
     res["solution_rel_diff"] = float(d)
+    # precision alone: the float64 path at the float32 plan's (M, n, m, h)
+    i0 = plan32.info(0)
+    plan64s = A.anova_fastsum_plan(X, p.windows, A.make_params(p.ell, A.ANOVA_FP64, M=i0.M, n=i0.n,
+                                                               m=i0.m, h=i0.h))
+    x64s = torch.empty_like(y)
+    A.krr_cg_solve(plan64s, y, x64s, p.beta, 1e-6, 3000, allow_not_converged=True)
+    torch.cuda.synchronize()
+    plan64s.destroy()
+    x64s = x64s.cpu().numpy()
+    res["solution_rel_diff_same_params"] = float(np.linalg.norm(xs["fp32_nfft"] - x64s) /
+                                                 np.linalg.norm(x64s))
     res["cg"] = ("tol 1e-6 on y of the headline workload, beta=1, x0=0; each path plans its own "
                  "parameters for the same error target, so the solutions differ by both "
                  "approximations as well as by precision")
