@@ -72,7 +72,10 @@ typedef struct {
 
 /* Plan parameters.  Zero in M, m, n or h means "choose": the plan then picks
  * the cheapest (M, m, n) whose per-entry error estimate (images + truncation
- * + window aliasing + rounding, weighted by eta) is at most target_err. */
+ * + window aliasing + rounding, weighted by eta, summed) is at most
+ * target_err; for float32 windows on the per-cell kernels it may raise h so
+ * that the points fill whole tiles of grid cells (estimate still within
+ * target_err) when that is modelled to run faster. */
 typedef struct {
     double ell;          /* Gaussian width: exp(-||r||^2 / ell^2), ell > 0 */
     int32_t precision;   /* anova_precision */
@@ -313,7 +316,9 @@ anova_status anova_stage_gather(anova_plan_t plan, int32_t l, const void *grid, 
  * 1 spread (window-weighted sums into per-tile grid regions), 2 tile sum
  * (regions of one tile added, where a tile holds several), 3 fold (tile
  * regions added into the grid with periodic wrap), 4 convolve (FFT, multiply,
- * inverse FFT; one launch per axis), 5 gather (interpolation at the points,
+ * inverse FFT, one launch per axis; for n <= 32 in 2-D and 3-D the same filter
+ * as a circular convolution, x and y in one launch, z in another), 5 gather
+ * (interpolation at the points,
  * written in the caller's order), 6 combine (weighted sum over windows plus
  * the shift).  anova_plan_stage_times synchronises, writes the
  * accumulated milliseconds and launch counts per kind (host arrays of 7) and
