@@ -260,17 +260,17 @@ struct Choice {
 // smallest M, then the smallest m), cheapest model cost first.  Fixed
 // parameters give one candidate.
 //
-// Model cost: N (2m)^dA + 4 n^dA log2(n) dA.  For float32 windows that
+// Model cost: N (2m)^dA / eff + 4 n^dA log2(n) dA, eff the lane efficiency
+// of the spreading and gathering kernels at the points' density (eff_of).
+// For float32 windows that
 // will run the per-cell kernels (support width supported and several points
 // per cell) there is also an aligned variant: a wave of those kernels covers
 // a slab of cells and runs as long as its fullest cell, so points that end
 // inside a tile leave lanes idle; the variant raises h so that the points
 // span a whole number of tiles (one tile fewer) with M and m chosen again
 // for that h, and puts the data's lower edge on a tile boundary (centre
-// chosen in make_plan).  It has the same or a higher model cost (the model
-// does not see lane efficiency, and fewer points per cell raise the
-// per-thread overheads), so only the measured choice (tune) takes it when
-// it runs faster.
+// chosen in make_plan).  It is placed just before its plain twin when the
+// per-cell launch model (best_chunks) says it runs faster, else just after.
 std::vector<Choice> candidates(const anova_params &prm, double D, int dA, double budget,
                                int64_t N, int share) {
     const int prec = prm.precision;
@@ -324,6 +324,16 @@ std::vector<Choice> candidates(const anova_params &prm, double D, int dA, double
         return (double)N * std::pow(2.0 * c.m, dA) / eff +
                4.0 * std::pow((double)c.n, dA) * std::log2((double)c.n) * dA;
     };
+    // lane efficiency of the spreading and gathering kernels: per cell, a
+    // lane's points of one cell against the fixed work of a workgroup (about
+    // four points' worth, as in best_chunks); float32 per point, bound by
+    // int64 LDS atomics, a quarter (float64 candidates are all per point)
+    auto eff_of = [&](const Choice &c, double span) {
+        if (!per_cell_likely(c, span)) return prec == ANOVA_FP32_NFFT ? 0.25 : 1.0;
+        const double steps = (double)N / std::pow(std::max(span, 1.0), dA) /
+                             cell_point_splits(dA, 2 * c.m);
+        return steps / (steps + 4.0);
+    };
     std::vector<Choice> out;
     const bool fixed = prm.M > 0 && prm.m > 0 && prm.n > 0;
     if (fixed) {
@@ -338,14 +348,13 @@ std::vector<Choice> candidates(const anova_params &prm, double D, int dA, double
             Choice c;
             if (!search(h0, n, c)) continue;
             const double span = n * D / h0;  // cells the points cover per dimension
-            if (!per_cell_likely(c, span) || D <= 0) {
-                c.cost = cost(c, 1.0);
-                out.push_back(c);
-                continue;
-            }
-            const int k1 = std::max(1, (int)std::ceil(span / T - 1e-9));
-            c.cost = cost(c, 1.0);
+            c.cost = cost(c, eff_of(c, span));
             out.push_back(c);
+            // the aligned variant serves the kernels with one support per
+            // thread (the wide 3-D kernels' lanes walk every point of a cell,
+            // which the launch model below does not describe)
+            if (!per_cell_likely(c, span) || D <= 0 || (dA == 3 && 2 * c.m > 6)) continue;
+            const int k1 = std::max(1, (int)std::ceil(span / T - 1e-9));
             if (k1 >= 2 && prm.h <= 0 && prm.center == 0) {
                 Choice a;
                 const double h1 = n * D / ((k1 - 1) * T * (1.0 - 4e-5));
