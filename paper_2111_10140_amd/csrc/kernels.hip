@@ -129,6 +129,13 @@ struct WinPoly {
 #pragma unroll
         for (int a = 0; a < H; ++a) pair(z, z2, a, w[a], w[W - 1 - a]);
     }
+    // weight of offset a < W/2 alone at z (offset W-1-a: at -z)
+    __device__ __forceinline__ T at(T z, int a) const {
+        T v = c[a][D];
+#pragma unroll
+        for (int k = D - 1; k >= 0; --k) v = v * z + c[a][k];
+        return v;
+    }
 };
 
 // The three fractional offsets of a float32 node record (its packed cell
@@ -574,25 +581,6 @@ constexpr int wide_lanes() { return WideSplit<W>::SX * WideSplit<W>::SY * WideSp
 template <int W>
 constexpr int wide_group_cells() { return kWideThreads / wide_lanes<W>(); }
 
-// Lower-half window polynomials, uniform across the workgroup.
-template <int W>
-struct HalfPoly {
-    static constexpr int D = PolyDeg<float>::value, H = W / 2;
-    float c[H][D + 1];
-    __device__ __forceinline__ void load(const float *__restrict__ poly) {
-#pragma unroll
-        for (int a = 0; a < H; ++a)
-#pragma unroll
-            for (int k = 0; k <= D; ++k) c[a][k] = uniform(poly[a * (D + 1) + k]);
-    }
-    __device__ __forceinline__ float at(float z, int a) const {
-        float v = c[a][D];
-#pragma unroll
-        for (int k = D - 1; k >= 0; --k) v = v * z + c[a][k];
-        return v;
-    }
-};
-
 // One axis of a lane's block: NA offsets, register i <-> support offset
 // offset(s, i), weighted by a lower-half polynomial at z or -z.
 template <int W, int SA>
@@ -604,20 +592,19 @@ struct WideAxis {
         if constexpr (SA == 2) return s ? W - 1 - i : i;
         else return i;
     }
-    __device__ __forceinline__ static void weights(const HalfPoly<W> &hp, float z, int s,
+    __device__ __forceinline__ static void weights(const WinPoly<float, W> &hp, float z, int s,
                                                    float (&w)[NA]) {
         if constexpr (SA == 2) {
             const float zs = s ? -z : z;
 #pragma unroll
             for (int i = 0; i < NA; ++i) w[i] = hp.at(zs, i);
         } else {
+            const float z2 = z * z;
 #pragma unroll
-            for (int i = 0; i < W / 2; ++i) w[i] = hp.at(z, i);
-#pragma unroll
-            for (int i = W / 2; i < W; ++i) w[i] = hp.at(-z, W - 1 - i);
+            for (int i = 0; i < W / 2; ++i) hp.pair(z, z2, i, w[i], w[W - 1 - i]);
         }
     }
-    __device__ __forceinline__ static float weight(const HalfPoly<W> &hp, float z, int s, int i) {
+    __device__ __forceinline__ static float weight(const WinPoly<float, W> &hp, float z, int s, int i) {
         if constexpr (SA == 2) return hp.at(s ? -z : z, i);
         else return i < W / 2 ? hp.at(z, i) : hp.at(-z, W - 1 - i);
     }
@@ -699,7 +686,7 @@ __global__ __launch_bounds__(kWideThreads, 2) void spread_wide_kernel(
     const NodeF32 *__restrict__ nodes = static_cast<const NodeF32 *>(wi.nodes);
     const int32_t *__restrict__ perm = wi.perm;
     const double *__restrict__ alpha = wi.alpha;
-    HalfPoly<W> hp;
+    WinPoly<float, W> hp;
     hp.load(static_cast<const float *>(wi.poly));
     for (int e = threadIdx.x; e < VOL; e += NT) acc_lds[e] = 0ull;
     int tk, chunk, K;
@@ -774,15 +761,37 @@ __global__ __launch_bounds__(kWideThreads, 2) void spread_wide_kernel(
                     AX::weights(hp, 2.0f * p.x - 1.0f, ln.sx, wx);
                     AY::weights(hp, 2.0f * p.y - 1.0f, ln.sy, wy);
                     const float zz = 2.0f * p.z - 1.0f;
+                    if constexpr (SP::SZ == 1 && SP::NPS == 1) {
+                        // the whole z axis: planes in mirror pairs
+                        const float zz2 = zz * zz;
 #pragma unroll
-                    for (int c = 0; c < PZ; ++c) {
-                        const float wc = p.w * AZ::weight(hp, zz, ln.sz, pass * PZ + c);
+                        for (int c2 = 0; c2 < W / 2; ++c2) {
+                            float wlo, whi;
+                            hp.pair(zz, zz2, c2, wlo, whi);
 #pragma unroll
-                        for (int b = 0; b < WY; ++b) {
-                            const float wbc = wc * wy[b];
+                            for (int h = 0; h < 2; ++h) {
+                                const int c = h == 0 ? c2 : W - 1 - c2;
+                                const float wc = p.w * (h == 0 ? wlo : whi);
 #pragma unroll
-                            for (int i = 0; i < WX; ++i)
-                                acc[c][b][i] = fmaf(wbc, wx[i], acc[c][b][i]);
+                                for (int b = 0; b < WY; ++b) {
+                                    const float wbc = wc * wy[b];
+#pragma unroll
+                                    for (int i = 0; i < WX; ++i)
+                                        acc[c][b][i] = fmaf(wbc, wx[i], acc[c][b][i]);
+                                }
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < PZ; ++c) {
+                            const float wc = p.w * AZ::weight(hp, zz, ln.sz, pass * PZ + c);
+#pragma unroll
+                            for (int b = 0; b < WY; ++b) {
+                                const float wbc = wc * wy[b];
+#pragma unroll
+                                for (int i = 0; i < WX; ++i)
+                                    acc[c][b][i] = fmaf(wbc, wx[i], acc[c][b][i]);
+                            }
                         }
                     }
                 }
@@ -841,7 +850,7 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
     const float *__restrict__ grid = static_cast<const float *>(wi.grid);
     float *__restrict__ tmp = static_cast<float *>(wi.tmp);
     const int32_t *__restrict__ perm = wi.perm;
-    HalfPoly<W> hp;
+    WinPoly<float, W> hp;
     hp.load(static_cast<const float *>(wi.poly));
     const int n = wi.n, tpd = wi.tpd;
     int tk, chunk, K;
@@ -905,8 +914,7 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
                     AY::weights(hp, 2.0f * p.y - 1.0f, ln.sy, wy);
                     const float zz = 2.0f * p.z - 1.0f;
                     float part = 0.0f;
-#pragma unroll
-                    for (int c = 0; c < PZ; ++c) {
+                    auto plane = [&](int c) {
                         float sc = 0.0f;
 #pragma unroll
                         for (int b = 0; b < WY; ++b) {
@@ -915,7 +923,22 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
                             for (int i = 0; i < WX; ++i) sr = fmaf(gv[c][b][i], wx[i], sr);
                             sc = fmaf(sr, wy[b], sc);
                         }
-                        part = fmaf(sc, AZ::weight(hp, zz, ln.sz, pass * PZ + c), part);
+                        return sc;
+                    };
+                    if constexpr (SP::SZ == 1 && SP::NPG == 1) {
+                        // the whole z axis: planes in mirror pairs
+                        const float zz2 = zz * zz;
+#pragma unroll
+                        for (int c2 = 0; c2 < W / 2; ++c2) {
+                            float wlo, whi;
+                            hp.pair(zz, zz2, c2, wlo, whi);
+                            part = fmaf(plane(c2), wlo, part);
+                            part = fmaf(plane(W - 1 - c2), whi, part);
+                        }
+                    } else {
+#pragma unroll
+                        for (int c = 0; c < PZ; ++c)
+                            part = fmaf(plane(c), AZ::weight(hp, zz, ln.sz, pass * PZ + c), part);
                     }
                     const float v = cell_lanes_sum<TPC>(part);
                     if (lead) *dst = prev + v;  // caller order
