@@ -130,6 +130,19 @@ def test_small_and_ragged_sizes(A, N):
         assert e <= gate, (N, precision, e)
 
 
+@pytest.mark.parametrize("precision,gate", [(F32, 1e-4), (F64, 1e-9)])
+@pytest.mark.parametrize("windows,d", [([(0, 1, 2)], 3), ([(0, 1)], 2), ([(0,)], 1)])
+def test_largest_grid_and_support(A, precision, gate, windows, d):
+    # the parameter limits: FFT length n = 256, support 2m = 16, M = 128
+    p = workloads.random_problem(5000, d, windows, 0.05, seed=77 + d, eta=[1.0])
+    plan = make_plan(A, p, precision, M=128, m=8, n=256)
+    a = p.alpha[:, 0]
+    e = rel_err(gpu_matvec(A, plan, a, p.beta),
+                oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a), a)
+    print(f"n=256 m=8 d_A={d} precision={precision}: E = {e:.3e}, estimate {plan.err_estimate():.3e}")
+    assert e <= gate and e <= max(plan.err_estimate(), 1e-12)
+
+
 def test_degenerate_identical_points(A):
     # all points equal: every kernel entry is sum(eta) = 1
     X = np.tile(np.array([[0.1, -0.2, 0.05]]), (500, 1))
