@@ -1376,7 +1376,7 @@ __global__ __launch_bounds__(kBlock) void convolve_z_kernel(const WinInst *__res
 // line-sized random reads of reading them back through the inverse
 // permutation).  Blocks: ceil(N / kCombineSpan) per instance.
 constexpr int kConvolveDirectMax = 32;  // largest n convolved by direct taps
-constexpr int kCombinePerThread = 4;
+constexpr int kCombinePerThread = 2;
 constexpr int kCombineSpan = kCombinePerThread * kBlock;
 
 template <typename T>
