@@ -2,8 +2,10 @@
 
 Test infrastructure only.  Computes the plain definitions:
 kernel (Sec. 3, eq. extended_Gaussian_ANOVA_kernel, weighted as in Sec. 5),
-product K alpha (Sec. 2, eq. mult_with_K) and the shifted product
-(K + beta I) alpha of the normal equation (Sec. 2).
+product K alpha (Sec. 2, eq. mult_with_K), the shifted product
+(K + beta I) alpha of the normal equation (Sec. 2), and the sum over training
+points at new points, s(z_i) = sum_j alpha_j kappa(z_i, x_j) (Sec. 4.2,
+eq. kernelsum; used for prediction in Sec. 4.3).
 """
 from __future__ import annotations
 
@@ -31,6 +33,13 @@ def _load():
             P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_double), ctypes.c_int32,
             ctypes.c_double, ctypes.c_double,
             P(ctypes.c_double), ctypes.c_int32, ctypes.c_int64,
+            P(ctypes.c_int64), ctypes.c_int64, P(ctypes.c_double)]
+        lib.oracle_anova_predict.restype = ctypes.c_int
+        lib.oracle_anova_predict.argtypes = [
+            P(ctypes.c_double), ctypes.c_int64, ctypes.c_int64,
+            P(ctypes.c_double), ctypes.c_int64, ctypes.c_int64,
+            P(ctypes.c_int32), P(ctypes.c_int32), P(ctypes.c_double), ctypes.c_int32,
+            ctypes.c_double, P(ctypes.c_double), ctypes.c_int32, ctypes.c_int64,
             P(ctypes.c_int64), ctypes.c_int64, P(ctypes.c_double)]
         lib.oracle_kernel_block.restype = None
         lib.oracle_kernel_block.argtypes = [
@@ -91,6 +100,44 @@ def anova_matvec(X: np.ndarray, windows, ell: float, beta: float, alpha: np.ndar
         _ptr(X, ctypes.c_double), N, d, _ptr(feat, ctypes.c_int32), _ptr(dA, ctypes.c_int32),
         _ptr(eta, ctypes.c_double), len(windows), float(ell), float(beta),
         _ptr(A, ctypes.c_double), nrhs, N,
+        None if rows_arr is None else _ptr(rows_arr, ctypes.c_int64), nrows,
+        _ptr(out, ctypes.c_double))
+    res = out.T
+    if vec:
+        res = res[:, 0]
+    return (res, nt) if return_threads else res
+
+
+def anova_predict(Z: np.ndarray, X: np.ndarray, windows, ell: float, alpha: np.ndarray,
+                  rows: Optional[Sequence[int]] = None, return_threads: bool = False):
+    """s(z_i) = sum_j alpha_j kappa(z_i, x_j) for i in rows (all of Z by
+    default), in float64.  Z: (Nz, d) new points; X: (N, d) training points;
+    alpha: (N,) or (N, nrhs).  Returns (len(rows), nrhs), or a vector for a
+    vector alpha."""
+    lib = _load()
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    N, d = X.shape
+    Nz, dz = Z.shape
+    if dz != d:
+        raise ValueError("Z and X must have the same number of features")
+    vec = alpha.ndim == 1
+    A = np.asfortranarray(alpha.reshape(N, -1), dtype=np.float64)
+    nrhs = A.shape[1]
+    feat, dA, eta = _windows(windows)
+    if rows is None:
+        rows_arr = None
+        nrows = Nz
+    else:
+        rows_arr = np.ascontiguousarray(np.asarray(rows, dtype=np.int64))
+        nrows = rows_arr.size
+        if nrows and (rows_arr.min() < 0 or rows_arr.max() >= Nz):
+            raise IndexError("row index out of range")
+    out = np.zeros((nrhs, nrows), dtype=np.float64)
+    nt = lib.oracle_anova_predict(
+        _ptr(Z, ctypes.c_double), Nz, d, _ptr(X, ctypes.c_double), N, d,
+        _ptr(feat, ctypes.c_int32), _ptr(dA, ctypes.c_int32), _ptr(eta, ctypes.c_double),
+        len(windows), float(ell), _ptr(A, ctypes.c_double), nrhs, N,
         None if rows_arr is None else _ptr(rows_arr, ctypes.c_int64), nrows,
         _ptr(out, ctypes.c_double))
     res = out.T

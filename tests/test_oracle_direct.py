@@ -166,3 +166,74 @@ def test_golden_figure_gaussian_value():
         rr = (r + h / 2) % h - h / 2
         assert abs(abs(rr) - L) < 1e-12
         assert round(K[0, 1], 4) == val and round(K[0, 2], 4) == val
+
+
+# ---------------------------------------------------------------- prediction
+# s(z_i) = sum_j alpha_j kappa(z_i, x_j) over two node sets (Sec. 4.2,
+# eq. kernelsum; Sec. 4.3 evaluates the trained model at test points so).
+
+def test_predict_matches_library_rectangular_kernel():
+    p = _prob(N=120)
+    rng = np.random.default_rng(11)
+    Z = rng.uniform(-0.3, 0.3, (45, p.X.shape[1]))
+    alpha = rng.standard_normal((120, 2))
+    ref = sum(w.eta * rbf_kernel(Z[:, list(w.feat)], p.X[:, list(w.feat)], gamma=1.0 / p.ell ** 2)
+              for w in p.windows) @ alpha
+    out = D.anova_predict(Z, p.X, p.windows, p.ell, alpha)
+    assert out.shape == (45, 2)
+    np.testing.assert_allclose(out, ref, rtol=1e-13, atol=1e-13)
+
+
+def test_predict_at_the_training_points_is_the_unshifted_product():
+    # the special case Z = X of the two-set sum is the product K alpha
+    p = _prob(N=90)
+    alpha = np.random.default_rng(12).standard_normal(90)
+    out = D.anova_predict(p.X, p.X, p.windows, p.ell, alpha)
+    ref = D.anova_matvec(p.X, p.windows, p.ell, 0.0, alpha)
+    np.testing.assert_allclose(out, ref, rtol=1e-15, atol=1e-15)
+
+
+def test_predict_single_training_point_closed_form():
+    # one training point x0 with alpha = 2: s(z) = 2 sum_l eta_l exp(-r_l^2/ell^2)
+    ell = 0.3
+    x0 = np.array([[0.1, -0.2, 0.05, 0.0, 0.2]])
+    wins = [Window((0,), 0.5), Window((1, 2), 0.3), Window((4,), 0.2)]
+    Z = np.repeat(x0, 5, axis=0)
+    Z[1, 0] += ell                     # r = ell in window 0
+    Z[2, 1] += ell / math.sqrt(2.0)    # r = ell in window 1, split over two features
+    Z[2, 2] -= ell / math.sqrt(2.0)
+    Z[3, 3] += 5.0                     # feature 3 is in no window
+    Z[4, :] += 10.0                    # far from x0 in every window
+    s = D.anova_predict(Z, x0, wins, ell, np.array([2.0]))
+    e1 = math.exp(-1.0)
+    expect = [2.0, 2.0 * (0.5 * e1 + 0.5), 2.0 * (0.7 + 0.3 * e1), 2.0, 0.0]
+    np.testing.assert_allclose(s, expect, rtol=1e-14, atol=1e-300)
+
+
+def test_predict_adjoint_identity():
+    # gamma^T K(Z, X) alpha = alpha^T K(X, Z) gamma: a transposed operand or an
+    # index taken from the wrong set fails this
+    rng = np.random.default_rng(13)
+    wins = [Window((0, 2), 0.6), Window((1,), 0.4)]
+    X = rng.uniform(-0.25, 0.25, (70, 3))
+    Z = rng.uniform(-0.25, 0.25, (33, 3))
+    a, g = rng.standard_normal(70), rng.standard_normal(33)
+    lhs = g @ D.anova_predict(Z, X, wins, 0.15, a)
+    rhs = a @ D.anova_predict(X, Z, wins, 0.15, g)
+    assert abs(lhs - rhs) <= 1e-13 * (np.abs(g).sum() * np.abs(a).sum())
+
+
+def test_predict_rows_and_columns():
+    p = _prob(N=64)
+    rng = np.random.default_rng(14)
+    Z = rng.uniform(-0.25, 0.25, (40, p.X.shape[1]))
+    alpha = rng.standard_normal((64, 3))
+    full = D.anova_predict(Z, p.X, p.windows, p.ell, alpha)
+    rows = [39, 0, 17, 17]
+    np.testing.assert_array_equal(D.anova_predict(Z, p.X, p.windows, p.ell, alpha, rows=rows),
+                                  full[rows])
+    for c in range(3):
+        np.testing.assert_array_equal(D.anova_predict(Z, p.X, p.windows, p.ell, alpha[:, c]),
+                                      full[:, c])
+    with pytest.raises(IndexError):
+        D.anova_predict(Z, p.X, p.windows, p.ell, alpha, rows=[40])
