@@ -59,6 +59,7 @@ def parse():
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-tuned", action="store_true")
     ap.add_argument("--skip-large", action="store_true")
+    ap.add_argument("--skip-predict", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run 5 device-to-device copies of 1 GiB (counter calibration)")
     return ap.parse_args()
@@ -304,6 +305,54 @@ def large_config(A, torch):
     return res
 
 
+def predict_config(A, torch, steps):
+    """Prediction at new points: 1e6 training and 1e6 test points of the
+    headline distribution (the paper's experiments split each sample into
+    training and test halves), float32 plan for a per-entry estimate <= 1e-4;
+    predictions/s (one = all test points for one coefficient vector), the
+    per-stage split.  Its parity with the oracle is a test, not part of this
+    timing."""
+    import workloads
+    p, Zn = workloads.train_test(1_000_000, 1_000_000, seed=31)
+    X = torch.from_numpy(p.X).cuda()
+    Z = torch.from_numpy(Zn).cuda()
+    a_np = np.ascontiguousarray(p.alpha[:, 0])
+    a = torch.from_numpy(a_np.copy()).cuda()
+    out = torch.empty(Zn.shape[0], dtype=torch.float64, device="cuda")
+    t = time.perf_counter()
+    plan = A.anova_predict_plan(X, Z, p.windows, A.make_params(p.ell, A.ANOVA_FP32_NFFT,
+                                                               target_err=1e-4))
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t
+    for _ in range(3):
+        A.anova_predict(plan, a, out)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(steps):
+        A.anova_predict(plan, a, out)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / steps
+    plan.set_timing(True)
+    for _ in range(10):
+        A.anova_predict(plan, a, out)
+    torch.cuda.synchronize()
+    st = plan.stage_times()
+    plan.set_timing(False)
+    res = {"workload": "train N=1e6, test Nz=1e6, d=9, 3 windows of 3 features, ell=0.2, "
+                       "float32, per-entry estimate <= 1e-4",
+           "ms_per_predict": round(ms, 4), "predicts_per_s": round(1e3 / ms, 2),
+           "test_points_per_s": round(Zn.shape[0] / (ms * 1e-3), 1),
+           "plan_seconds": round(plan_s, 3),
+           "params": [dict(M=i.M, n=i.n, m=i.m, h=round(i.h, 4), per_cell=i.per_cell)
+                      for i in (plan.info(l) for l in range(plan.P))],
+           "err_estimate": plan.err_estimate(),
+           "stage_avg_us": {k: round(v[0] / v[1] * 1e3, 2) for k, v in st.items() if v[1]}}
+    plan.destroy()
+    return res
+
+
 def serving(args, A):
     """Served KRR solves: closed-loop capacity (every request queued at t=0),
     the same with one request at a time, then Poisson arrivals at
@@ -484,6 +533,10 @@ def main():
         batched = batched_config(A, torch)
         print(f"# batched: {json.dumps(batched)}", file=sys.stderr, flush=True)
     large = None if args.skip_large else large_config(A, torch)
+    predicted = None
+    if not args.skip_predict:
+        predicted = predict_config(A, torch, max(10, args.steps // 2))
+        print(f"# predict: {json.dumps(predicted)}", file=sys.stderr, flush=True)
     served = None if args.skip_serve else serving(args, A)
 
     res = {
@@ -505,6 +558,7 @@ def main():
         "precision_split": split,
         "batched": batched,
         "large": large,
+        "predict": predicted,
         "serving": served,
         "cpu_baseline": cpu,
     }

@@ -181,6 +181,46 @@ anova_status anova_matvec(anova_plan_t plan, const double *alpha, double *out, i
                           int64_t ld, double beta, void *stream);
 
 /*
+ * Plan for prediction at new points: the sum over training points
+ * s(z_i) = sum_j alpha_j kappa(z_i, x_j) at targets z_i (Sec. 4.2, the fast
+ * summation with target set Z and source set X; Sec. 4.3 evaluates the
+ * trained model at test data this way).  Builds the plan anova_fastsum_plan
+ * builds for the training points X, except that each window's period h and
+ * centre are chosen for the points of X and Z together (every difference
+ * z - x must lie in the periodised kernel's fundamental cell); anova_matvec,
+ * krr_cg_solve and the other plan calls work on it unchanged.  The targets Z
+ * (device, Nz x d row-major float64, ldz >= d, same features as X) are
+ * binned and sorted on the same grids; the plan does not keep Z.
+ * Synchronises `stream`.
+ * Errors: as anova_fastsum_plan, and ANOVA_E_INVALID for Z == NULL, Nz < 1,
+ * Nz > 2^31-1, ldz < d or a non-finite Z.
+ */
+anova_status anova_predict_plan(anova_plan_t *out, const double *X, int64_t N, const double *Z,
+                                int64_t Nz, int32_t d, int64_t ldx, int64_t ldz,
+                                const anova_window *win, int32_t P, const anova_params *prm,
+                                void *stream);
+
+/* anova_predict_plan with X and Z in host memory.  Errors as anova_predict_plan. */
+anova_status anova_predict_plan_host(anova_plan_t *out, const double *X, int64_t N,
+                                     const double *Z, int64_t Nz, int32_t d, int64_t ldx,
+                                     int64_t ldz, const anova_window *win, int32_t P,
+                                     const anova_params *prm);
+
+/*
+ * out = K~(Z, X) alpha for nrhs columns: out_i = s(z_i), the weighted window
+ * sums of Sec. 5 evaluated by spreading alpha at the training points, the
+ * windows' Fourier multiplications, and interpolation at the targets (in
+ * matrix form Phi_Z D Phi_X^* alpha, Sec. 4.3).  No shift is added.
+ * alpha: device, N x nrhs column-major, lda >= N; out: device, Nz x nrhs
+ * column-major, ldo >= Nz; they must not overlap.  Arithmetic as anova_matvec
+ * in the plan's precision.  Asynchronous on `stream`.
+ * Errors: ANOVA_E_INVALID for a NULL plan/pointer, a plan built without
+ * targets, nrhs < 1, lda < N, ldo < Nz.
+ */
+anova_status anova_predict(anova_plan_t plan, const double *alpha, double *out, int32_t nrhs,
+                           int64_t lda, int64_t ldo, void *stream);
+
+/*
  * Solve (K~ + beta I) alpha = y by conjugate gradients (Sec. 2), one
  * independent recurrence per column, no preconditioner.  x0 = 0; dot
  * products, vector updates and residual recomputations are float64.  Every

@@ -103,6 +103,12 @@ def load():
         "krr_cg_active": [ctypes.POINTER(VP), i32, VP, VP, VP],
         "anova_fastsum_plan_host": [ctypes.POINTER(VP), VP, i64, i32, i64,
                                     ctypes.POINTER(anova_window), i32, ctypes.POINTER(anova_params)],
+        "anova_predict_plan": [ctypes.POINTER(VP), VP, i64, VP, i64, i32, i64, i64,
+                               ctypes.POINTER(anova_window), i32, ctypes.POINTER(anova_params), VP],
+        "anova_predict_plan_host": [ctypes.POINTER(VP), VP, i64, VP, i64, i32, i64, i64,
+                                    ctypes.POINTER(anova_window), i32,
+                                    ctypes.POINTER(anova_params)],
+        "anova_predict": [VP, VP, VP, i32, i64, i64, VP],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -199,9 +205,10 @@ STAGE_KINDS = ("permute", "spread", "tile_sum", "fold", "convolve", "gather", "c
 class Plan:
     """Owning wrapper over an anova_plan_t."""
 
-    def __init__(self, handle: int, N: int, P: int, precision: int):
+    def __init__(self, handle: int, N: int, P: int, precision: int, Nz: int = 0):
         self.handle = handle
         self.N, self.P, self.precision = N, P, precision
+        self.Nz = Nz  # prediction plans: number of targets
 
     def __del__(self):
         try:
@@ -270,6 +277,53 @@ def anova_fastsum_plan_host(X, windows, params: anova_params) -> Plan:
                                         len(windows), ctypes.byref(params))
     _check(st)
     return Plan(h.value, N, len(windows), params.precision)
+
+
+def anova_predict_plan(X, Z, windows, params: anova_params, stream=None) -> Plan:
+    """Prediction plan for device training points X ((N, d)) and targets Z
+    ((Nz, d)), both row-major CUDA float64."""
+    for t, name in ((X, "X"), (Z, "Z")):
+        _dev_f64(t, name)
+        if t.dim() != 2 or t.stride(1) != 1:
+            raise ValueError(f"{name} must be (rows, d) row-major")
+    N, d = X.shape
+    Nz, dz = Z.shape
+    if dz != d:
+        raise ValueError("X and Z must have the same number of features")
+    wins = make_windows(windows)
+    h = VP()
+    st = load().anova_predict_plan(ctypes.byref(h), X.data_ptr(), N, Z.data_ptr(), Nz, d,
+                                   X.stride(0), Z.stride(0), wins, len(windows),
+                                   ctypes.byref(params), _stream(stream))
+    _check(st)
+    return Plan(h.value, N, len(windows), params.precision, Nz)
+
+
+def anova_predict_plan_host(X, Z, windows, params: anova_params) -> Plan:
+    """Prediction plan for host arrays X ((N, d)) and Z ((Nz, d))."""
+    import numpy as np
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    Z = np.ascontiguousarray(Z, dtype=np.float64)
+    if X.ndim != 2 or Z.ndim != 2 or X.shape[1] != Z.shape[1]:
+        raise ValueError("X and Z must be (rows, d) with the same d")
+    N, d = X.shape
+    Nz = Z.shape[0]
+    wins = make_windows(windows)
+    h = VP()
+    st = load().anova_predict_plan_host(ctypes.byref(h), X.ctypes.data, N, Z.ctypes.data, Nz, d,
+                                        d, d, wins, len(windows), ctypes.byref(params))
+    _check(st)
+    return Plan(h.value, N, len(windows), params.precision, Nz)
+
+
+def anova_predict(plan: Plan, alpha, out, stream=None) -> None:
+    """out = K~(Z, X) alpha at the plan's targets (asynchronous on the stream).
+    alpha: (N,) or (N, nrhs); out: (Nz,) or (Nz, nrhs), column-major."""
+    pa, nrhs, lda = _colmajor(alpha, "alpha", plan.N)
+    po, nrhs2, ldo = _colmajor(out, "out", plan.Nz)
+    if nrhs != nrhs2:
+        raise ValueError("alpha and out must have the same number of columns")
+    _check(load().anova_predict(plan.handle, pa, po, nrhs, lda, ldo, _stream(stream)))
 
 
 def anova_matvec(plan: Plan, alpha, out, beta: float, stream=None) -> None:

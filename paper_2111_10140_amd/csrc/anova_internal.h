@@ -174,10 +174,15 @@ struct anova_plan_s {
     // float32 plans with float64 residuals: the same windows in float64
     // (empty otherwise)
     std::vector<anova::WindowPlan> win64;
+    // prediction plans: the target points binned with each window's
+    // parameters (empty otherwise)
+    int64_t Nz = 0;
+    std::vector<anova::WindowPlan> tgt;
     int device = 0;
-    // batched launches of this plan's own products (anova_matvec), reused
-    // while the vectors and the shift stay the same
-    std::unique_ptr<anova::Batch> mv_batch;
+    // batched launches of this plan's own products (anova_matvec) and
+    // predictions (anova_predict), reused while the vectors and the shift
+    // stay the same
+    std::unique_ptr<anova::Batch> mv_batch, pred_batch;
     // optional per-stage timing (events on the launching stream)
     bool timing = false;
     struct TimedLaunch {
@@ -262,6 +267,8 @@ struct BatchProblem {
                                     // the caller (nullptr: the batch allocates)
     bool residual = false;          // use the plan's float64 residual windows
                                     // when it has them
+    bool predict = false;           // out (plan->Nz rows) = K~(Z, X) alpha: spread
+                                    // at the plan's points, gather at its targets
 };
 
 // Windows and arithmetic precision a batch problem runs with.
@@ -283,6 +290,7 @@ class Batch {
   public:
     int precision = 0;
     std::vector<WinInst> insts;
+    std::vector<uint8_t> roles;  // per instance: bit 0 spreads and convolves, bit 1 gathers
     std::vector<CombInst> combs;
     std::vector<CombineWin> cwins;
     std::vector<BatchGroup> groups;  // execution order
@@ -317,6 +325,8 @@ int permute_span();
 // plan helpers (plan.hip)
 void plan_matvec(anova_plan_s *p, const double *alpha, double *out, int nrhs, int64_t ld,
                  double beta, hipStream_t s);
+void plan_predict(anova_plan_s *p, const double *alpha, double *out, int nrhs, int64_t lda,
+                  int64_t ldo, hipStream_t s);
 template <typename T>
 void upload(DevBuf &buf, const std::vector<T> &v) {
     size_t bytes = v.size() * sizeof(T);

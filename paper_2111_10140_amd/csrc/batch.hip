@@ -3,7 +3,10 @@
 //
 // build() lays out one WinInst per instance (window data of the plan, the
 // input column, and a private slice of one work-space allocation: grid,
-// spread regions, per-tile region sums, interpolated values), groups the
+// spread regions, per-tile region sums, interpolated values); a prediction
+// takes two per window and column, one that spreads the training points and
+// convolves, and one that gathers at the targets from the same grid (the
+// two node sets of the fast sum, Sec. 4.2).  It groups the
 // instances of each stage by kernel signature, and uploads the instance and
 // group tables.  run() issues the stages in order: permute, spread, tile
 // sum, fold, convolve (one pass per axis), gather, combine.  Nothing is allocated or
@@ -33,6 +36,38 @@ Sizes instance_sizes(const WindowPlan &w, size_t es, bool own_grid) {
     return z;
 }
 
+// Instance fields taken from a window's plan.
+void fill_inst(WinInst &wi, const WindowPlan &w, const double *alpha, void *grid) {
+    wi.nodes = w.nodes.ptr;
+    wi.perm = w.perm.as<int32_t>();
+    wi.subs = w.subs.as<SubProblem>();
+    wi.tiles_ne = w.tiles_ne.as<int32_t>();
+    wi.cell_start = w.cell_start.as<int32_t>();
+    wi.src_sub = w.src_sub.as<int32_t>();
+    wi.fold_pairs = w.fold_pairs.as<int2>();
+    wi.fold_start = w.fold_start.as<int32_t>();
+    wi.fold_tiles = w.fold_tiles.as<int32_t>();
+    wi.fold_act = w.fold_act;
+    wi.fold_len = w.fold_len;
+    wi.poly = w.poly.ptr;
+    wi.bconv = w.bconv.ptr;
+    wi.ctaps = w.ctaps.ptr;
+    wi.twiddle = w.twiddle.ptr;
+    wi.alpha = alpha;
+    wi.grid = grid;
+    wi.n = w.n;
+    wi.tile = w.tile;
+    wi.tpd = w.tiles_per_dim;
+    wi.vol = (int32_t)w.region_elems();
+    wi.n_sub = (int32_t)w.n_sub;
+    wi.n_nonempty = (int32_t)w.n_nonempty;
+    wi.n_tiles = (int32_t)w.n_tiles;
+    wi.n_regions = (int32_t)w.n_regions;
+    wi.N = (int32_t)w.n_points;
+    wi.dA = w.dA;
+    wi.width = 2 * w.m;
+}
+
 }  // namespace
 
 size_t problem_work_bytes(const BatchProblem &bp) {
@@ -44,6 +79,7 @@ size_t problem_work_bytes(const BatchProblem &bp) {
             if (bp.only_window >= 0 && l != bp.only_window) continue;
             const Sizes z = instance_sizes(wins[l], es, bp.grid_override == nullptr);
             total += z.grid + z.priv + z.treg + z.tmp;
+            if (bp.predict) total += align256((size_t)bp.plan->tgt[l].n_points * es);
         }
     return total;
 }
@@ -60,7 +96,7 @@ bool Batch::same(const std::vector<BatchProblem> &problems) const {
             a.ld != b.ld || a.ld_out != b.ld_out || a.beta != b.beta ||
             a.only_window != b.only_window ||
             a.grid_override != b.grid_override || a.work != b.work ||
-            a.residual != b.residual)
+            a.residual != b.residual || a.predict != b.predict)
             return false;
     }
     return true;
@@ -69,11 +105,16 @@ bool Batch::same(const std::vector<BatchProblem> &problems) const {
 void Batch::build(const std::vector<BatchProblem> &problems) {
     ANOVA_REQUIRE(!problems.empty(), "empty batch");
     precision = problem_precision(problems[0]);
-    for (const BatchProblem &bp : problems)
+    for (const BatchProblem &bp : problems) {
         ANOVA_REQUIRE(problem_precision(bp) == precision,
                       "a batch mixes float32 and float64 products");
+        ANOVA_REQUIRE(!bp.predict || ((int)bp.plan->tgt.size() == bp.plan->P &&
+                                      bp.only_window < 0 && !bp.grid_override && !bp.residual),
+                      "prediction needs a plan with targets, all windows and its own grids");
+    }
     const size_t es = precision == ANOVA_FP64 ? 8 : 4;
     insts.clear();
+    roles.clear();
     combs.clear();
     cwins.clear();
     groups.clear();
@@ -83,6 +124,8 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
     };
     std::vector<Slot> slots;
     std::vector<char *> slot_base;  // nullptr: the batch's own work space
+    std::vector<int64_t> grid_of;   // -1, or the instance whose grid this one gathers from
+    std::vector<int64_t> cwin_inst; // instance whose values each combine window reads
     size_t total = 0;
     for (const BatchProblem &bp : problems) {
         anova_plan_s *p = bp.plan;
@@ -92,9 +135,10 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
             CombInst ci{};
             const int64_t ldo = bp.ld_out >= 0 ? bp.ld_out : bp.ld;
             ci.out = bp.out ? bp.out + (size_t)c * ldo : nullptr;
-            ci.alpha = bp.alpha + (size_t)c * bp.ld;
-            ci.beta = bp.beta;
-            ci.N = (int32_t)p->N;
+            // a prediction has no shift (its output rows are other points)
+            ci.alpha = bp.predict ? nullptr : bp.alpha + (size_t)c * bp.ld;
+            ci.beta = bp.predict ? 0.0 : bp.beta;
+            ci.N = (int32_t)(bp.predict ? p->Nz : p->N);
             ci.win0 = (int32_t)cwins.size();
             ci.accumulate = bp.only_window >= 0 ? 1 : 0;
             int nw = 0;
@@ -107,35 +151,25 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
                 slots.push_back(sl);
                 slot_base.push_back(static_cast<char *>(bp.work));
                 WinInst wi{};
-                wi.nodes = w.nodes.ptr;
-                wi.perm = w.perm.as<int32_t>();
-                wi.subs = w.subs.as<SubProblem>();
-                wi.tiles_ne = w.tiles_ne.as<int32_t>();
-                wi.cell_start = w.cell_start.as<int32_t>();
-                wi.src_sub = w.src_sub.as<int32_t>();
-                wi.fold_pairs = w.fold_pairs.as<int2>();
-                wi.fold_start = w.fold_start.as<int32_t>();
-                wi.fold_tiles = w.fold_tiles.as<int32_t>();
-                wi.fold_act = w.fold_act;
-                wi.fold_len = w.fold_len;
-                wi.poly = w.poly.ptr;
-                wi.bconv = w.bconv.ptr;
-                wi.ctaps = w.ctaps.ptr;
-                wi.twiddle = w.twiddle.ptr;
-                wi.alpha = ci.alpha;
-                wi.grid = bp.grid_override;  // patched below when owned
-                wi.n = w.n;
-                wi.tile = w.tile;
-                wi.tpd = w.tiles_per_dim;
-                wi.vol = (int32_t)w.region_elems();
-                wi.n_sub = (int32_t)w.n_sub;
-                wi.n_nonempty = (int32_t)w.n_nonempty;
-                wi.n_tiles = (int32_t)w.n_tiles;
-                wi.n_regions = (int32_t)w.n_regions;
-                wi.N = (int32_t)w.n_points;
-                wi.dA = w.dA;
-                wi.width = 2 * w.m;
+                // the grid is patched below when owned
+                fill_inst(wi, w, bp.alpha + (size_t)c * bp.ld, bp.grid_override);
                 insts.push_back(wi);
+                roles.push_back(bp.predict ? 1 : 3);
+                grid_of.push_back(-1);
+                if (bp.predict) {
+                    // the targets: no grid, regions or sums of their own
+                    const WindowPlan &v = p->tgt[l];
+                    const size_t tz = align256((size_t)v.n_points * es);
+                    slots.push_back(Slot{off, off, off, off});
+                    off += tz;
+                    slot_base.push_back(static_cast<char *>(bp.work));
+                    WinInst wt{};
+                    fill_inst(wt, v, nullptr, nullptr);
+                    grid_of.push_back((int64_t)insts.size() - 1);
+                    insts.push_back(wt);
+                    roles.push_back(2);
+                }
+                cwin_inst.push_back((int64_t)insts.size() - 1);
                 cwins.push_back(CombineWin{nullptr, w.eta});
                 ++nw;
             }
@@ -149,12 +183,15 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
         work.alloc(total);
     for (size_t i = 0; i < insts.size(); ++i) {
         char *base = slot_base[i] ? slot_base[i] : static_cast<char *>(work.ptr);
-        if (!insts[i].grid) insts[i].grid = base + slots[i].grid;
+        if (grid_of[i] >= 0)
+            insts[i].grid = insts[(size_t)grid_of[i]].grid;  // built before it
+        else if (!insts[i].grid)
+            insts[i].grid = base + slots[i].grid;
         insts[i].priv = base + slots[i].priv;
         insts[i].treg = base + slots[i].treg;
         insts[i].tmp = base + slots[i].tmp;
-        cwins[i].tmp = insts[i].tmp;
     }
+    for (size_t k = 0; k < cwins.size(); ++k) cwins[k].tmp = insts[(size_t)cwin_inst[k]].tmp;
     // ---- groups: key -> member list, per stage
     std::vector<int32_t> table;  // all members and prefixes, packed
     struct PendingGroup {
@@ -164,7 +201,9 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
     std::vector<PendingGroup> pending;
     auto add_stage = [&](int stage, auto key_of, auto blocks_of, auto fill) {
         std::map<std::tuple<int, int, int, int, int, int>, size_t> idx;
+        const unsigned role = stage == kStageGather ? 2u : 1u;
         for (size_t i = 0; i < insts.size(); ++i) {
+            if (!(roles[i] & role)) continue;
             int b = 0;
             if (!blocks_of(insts[i], b) || b <= 0) continue;
             const auto key = key_of(insts[i]);

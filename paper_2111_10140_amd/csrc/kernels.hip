@@ -1370,7 +1370,8 @@ __global__ __launch_bounds__(kBlock) void convolve_z_kernel(const WinInst *__res
 
 // ------------------------------------------------------------------ combine
 // out_i = beta alpha_i + sum_l eta_l tmp_l[i] in float64, windows in order
-// (accumulate: out_i += the sum instead).  tmp_l holds window l's
+// (accumulate: out_i += the sum instead; no alpha, as for predictions at
+// other points: the sum alone).  tmp_l holds window l's
 // interpolated values in the caller's point order (the gather kernels write
 // them there: scattered writes, which the caches merge, cost less than the
 // line-sized random reads of reading them back through the inverse
@@ -1392,7 +1393,8 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(const CombInst *__restr
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int i = i0 + e * kBlock;
-        s[e] = i < ci.N ? (ci.accumulate ? ci.out[i] : ci.beta * ci.alpha[i]) : 0.0;
+        s[e] = i < ci.N ? (ci.accumulate ? ci.out[i] : ci.alpha ? ci.beta * ci.alpha[i] : 0.0)
+                        : 0.0;
     }
     for (int l = 0; l < ci.P; ++l) {
         const CombineWin cw = wins[ci.win0 + l];

@@ -755,6 +755,24 @@ void plan_matvec(anova_plan_s *p, const double *alpha, double *out, int nrhs, in
     p->mv_batch->run(s, p);
 }
 
+// out = K~(Z, X) alpha for nrhs columns (rows: the plan's targets), batched
+// like plan_matvec.
+void plan_predict(anova_plan_s *p, const double *alpha, double *out, int nrhs, int64_t lda,
+                  int64_t ldo, hipStream_t s) {
+    BatchProblem bp;
+    bp.plan = p;
+    bp.alpha = alpha;
+    bp.out = out;
+    bp.nrhs = nrhs;
+    bp.ld = lda;
+    bp.ld_out = ldo;
+    bp.predict = true;
+    const std::vector<BatchProblem> probs{bp};
+    if (!p->pred_batch) p->pred_batch.reset(new Batch());
+    if (!p->pred_batch->same(probs)) p->pred_batch->build(probs);
+    p->pred_batch->run(s, p);
+}
+
 }  // namespace anova
 
 using namespace anova;
@@ -778,13 +796,14 @@ static anova_status guarded(F &&f) {
 
 size_t anova::plan_device_bytes(const anova_plan_s *p) {
     size_t b = 0;
-    for (const std::vector<WindowPlan> *ws : {&p->win, &p->win64})
+    for (const std::vector<WindowPlan> *ws : {&p->win, &p->win64, &p->tgt})
       for (const WindowPlan &w : *ws)
         for (const DevBuf *d : {&w.nodes, &w.perm, &w.subs, &w.poly, &w.bconv, &w.ctaps, &w.twiddle,
                                 &w.src_sub, &w.cell_start, &w.tiles_ne, &w.fold_pairs,
                                 &w.fold_start, &w.fold_tiles})
             b += d->bytes;
     if (p->mv_batch) b += p->mv_batch->device_bytes();
+    if (p->pred_batch) b += p->pred_batch->device_bytes();
     return b;
 }
 
@@ -877,18 +896,25 @@ static double time_window(anova_plan_s &one, const double *alpha, double *out, i
     return best;
 }
 
-// Plan from validated arguments and host points Xh (rows ldx apart).
+// Plan from validated arguments and host points Xh (rows ldx apart); with
+// targets Zh (Nz rows ldz apart) also a prediction plan, whose periods and
+// centres are chosen for both point sets together.
 static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, int32_t d,
                               int64_t ldx, const anova_window *win, int32_t P,
-                              const anova_params *prm) {
+                              const anova_params *prm, const double *Zh = nullptr,
+                              int64_t Nz = 0, int64_t ldz = 0) {
     anova_plan_s *p = nullptr;
     anova_status st = guarded([&] {
         for (size_t i = 0; i < (size_t)N; ++i)
             for (int t = 0; t < d; ++t)
                 ANOVA_REQUIRE(std::isfinite(Xh[i * ldx + t]), "X holds a non-finite value");
+        for (size_t i = 0; i < (size_t)Nz; ++i)
+            for (int t = 0; t < d; ++t)
+                ANOVA_REQUIRE(std::isfinite(Zh[i * ldz + t]), "Z holds a non-finite value");
         p = new anova_plan_s();
         ANOVA_HIP_CHECK(hipGetDevice(&p->device));
         p->N = N; p->d = d; p->P = P; p->precision = prm->precision; p->ell = prm->ell;
+        p->Nz = Zh ? Nz : 0;
         p->win.resize(P);
         double eta_abs = 0.0;
         for (int l = 0; l < P; ++l) eta_abs += std::fabs(win[l].eta);
@@ -907,6 +933,14 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
                 lo[t] = hi[t] = Xh[w.feat[t]];
                 for (int64_t i = 1; i < N; ++i) {
                     const double v = Xh[(size_t)i * ldx + w.feat[t]];
+                    lo[t] = std::min(lo[t], v);
+                    hi[t] = std::max(hi[t], v);
+                }
+                // targets: every difference z - x enters the periodised
+                // kernel, so the box holds both sets (Sec. 4.2 scales both
+                // into the same torus)
+                for (int64_t i = 0; Zh && i < Nz; ++i) {
+                    const double v = Zh[(size_t)i * ldz + w.feat[t]];
                     lo[t] = std::min(lo[t], v);
                     hi[t] = std::max(hi[t], v);
                 }
@@ -966,6 +1000,22 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
                 build_window<double, NodeF64>(v, Xh, N, ldx, ANOVA_FP64);
             }
         }
+        if (Zh) {
+            // the targets binned on the same grids, in the plan's precision
+            p->tgt.resize(P);
+            for (int l = 0; l < P; ++l) {
+                const WindowPlan &w = p->win[l];
+                WindowPlan &v = p->tgt[l];
+                v.dA = w.dA; v.eta = w.eta; v.ell = w.ell; v.h = w.h; v.extent = w.extent;
+                v.M = w.M; v.n = w.n; v.m = w.m; v.kb_b = w.kb_b;
+                v.launch_windows = w.launch_windows;
+                v.err_images = w.err_images; v.err_trunc = w.err_trunc;
+                v.err_window = w.err_window; v.err_round = w.err_round;
+                v.err_total = w.err_total;
+                for (int t = 0; t < 3; ++t) { v.feat[t] = w.feat[t]; v.center[t] = w.center[t]; }
+                build_for(v, Zh, Nz, ldz, prm->precision);
+            }
+        }
         if (prm->target_err > 0) {
             double tot = 0.0;
             for (auto &w : p->win) tot += w.err_total;
@@ -1018,6 +1068,68 @@ extern "C" anova_status anova_fastsum_plan_host(anova_plan_t *out, const double 
     const anova_status st = guarded([&] { validate(X, N, d, ldx, win, P, prm); });
     if (st != ANOVA_OK) return st;
     return make_plan(out, X, N, d, ldx, win, P, prm);
+}
+
+static void validate_targets(const double *Z, int64_t Nz, int32_t d, int64_t ldz) {
+    ANOVA_REQUIRE(Z != nullptr, "Z is NULL");
+    ANOVA_REQUIRE(Nz >= 1 && Nz <= 2147483647LL, "Nz must be in [1, 2^31-1]");
+    ANOVA_REQUIRE(ldz >= d, "ldz must be >= d");
+}
+
+extern "C" anova_status anova_predict_plan(anova_plan_t *out, const double *X, int64_t N,
+                                           const double *Z, int64_t Nz, int32_t d, int64_t ldx,
+                                           int64_t ldz, const anova_window *win, int32_t P,
+                                           const anova_params *prm, void *stream) {
+    if (!out) {
+        set_error("out is NULL");
+        return ANOVA_E_INVALID;
+    }
+    *out = nullptr;
+    std::vector<double> Xh, Zh;
+    const anova_status st = guarded([&] {
+        validate(X, N, d, ldx, win, P, prm);
+        validate_targets(Z, Nz, d, ldz);
+        hipStream_t s = (hipStream_t)stream;
+        ANOVA_HIP_CHECK(hipStreamSynchronize(s));
+        const size_t cx = (size_t)(N - 1) * ldx + d, cz = (size_t)(Nz - 1) * ldz + d;
+        Xh.resize(cx);
+        Zh.resize(cz);
+        std::lock_guard<std::recursive_mutex> lock(device_mutex());
+        ANOVA_HIP_CHECK(hipMemcpy(Xh.data(), X, cx * sizeof(double), hipMemcpyDeviceToHost));
+        ANOVA_HIP_CHECK(hipMemcpy(Zh.data(), Z, cz * sizeof(double), hipMemcpyDeviceToHost));
+    });
+    if (st != ANOVA_OK) return st;
+    return make_plan(out, Xh.data(), N, d, ldx, win, P, prm, Zh.data(), Nz, ldz);
+}
+
+extern "C" anova_status anova_predict_plan_host(anova_plan_t *out, const double *X, int64_t N,
+                                                const double *Z, int64_t Nz, int32_t d,
+                                                int64_t ldx, int64_t ldz, const anova_window *win,
+                                                int32_t P, const anova_params *prm) {
+    if (!out) {
+        set_error("out is NULL");
+        return ANOVA_E_INVALID;
+    }
+    *out = nullptr;
+    const anova_status st = guarded([&] {
+        validate(X, N, d, ldx, win, P, prm);
+        validate_targets(Z, Nz, d, ldz);
+    });
+    if (st != ANOVA_OK) return st;
+    return make_plan(out, X, N, d, ldx, win, P, prm, Z, Nz, ldz);
+}
+
+extern "C" anova_status anova_predict(anova_plan_t p, const double *alpha, double *out,
+                                      int32_t nrhs, int64_t lda, int64_t ldo, void *stream) {
+    return guarded([&] {
+        ANOVA_REQUIRE(p != nullptr, "NULL plan");
+        ANOVA_REQUIRE(p->Nz > 0 && (int)p->tgt.size() == p->P, "the plan has no targets");
+        ANOVA_REQUIRE(alpha != nullptr && out != nullptr, "NULL vector");
+        ANOVA_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+        ANOVA_REQUIRE(lda >= p->N, "lda must be >= N");
+        ANOVA_REQUIRE(ldo >= p->Nz, "ldo must be >= Nz");
+        plan_predict(p, alpha, out, nrhs, lda, ldo, (hipStream_t)stream);
+    });
 }
 
 extern "C" anova_status anova_plan_destroy(anova_plan_t p) {

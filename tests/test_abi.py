@@ -115,3 +115,31 @@ def test_newer_entry_points_validate_before_device_work(lib):
     assert lib.krr_cg_solve_batched(0, None, None, None, None, None, None, 1e-6, 10, None,
                                     None) == _lib.ANOVA_E_INVALID
     assert lib.anova_plan_destroy(None) == _lib.ANOVA_OK
+
+
+def test_prediction_entry_points_validate_before_device_work(lib):
+    from paper_2111_10140_amd import _lib
+    h = ctypes.c_void_p()
+    wins = _lib.make_windows([((0, 1, 2), 1.0)])
+    prm = _lib.make_params(0.2)
+    X = (ctypes.c_double * 30)()
+    Z = (ctypes.c_double * 12)()
+    # NULL targets, empty target set, short target rows, NULL handle
+    assert lib.anova_predict_plan_host(ctypes.byref(h), X, 10, None, 4, 3, 3, 3, wins, 1,
+                                       ctypes.byref(prm)) == _lib.ANOVA_E_INVALID
+    assert "Z" in _lib.anova_last_error()
+    assert lib.anova_predict_plan_host(ctypes.byref(h), X, 10, Z, 0, 3, 3, 3, wins, 1,
+                                       ctypes.byref(prm)) == _lib.ANOVA_E_INVALID
+    assert "Nz" in _lib.anova_last_error()
+    assert lib.anova_predict_plan_host(ctypes.byref(h), X, 10, Z, 4, 3, 3, 2, wins, 1,
+                                       ctypes.byref(prm)) == _lib.ANOVA_E_INVALID
+    assert "ldz" in _lib.anova_last_error()
+    assert lib.anova_predict_plan_host(None, X, 10, Z, 4, 3, 3, 3, wins, 1,
+                                       ctypes.byref(prm)) == _lib.ANOVA_E_INVALID
+    # the training-point checks still apply
+    assert lib.anova_predict_plan_host(ctypes.byref(h), None, 10, Z, 4, 3, 3, 3, wins, 1,
+                                       ctypes.byref(prm)) == _lib.ANOVA_E_INVALID
+    assert lib.anova_predict_plan(ctypes.byref(h), ctypes.c_void_p(16), 10, None, 4, 3, 3, 3,
+                                  wins, 1, ctypes.byref(prm), None) == _lib.ANOVA_E_INVALID
+    assert h.value is None
+    assert lib.anova_predict(None, None, None, 1, 10, 4, None) == _lib.ANOVA_E_INVALID

@@ -24,6 +24,9 @@ Workloads
                     beta=0.5.
 ``serving``         Poisson stream of requests with N uniform in [1000, 500000],
                     d in {6, 9, 12}, ell uniform in [0.1, 0.4], 1..8 RHS.
+``train_test``      a feature-grouped training problem and Nz test points
+                    from the same distribution (or a wider box), for
+                    prediction at new points.
 """
 from __future__ import annotations
 
@@ -229,3 +232,22 @@ def random_problem(N: int, d: int, windows: Sequence[Tuple[int, ...]], ell: floa
     alpha = np.asfortranarray(rng.standard_normal((N, nrhs)))
     y = np.asfortranarray(rng.standard_normal((N, nrhs)))
     return Problem(f"random_N{N}_d{d}_s{seed}", X, wins, ell, beta, alpha, y)
+
+
+def train_test(N: int, Nz: int, d: int = 9, seed: int = 6, ell: float = 0.2,
+               test_lo: float = LO, test_hi: float = HI) -> Tuple[Problem, np.ndarray]:
+    """Training problem shaped like ``feature_grouped`` (d features uniform in
+    [-1/4, 1/4), consecutive triples as windows with weights 1/P, beta = 1)
+    and Nz test points uniform in [test_lo, test_hi)^d drawn after it from the
+    same generator; the paper's experiments split each sample into training
+    and test halves (Sec. 6).  Returns (problem, Z)."""
+    rng = np.random.default_rng(seed)
+    X = _uniform_points(rng, N, d)
+    wins = consecutive_windows(d)
+    alpha = rng.standard_normal((N, 1))
+    y = (sum(_smooth_target(X[:, list(w.feat)]) for w in wins)
+         + rng.normal(0.0, 0.1, size=N))[:, None]
+    Z = np.ascontiguousarray(rng.uniform(test_lo, test_hi, size=(Nz, d)))
+    prob = Problem(f"train_test_N{N}_Nz{Nz}_s{seed}", X, wins, ell, 1.0,
+                   np.asfortranarray(alpha), np.asfortranarray(y))
+    return prob, Z
