@@ -294,6 +294,35 @@ anova_status krr_cg_solve_batched(int32_t count, const anova_plan_t *plans,
                                   const int32_t *nrhs, const int64_t *ld, const double *beta,
                                   double tol, int32_t maxit, krr_cg_info *info, void *stream);
 
+/*
+ * Solve (K~ + lambda_s I) alpha_s = y for nshift regularisation parameters
+ * lambda_s at once (the grid over the regularisation parameter in the
+ * paper's grid search, Sec. 6; each system is the normal equation of
+ * Sec. 2).  The systems share one Krylov space: CG runs on the system with
+ * the smallest lambda, and every other system's residual stays a multiple
+ * zeta_s of its residual (shifted CG), so one kernel product per iteration
+ * serves all of them; each adds two float64 vector updates per iteration.
+ * A system stops when zeta_s ||r|| <= tol ||y||.  Then each system's true
+ * residual y - (K~ + lambda_s I) alpha_s is recomputed (float64 product;
+ * on FP32_NFFT plans the plan's float64 residual windows when it has them),
+ * and one that misses tol ||y|| is refined by krr_cg_solve on that
+ * residual.  x0 = 0; no preconditioner.
+ * y: device, N floats64.  alpha: device, N x nshift column-major, leading
+ * dimension ld >= N; column s solves for shifts[s].  shifts: host, nshift
+ * values, finite and > 0 (any order, repeats allowed).  info: host array
+ * of nshift entries (may be NULL): iters counts the shared iterations the
+ * system took part in plus any refinement iterations; relres is the recursive (or refinement)
+ * residual, true_relres the recomputed one, both / ||y||.
+ * Synchronises `stream`.  Returns ANOVA_E_NOT_CONVERGED if some system
+ * missed tol within maxit (alpha holds the last iterates),
+ * ANOVA_E_BREAKDOWN on p^T A p <= 0 or NaN.
+ * Errors: ANOVA_E_INVALID for a NULL plan/pointer, nshift < 1 or > 32, a
+ * shift <= 0 or non-finite, ld < N, tol < 0, maxit < 1.
+ */
+anova_status krr_cg_solve_shifts(anova_plan_t plan, const double *y, double *alpha,
+                                 int32_t nshift, const double *shifts, int64_t ld, double tol,
+                                 int32_t maxit, krr_cg_info *info, void *stream);
+
 /* Free every resource of the plan (synchronises the device).  NULL is a no-op. */
 anova_status anova_plan_destroy(anova_plan_t plan);
 

@@ -109,6 +109,8 @@ def load():
                                     ctypes.POINTER(anova_window), i32,
                                     ctypes.POINTER(anova_params)],
         "anova_predict": [VP, VP, VP, i32, i64, i64, VP],
+        "krr_cg_solve_shifts": [VP, VP, VP, i32, ctypes.POINTER(dbl), i64, dbl, i32,
+                                ctypes.POINTER(krr_cg_info), VP],
     }
     for name, args in sigs.items():
         fn = getattr(lib, name)
@@ -345,6 +347,28 @@ def krr_cg_solve(plan: Plan, y, alpha, beta: float, tol: float, maxit: int, stre
     info = (krr_cg_info * nrhs)()
     st = load().krr_cg_solve(plan.handle, py, pa, nrhs, lda, float(beta), float(tol), int(maxit),
                              info, _stream(stream))
+    allow = (ANOVA_OK, ANOVA_E_NOT_CONVERGED) if allow_not_converged else (ANOVA_OK,)
+    _check(st, allow)
+    return [dict(iters=i.iters, converged=bool(i.converged), relres=i.relres,
+                 true_relres=i.true_relres, status=STATUS_NAMES[st]) for i in info]
+
+
+def krr_cg_solve_shifts(plan: Plan, y, alpha, shifts, tol: float, maxit: int, stream=None,
+                        allow_not_converged: bool = False):
+    """Solve (K~ + shifts[s] I) alpha[:, s] = y for every shift at once;
+    y: (N,), alpha: (N, len(shifts)) column-major.  Returns a list of info
+    dicts, one per shift."""
+    py, ny, _ = _colmajor(y, "y", plan.N)
+    if ny != 1:
+        raise ValueError("y must be one column")
+    S = len(shifts)
+    pa, na, lda = _colmajor(alpha, "alpha", plan.N)
+    if na != S:
+        raise ValueError("alpha must have one column per shift")
+    sh = (ctypes.c_double * S)(*[float(v) for v in shifts])
+    info = (krr_cg_info * S)()
+    st = load().krr_cg_solve_shifts(plan.handle, py, pa, S, sh, lda, float(tol), int(maxit), info,
+                                    _stream(stream))
     allow = (ANOVA_OK, ANOVA_E_NOT_CONVERGED) if allow_not_converged else (ANOVA_OK,)
     _check(st, allow)
     return [dict(iters=i.iters, converged=bool(i.converged), relres=i.relres,

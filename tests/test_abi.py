@@ -143,3 +143,12 @@ def test_prediction_entry_points_validate_before_device_work(lib):
                                   wins, 1, ctypes.byref(prm), None) == _lib.ANOVA_E_INVALID
     assert h.value is None
     assert lib.anova_predict(None, None, None, 1, 10, 4, None) == _lib.ANOVA_E_INVALID
+
+
+def test_shifted_cg_validates_before_device_work(lib):
+    from paper_2111_10140_amd import _lib
+    sh = (ctypes.c_double * 2)(1.0, 10.0)
+    info = (_lib.krr_cg_info * 2)()
+    assert lib.krr_cg_solve_shifts(None, None, None, 2, sh, 10, 1e-6, 10, info,
+                                   None) == _lib.ANOVA_E_INVALID
+    assert "plan" in _lib.anova_last_error()
