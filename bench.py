@@ -60,6 +60,7 @@ def parse():
     ap.add_argument("--skip-tuned", action="store_true")
     ap.add_argument("--skip-large", action="store_true")
     ap.add_argument("--skip-predict", action="store_true")
+    ap.add_argument("--skip-grid", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run 5 device-to-device copies of 1 GiB (counter calibration)")
     return ap.parse_args()
@@ -353,6 +354,53 @@ def predict_config(A, torch, steps):
     return res
 
 
+def grid_config(A, torch, N=100_000, seed=1):
+    """The regularisation grid of the paper's grid search (lambda in {1, 10,
+    100, 1000}) on the feature-grouped workload (float32 plan, CG tol 1e-6):
+    one shifted-CG solve for all four systems, against the four systems
+    solved together by the batched single-shift solver and one after
+    another."""
+    import workloads
+    p = workloads.feature_grouped(N, seed=seed)
+    grid = [1.0, 10.0, 100.0, 1000.0]
+    X = torch.from_numpy(p.X).cuda()
+    y = torch.from_numpy(np.ascontiguousarray(p.y[:, 0])).cuda()
+    plan = A.anova_fastsum_plan(X, p.windows, A.make_params(p.ell, A.ANOVA_FP32_NFFT))
+    xs = torch.empty((len(grid), p.N), dtype=torch.float64, device="cuda").T
+    A.krr_cg_solve_shifts(plan, y, xs, grid, 1e-6, 5000)  # warm-up (graphs, work space)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    info = A.krr_cg_solve_shifts(plan, y, xs, grid, 1e-6, 5000)
+    torch.cuda.synchronize()
+    t_shift = time.perf_counter() - t
+    xb = [torch.empty_like(y) for _ in grid]
+    A.krr_cg_solve_batched([plan] * len(grid), [y] * len(grid), xb, grid, 1e-6, 5000)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ib = A.krr_cg_solve_batched([plan] * len(grid), [y] * len(grid), xb, grid, 1e-6, 5000)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t
+    t = time.perf_counter()
+    iters_one = []
+    for lam, xo in zip(grid, xb):
+        iters_one.append(A.krr_cg_solve(plan, y, xo, lam, 1e-6, 5000)[0]["iters"])
+    torch.cuda.synchronize()
+    t_seq = time.perf_counter() - t
+    diff = max(float(torch.linalg.norm(xs[:, k] - xb[k]) / torch.linalg.norm(xb[k]))
+               for k in range(len(grid)))
+    plan.destroy()
+    return {"workload": f"feature_grouped N={N}, float32 plan, lambda in {{1,10,100,1000}}, "
+                        "CG tol 1e-6",
+            "shifted_seconds": round(t_shift, 4), "batched_seconds": round(t_batch, 4),
+            "sequential_seconds": round(t_seq, 4),
+            "speedup_vs_batched": round(t_batch / t_shift, 2),
+            "speedup_vs_sequential": round(t_seq / t_shift, 2),
+            "shifted_iters": [i["iters"] for i in info],
+            "single_iters": iters_one,
+            "true_relres": [i["true_relres"] for i in info],
+            "max_rel_diff_vs_single": diff}
+
+
 def serving(args, A):
     """Served KRR solves: closed-loop capacity (every request queued at t=0),
     the same with one request at a time, then Poisson arrivals at
@@ -533,6 +581,10 @@ def main():
         batched = batched_config(A, torch)
         print(f"# batched: {json.dumps(batched)}", file=sys.stderr, flush=True)
     large = None if args.skip_large else large_config(A, torch)
+    gridded = None
+    if not args.skip_grid:
+        gridded = [grid_config(A, torch), grid_config(A, torch, N, 2)]
+        print(f"# grid: {json.dumps(gridded)}", file=sys.stderr, flush=True)
     predicted = None
     if not args.skip_predict:
         predicted = predict_config(A, torch, max(10, args.steps // 2))
@@ -559,6 +611,7 @@ def main():
         "batched": batched,
         "large": large,
         "predict": predicted,
+        "lambda_grid": gridded,
         "serving": served,
         "cpu_baseline": cpu,
     }

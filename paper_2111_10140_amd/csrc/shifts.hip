@@ -321,6 +321,16 @@ __global__ __launch_bounds__(kMsBlock) void ms_col_sums_kernel(const double *__r
     if (threadIdx.x == 0) out[blockIdx.x] = v;
 }
 
+// A captured run of kCheckEvery iterations and the stream it was captured on.
+struct MsGraph {
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~MsGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
 // x += d
 __global__ __launch_bounds__(kMsBlock) void ms_axpy_kernel(double *__restrict__ x,
                                                            const double *__restrict__ d, int64_t N) {
@@ -396,30 +406,55 @@ extern "C" anova_status krr_cg_solve_shifts(anova_plan_t plan, const double *y, 
                 bp.beta = lam0;
                 prod.build({bp});
             }
+            // one iteration: the product, then five small kernels; the
+            // launches after the last shift stops change nothing, so
+            // kCheckEvery iterations are captured into one graph and the
+            // host checks for completion between replays
+            auto record = [&](hipStream_t cs) {
+                prod.run(cs);
+                hipLaunchKernelGGL(ms_dot_kernel, dim3(nblk), dim3(kMsBlock), 0, cs, pbase, q, N,
+                                   dst, dpart);
+                hipLaunchKernelGGL(ms_alpha_kernel, dim3(1), dim3(kMsBlock), 0, cs, dst, dpart,
+                                   nblk);
+                hipLaunchKernelGGL(ms_update_r_kernel, dim3(nblk), dim3(kMsBlock), 0, cs, r, q, N,
+                                   dst, dpart);
+                hipLaunchKernelGGL(ms_shift_scal_kernel, dim3(1), dim3(kMsBlock), 0, cs, dtab, S,
+                                   dst, dpart, nblk);
+                hipLaunchKernelGGL(ms_update_kernel, dim3(nblk), dim3(kMsBlock), 0, cs, r, dtab,
+                                   S, N, dst);
+                ANOVA_HIP_CHECK(hipGetLastError());
+            };
+            MsGraph G;
+            {
+                // capturing must not overlap other threads' allocations
+                std::lock_guard<std::recursive_mutex> lock(device_mutex());
+                ANOVA_HIP_CHECK(hipStreamCreateWithFlags(&G.cap, hipStreamNonBlocking));
+                hipGraph_t g = nullptr;
+                ANOVA_HIP_CHECK(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
+                try {
+                    for (int j = 0; j < kCheckEvery; ++j) record(G.cap);
+                } catch (...) {
+                    (void)hipStreamEndCapture(G.cap, &g);
+                    if (g) (void)hipGraphDestroy(g);
+                    throw;
+                }
+                ANOVA_HIP_CHECK(hipStreamEndCapture(G.cap, &g));
+                const hipError_t e = hipGraphInstantiate(&G.exec, g, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(g);
+                ANOVA_HIP_CHECK(e);
+            }
             hipLaunchKernelGGL(ms_init_kernel, dim3(nblk), dim3(kMsBlock), 0, s, y, r, dtab, S, N,
                                dpart);
             hipLaunchKernelGGL(ms_init_scal_kernel, dim3(1), dim3(kMsBlock), 0, s, dtab, S, dst,
                                dpart, nblk, tol, maxit);
             ANOVA_HIP_CHECK(hipGetLastError());
             MsState hst{};
-            for (int it = 0;; ++it) {
-                if (it % kCheckEvery == 0) {
-                    ANOVA_HIP_CHECK(hipMemcpyAsync(&hst, dst, sizeof(MsState),
-                                                   hipMemcpyDeviceToHost, s));
-                    ANOVA_HIP_CHECK(hipStreamSynchronize(s));
-                    if (!hst.any) break;
-                }
-                prod.run(s);
-                hipLaunchKernelGGL(ms_dot_kernel, dim3(nblk), dim3(kMsBlock), 0, s, pbase, q, N,
-                                   dst, dpart);
-                hipLaunchKernelGGL(ms_alpha_kernel, dim3(1), dim3(kMsBlock), 0, s, dst, dpart, nblk);
-                hipLaunchKernelGGL(ms_update_r_kernel, dim3(nblk), dim3(kMsBlock), 0, s, r, q, N,
-                                   dst, dpart);
-                hipLaunchKernelGGL(ms_shift_scal_kernel, dim3(1), dim3(kMsBlock), 0, s, dtab, S,
-                                   dst, dpart, nblk);
-                hipLaunchKernelGGL(ms_update_kernel, dim3(nblk), dim3(kMsBlock), 0, s, r, dtab, S,
-                                   N, dst);
-                ANOVA_HIP_CHECK(hipGetLastError());
+            for (;;) {
+                ANOVA_HIP_CHECK(hipMemcpyAsync(&hst, dst, sizeof(MsState), hipMemcpyDeviceToHost,
+                                               s));
+                ANOVA_HIP_CHECK(hipStreamSynchronize(s));
+                if (!hst.any) break;
+                ANOVA_HIP_CHECK(hipGraphLaunch(G.exec, s));
             }
             std::vector<MsShift> fin(S);
             ANOVA_HIP_CHECK(hipMemcpyAsync(fin.data(), dtab, (size_t)S * sizeof(MsShift),
