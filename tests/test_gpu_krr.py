@@ -1,0 +1,57 @@
+"""End to end on the GPU: z-scoring and MIS windows (Sec. 5, Sec. 6), CG fit
+(Sec. 2), prediction at test points (Sec. 4.2, Sec. 4.3), and the grid
+search over sigma and lambda (Sec. 6) with a shifted solve per sigma.  The
+decision values are checked against the oracle's two-set direct sum with
+the GPU's coefficients; accuracies against the synthetic labels."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2111_10140_amd import krr
+    return krr
+
+
+def test_fit_predict_end_to_end(K):
+    X, y, Z, yz = workloads.labelled(20000, 5000)
+    m = K.KernelRidge(sigma=1.0, lam=1.0, tol=1e-3).fit(X, y)
+    assert set(m.windows_[0][0]) == {2, 5, 7}
+    assert m.fit_info_["converged"]
+    s = m.decision_function(Z)
+    acc = float(np.mean(np.where(s >= 0, 1.0, -1.0) == yz))
+    alpha = m.alpha_.cpu().numpy()
+    rows = np.sort(np.random.default_rng(60).choice(Z.shape[0], 300, replace=False))
+    ref = oracle.direct.anova_predict(m._scaled(Z), m.X_, m.windows_, m.sigma, alpha, rows=rows)
+    e = float(np.max(np.abs(s[rows] - ref)) / np.abs(alpha).sum())
+    print(f"windows {m.windows_}, CG {m.fit_info_['iters']} iterations, accuracy {acc:.4f}, "
+          f"decision E = {e:.3e}", flush=True)
+    assert e <= 1e-4
+    assert acc >= 0.85
+    assert np.array_equal(m.predict(Z), np.where(s >= 0, 1.0, -1.0))
+
+
+def test_grid_search(K):
+    X, y, Z, yz = workloads.labelled(8000, 2000, seed=51)
+    res = K.grid_search(X, y, Z, yz, sigmas=[1e-3, 0.5, 1.0, 2.0],
+                        lambdas=[1.0, 10.0, 100.0, 1000.0], tol=1e-3)
+    for r in res["table"]:
+        print(r, flush=True)
+    # a width far below the data's spacing cannot meet the error target
+    assert not res["table"][0]["feasible"] and res["table"][0]["sigma"] == 1e-3
+    cells = [r for r in res["table"] if r["feasible"]]
+    assert len(cells) == 12 and all(r["converged"] for r in cells)
+    assert res["best"]["accuracy"] >= 0.85
+    # one cell against a fit of its own
+    one = K.KernelRidge(sigma=1.0, lam=10.0, tol=1e-3).fit(X, y)
+    acc1 = float(np.mean(one.predict(Z) == yz))
+    cell = [r for r in cells if r["sigma"] == 1.0 and r["lam"] == 10.0][0]
+    print(f"cell accuracy {cell['accuracy']:.4f}, own fit {acc1:.4f}", flush=True)
+    assert abs(cell["accuracy"] - acc1) <= 0.01

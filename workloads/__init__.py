@@ -27,6 +27,8 @@ Workloads
 ``train_test``      a feature-grouped training problem and Nz test points
                     from the same distribution (or a wider box), for
                     prediction at new points.
+``labelled``        raw (unscaled) features with +-1 labels that depend on
+                    three of them, split into training and test sets.
 """
 from __future__ import annotations
 
@@ -251,3 +253,28 @@ def train_test(N: int, Nz: int, d: int = 9, seed: int = 6, ell: float = 0.2,
     prob = Problem(f"train_test_N{N}_Nz{Nz}_s{seed}", X, wins, ell, 1.0,
                    np.asfortranarray(alpha), np.asfortranarray(y))
     return prob, Z
+
+
+def labelled(N: int, Nz: int, d: int = 9, informative: Tuple[int, int, int] = (2, 5, 7),
+             seed: int = 50, flip: float = 0.05):
+    """Binary classification data in raw units: feature j uniform on
+    [0, scale_j) with scales from 0.1 to 100 (so that z-scoring matters),
+    label sign(sin(pi u_a) + 0.7 u_b + 0.5 u_c) on the informative features
+    u = (x - mean) / std (population statistics), each label flipped with
+    probability `flip` (each term is informative on its own: the paper's
+    score is univariate, Sec. 5).  The paper classifies z-scored data with labels in
+    {-1, 1} (Sec. 2, Sec. 6).  Returns (X, y, Z, yz) for N training and Nz
+    test points."""
+    rng = np.random.default_rng(seed)
+    scales = np.exp(rng.uniform(math.log(0.1), math.log(100.0), size=d))
+    def draw(n):
+        X = rng.uniform(0.0, 1.0, size=(n, d)) * scales
+        u = (X / scales - 0.5) * math.sqrt(12.0)
+        a, b, c = informative
+        g = np.sin(math.pi * u[:, a]) + 0.7 * u[:, b] + 0.5 * u[:, c]
+        y = np.where(g >= 0.0, 1.0, -1.0)
+        y = np.where(rng.uniform(size=n) < flip, -y, y)
+        return np.ascontiguousarray(X), y
+    X, y = draw(N)
+    Z, yz = draw(Nz)
+    return X, y, Z, yz
