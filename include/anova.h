@@ -308,7 +308,8 @@ anova_status krr_cg_solve_batched(int32_t count, const anova_plan_t *plans,
  * and one that misses tol ||y|| is refined by krr_cg_solve on that
  * residual.  x0 = 0; no preconditioner.
  * y: device, N floats64.  alpha: device, N x nshift column-major, leading
- * dimension ld >= N; column s solves for shifts[s].  shifts: host, nshift
+ * dimension ld >= N, not overlapping y; column s solves for shifts[s].
+ * shifts: host, nshift
  * values, finite and > 0 (any order, repeats allowed).  info: host array
  * of nshift entries (may be NULL): iters counts the shared iterations the
  * system took part in plus any refinement iterations; relres is the recursive (or refinement)

@@ -136,3 +136,24 @@ def test_padded_columns_zero_rhs_and_limits(A):
     assert info[0]["status"] == "E_NOT_CONVERGED"
     with pytest.raises(A.AnovaError):
         A.krr_cg_solve_shifts(plan, y, empty_cols(p.N, 2), [1.0, -1.0], 1e-8, 10)
+
+
+def test_headline_size_grid(A):
+    # the benchmark's grid at N = 1e6 (feature-grouped, float32 plan, tol
+    # 1e-6): every shift against its single-shift solve and 128 sampled rows
+    # of the oracle's exact product
+    p = workloads.feature_grouped(1_000_000, seed=2)
+    plan = A.anova_fastsum_plan(dev_rows(p.X), p.windows, A.make_params(p.ell, F32))
+    y = p.y[:, 0]
+    x, info = solve_shifts(A, plan, y, GRID, 1e-6, 5000)
+    rows = np.sort(np.random.default_rng(45).choice(p.N, 128, replace=False))
+    for s, lam in enumerate(GRID):
+        assert info[s]["converged"] and info[s]["true_relres"] <= 1e-6
+        one, _ = solve_one(A, plan, y, lam, 1e-6, 5000)
+        d = np.linalg.norm(x[:, s] - one) / np.linalg.norm(one)
+        Ax = oracle.direct.anova_matvec(p.X, p.windows, p.ell, lam, x[:, s], rows=rows)
+        res = np.max(np.abs(y[rows] - Ax)) / np.abs(x[:, s]).sum()
+        print(f"N=1e6 lambda {lam}: iters {info[s]['iters']}, ||x - x_alone|| / ||x_alone|| "
+              f"= {d:.3e}, sampled exact residual / ||x||_1 = {res:.3e}", flush=True)
+        assert d <= 2e-3
+        assert res <= 1e-4
