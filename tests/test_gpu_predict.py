@@ -186,3 +186,17 @@ def test_full_size_sampled_rows(A):
     e, est = check(A, p, Z, plan, p.alpha[:, 0], 1e-4, rows=rows)
     assert e <= est
     assert all(plan.info(l).per_cell for l in range(plan.P))
+
+
+def test_host_plan_equals_device_plan(A):
+    # the same plan built from host arrays gives the same predictions, bit for bit
+    p, Z = workloads.train_test(9000, 4000, seed=33)
+    prm = A.make_params(p.ell, F32, target_err=1e-4)
+    dev = A.anova_predict_plan(dev_rows(p.X), dev_rows(Z), p.windows, prm)
+    host = A.anova_predict_plan_host(p.X, Z, p.windows, prm)
+    assert host.Nz == dev.Nz == Z.shape[0]
+    for l in range(dev.P):
+        a, b = dev.info(l), host.info(l)
+        assert (a.M, a.n, a.m, a.h, a.center) == (b.M, b.n, b.m, b.h, b.center)
+    np.testing.assert_array_equal(gpu_predict(A, host, p.alpha[:, 0]),
+                                  gpu_predict(A, dev, p.alpha[:, 0]))
