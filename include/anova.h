@@ -97,6 +97,17 @@ typedef struct {
                             whose product runs fastest on this device (the
                             plan then launches kernels and takes several
                             times longer) */
+    int32_t reg_q;       /* 0: periodise the Gaussian, with h large enough
+                            that its periodic images decay (or the given h);
+                            1..12: regularise it instead (Sec. 4.2), in each
+                            dimension: keep exp(-r^2/ell^2) for |r| <= L (L
+                            the window's extent, so the kernel is exact for
+                            every pair of points) and join it to its h-periodic
+                            continuation on (L, h - L) by the polynomial
+                            matching its derivatives of orders 0..reg_q at
+                            both ends; h must exceed 2L (when 0 the cheapest
+                            of 2.5L, 3L and 4L).  Serves kernels too wide
+                            for the given h. */
 } anova_params;
 
 /* Residual product of CG on FP32_NFFT plans.  The float32 product's rounding
@@ -151,7 +162,8 @@ typedef struct {
  * d < 1, ldx < d, P < 1, P > 64, d_A not in {1,2,3}, a feature index out of
  * range or repeated inside one window, a non-finite eta or X, ell <= 0,
  * odd M, n not a power of two or n < M, m out of range, residual not an anova_residual,
- * tune not 0 or 1.
+ * tune not 0 or 1, reg_q outside 0..12, and with reg_q > 0 an h not above
+ * twice the extent.
  * ANOVA_E_ACCURACY when fixed parameters miss target_err.
  */
 anova_status anova_fastsum_plan(anova_plan_t *out, const double *X, int64_t N, int32_t d,

@@ -40,7 +40,8 @@ class anova_params(ctypes.Structure):
     _fields_ = [("ell", ctypes.c_double), ("precision", ctypes.c_int32), ("M", ctypes.c_int32),
                 ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("h", ctypes.c_double),
                 ("target_err", ctypes.c_double), ("center", ctypes.c_int32),
-                ("residual", ctypes.c_int32), ("tune", ctypes.c_int32)]
+                ("residual", ctypes.c_int32), ("tune", ctypes.c_int32),
+                ("reg_q", ctypes.c_int32)]
 
 
 class anova_window_info(ctypes.Structure):
@@ -173,11 +174,11 @@ def make_windows(windows) -> "ctypes.Array":
 
 def make_params(ell: float, precision: int = ANOVA_FP32_NFFT, M: int = 0, m: int = 0, n: int = 0,
                 h: float = 0.0, target_err: float = 0.0, center: int = 0,
-                residual: int = 0, tune: int = 0) -> anova_params:
+                residual: int = 0, tune: int = 0, reg_q: int = 0) -> anova_params:
     p = anova_params()
     p.ell, p.precision, p.M, p.m, p.n = float(ell), int(precision), int(M), int(m), int(n)
     p.h, p.target_err, p.center, p.residual = float(h), float(target_err), int(center), int(residual)
-    p.tune = int(tune)
+    p.tune, p.reg_q = int(tune), int(reg_q)
     return p
 
 

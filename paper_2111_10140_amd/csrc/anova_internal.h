@@ -113,6 +113,7 @@ struct WindowPlan {
     int dA = 0, M = 0, n = 0, m = 0;
     int feat[3] = {0, 0, 0};
     double eta = 0, ell = 0, h = 0, extent = 0, kb_b = 0;
+    int reg_q = 0;               // > 0: regularised kernel, exact on [-extent, extent]
     double center[3] = {0, 0, 0};
     double err_images = 0, err_trunc = 0, err_window = 0, err_round = 0, err_total = 0;
     double fit_err = 0;          // max error of the window polynomials

@@ -10,6 +10,7 @@
 // into grid cells and sorted by grid tile for the spreading and gathering
 // kernels.
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstring>
 #include <limits>
@@ -83,12 +84,13 @@ double periodized_gauss(double r, double ell, double h) {
 }
 
 // b1[k + M/2], k = -M/2..M/2-1: DFT of the M equidistant samples
-// kappa~(j h / M), j = -M/2..M/2-1, divided by M.  The periodised Gaussian is
-// a product over dimensions, and so is its sampled DFT: b_k = prod_t b1[k_t].
-// The samples are even in j, so the coefficients are real.
-std::vector<double> sampled_coeffs_1d(int M, double ell, double h) {
-    std::vector<double> samp(M), b(M);
-    for (int j = -M / 2; j < M / 2; ++j) samp[j + M / 2] = periodized_gauss(j * h / M, ell, h);
+// samp[j + M/2] = kappa~(j h / M), j = -M/2..M/2-1, divided by M.  The
+// kernel is a product over dimensions, and so is its sampled DFT:
+// b_k = prod_t b1[k_t].  The samples are even in j, so the coefficients
+// are real.
+std::vector<double> coeffs_from_samples(const std::vector<double> &samp) {
+    const int M = (int)samp.size();
+    std::vector<double> b(M);
     for (int k = -M / 2; k < M / 2; ++k) {
         long double acc = 0.0L;
         for (int j = -M / 2; j < M / 2; ++j) {
@@ -100,6 +102,96 @@ std::vector<double> sampled_coeffs_1d(int M, double ell, double h) {
     }
     return b;
 }
+
+// Coefficients of the h-periodised Gaussian.
+std::vector<double> sampled_coeffs_1d(int M, double ell, double h) {
+    std::vector<double> samp(M);
+    for (int j = -M / 2; j < M / 2; ++j) samp[j + M / 2] = periodized_gauss(j * h / M, ell, h);
+    return coeffs_from_samples(samp);
+}
+
+// ------------------------------------------------------------- regularised kernel
+// Sec. 4.2's regularisation, applied to each 1-D factor g(r) = exp(-r^2/ell^2)
+// of the Gaussian: g~ = g on [-L, L] (every coordinate difference of the
+// points lies there), and on (L, h - L) the polynomial that matches g's
+// derivatives of orders 0..q at r = L and those of its periodic
+// continuation g(r - h) at r = h - L, so that the h-periodic g~ is q times
+// continuously differentiable.  The product of the factors equals the
+// kernel wherever the points can be, so only the truncation of g~'s
+// Fourier series is an error there.
+
+// j-th derivative of g at r: (-1/ell)^j H_j(r/ell) g(r), H_j the physicists'
+// Hermite polynomials (H_{j+1} = 2u H_j - 2j H_{j-1}).
+double gauss_deriv(int j, double r, double ell) {
+    const double u = r / ell;
+    double h0 = 1.0, h1 = 2.0 * u;
+    double Hj = j == 0 ? h0 : h1;
+    for (int k = 1; k < j; ++k) {
+        const double h2 = 2.0 * u * h1 - 2.0 * k * h0;
+        h0 = h1;
+        h1 = h2;
+        Hj = h1;
+    }
+    return std::pow(-1.0 / ell, j) * Hj * std::exp(-u * u);
+}
+
+// g~(r) for |r| <= h/2 (h > 2L).  On t = (|r| - L) / (h - 2L) in (0, 1) the
+// two-point Taylor interpolant with A_j, B_j the t-derivatives at t = 0 and
+// t = 1:  p(t) = (1-t)^(q+1) sum_j A_j t^j / j! sum_{k<=q-j} C(q+k, k) t^k
+//              + t^(q+1) sum_j B_j (t-1)^j / j! sum_{k<=q-j} C(q+k, k) (1-t)^k,
+// A_j = w^j g^(j)(L), B_j = (-1)^j A_j (the continuation is g mirrored).
+double reg_gauss(double r, double ell, double L, double h, int q) {
+    r = std::fabs(r);
+    if (r <= L) return std::exp(-(r / ell) * (r / ell));
+    const double w = h - 2.0 * L, t = (r - L) / w;
+    double s0 = 0.0, s1 = 0.0, wj = 1.0, fact = 1.0;
+    for (int j = 0; j <= q; ++j) {
+        if (j > 0) {
+            wj *= w;
+            fact *= j;
+        }
+        const double Aj = wj * gauss_deriv(j, L, ell);
+        const double Bj = (j % 2 ? -1.0 : 1.0) * Aj;
+        double in0 = 0.0, in1 = 0.0, binom = 1.0, tk = 1.0, uk = 1.0;
+        for (int k = 0; k <= q - j; ++k) {
+            if (k > 0) {
+                binom = binom * (q + k) / k;
+                tk *= t;
+                uk *= 1.0 - t;
+            }
+            in0 += binom * tk;
+            in1 += binom * uk;
+        }
+        s0 += Aj * std::pow(t, j) / fact * in0;
+        s1 += Bj * std::pow(t - 1.0, j) / fact * in1;
+    }
+    return std::pow(1.0 - t, q + 1) * s0 + std::pow(t, q + 1) * s1;
+}
+
+std::vector<double> reg_coeffs_1d(int M, double ell, double h, double L, int q) {
+    std::vector<double> samp(M);
+    for (int j = -M / 2; j < M / 2; ++j) samp[j + M / 2] = reg_gauss(j * h / M, ell, L, h, q);
+    return coeffs_from_samples(samp);
+}
+
+// Largest error on [-L, L] of the 1-D series sum_{|k| < M/2} b1_k e^{2 pi i k r / h}
+// against g, measured on 1024 points (the sampled coefficients' aliasing
+// included), times 1.25 for the points between.
+double reg_err1(const std::vector<double> &b1, double ell, double h, double L) {
+    const int M = (int)b1.size();
+    double e = 0.0;
+    for (int i = 0; i <= 1024; ++i) {
+        const double r = L * i / 1024.0;
+        double v = b1[M / 2];
+        for (int k = 1; k < M / 2; ++k) v += 2.0 * b1[k + M / 2] * std::cos(2.0 * kPi * k * r / h);
+        e = std::max(e, std::fabs(v - std::exp(-(r / ell) * (r / ell))));
+    }
+    return 1.25 * e;
+}
+
+// Per-entry error of the d_A-fold product of factors each within e1 of
+// factors of size <= 1.
+double reg_trunc_dA(double e1, int dA) { return dA * e1 * std::pow(1.0 + e1, dA - 1); }
 
 // ------------------------------------------------------------- error model
 // Per-entry error estimates of one window's approximation K~_ij - K_ij for
@@ -133,11 +225,11 @@ double est_trunc(int M, double h, double ell, int dA) {
 // aliases k + r n in the window transform, plus the jump of the truncated
 // window at |t| = m; combined over dimensions and over the adjoint and the
 // forward transform, weighted by the kernel coefficients.
-double est_window(int M, int n, int m, double ell, double h, int dA) {
+double est_window_b(const std::vector<double> &b1, int n, int m, int dA) {
+    const int M = (int)b1.size();
     const double b = kPi * m * (2.0 - (double)M / n);
     const double i0b = bessel_i0(b);
     const double jump = 1.0 / i0b;
-    const std::vector<double> b1 = sampled_coeffs_1d(M, ell, h);
     double B = 0.0, BA = 0.0;
     for (int k = -(M / 2 - 1); k <= M / 2 - 1; ++k) {
         const double c = std::fabs(b1[k + M / 2]);
@@ -157,6 +249,10 @@ double est_window(int M, int n, int m, double ell, double h, int dA) {
         d += binom * std::pow(B, dA - j) * std::pow(BA, j);
     }
     return 2.0 * d;
+}
+
+double est_window(int M, int n, int m, double ell, double h, int dA) {
+    return est_window_b(sampled_coeffs_1d(M, ell, h), n, m, dA);
 }
 
 double est_round(int precision, int n, int m, int dA) {
@@ -271,8 +367,95 @@ struct Choice {
 // for that h, and puts the data's lower edge on a tile boundary (centre
 // chosen in make_plan).  It is placed just before its plain twin when the
 // per-cell launch model (best_chunks) says it runs faster, else just after.
+// Regularised kernel (prm.reg_q > 0): the period is prm.h (> 2D) or the
+// cheapest of 2.5, 3 and 4 times D; at each (h, n) the smallest m, then the
+// smallest M, whose measured truncation error (reg_err1) plus the window
+// and rounding estimates fit the budget.  There is no image error: the
+// regularised kernel equals the Gaussian wherever the points can be.
+std::vector<Choice> candidates_reg(const anova_params &prm, double D, int dA, double budget,
+                                   int64_t N) {
+    const int prec = prm.precision;
+    ANOVA_REQUIRE(prm.h <= 0 || prm.h > 2.0 * D,
+                  "with reg_q, h must exceed twice the extent of the points");
+    const double base = D > 0 ? D : prm.ell;
+    std::vector<double> hs;
+    if (prm.h > 0)
+        hs.push_back(prm.h);
+    else
+        for (double f : {2.5, 3.0, 4.0}) hs.push_back(f * base);
+    const bool fixed = prm.M > 0 && prm.m > 0 && prm.n > 0;
+    std::vector<Choice> out;
+    for (double h : hs) {
+        std::map<int, std::vector<double>> bc;
+        std::map<int, double> ec;
+        auto coeffs = [&](int M) -> const std::vector<double> & {
+            auto it = bc.find(M);
+            if (it == bc.end()) it = bc.emplace(M, reg_coeffs_1d(M, prm.ell, h, D, prm.reg_q)).first;
+            return it->second;
+        };
+        auto etr = [&](int M) {
+            auto it = ec.find(M);
+            if (it == ec.end())
+                it = ec.emplace(M, reg_trunc_dA(reg_err1(coeffs(M), prm.ell, h, D), dA)).first;
+            return it->second;
+        };
+        auto fill = [&](Choice &c, int M, int n, int m) {
+            c = Choice{};
+            c.h = h; c.M = M; c.n = n; c.m = m;
+            c.e_img = 0.0;
+            c.e_trunc = etr(M);
+            c.e_win = est_window_b(coeffs(M), n, m, dA);
+            c.e_round = est_round(prec, n, m, dA);
+            c.cost = (double)N * std::pow(2.0 * m, dA) +
+                     4.0 * std::pow((double)n, dA) * std::log2((double)n) * dA;
+        };
+        if (fixed) {
+            Choice c;
+            fill(c, prm.M, prm.n, prm.m);
+            out.push_back(c);
+            continue;
+        }
+        for (int n = 8; n <= 256; n *= 2) {
+            if ((prm.n > 0 && n != prm.n) || prm.M > n) continue;
+            bool found = false;
+            Choice c;
+            for (int m = 2; m <= 8 && !found; ++m) {
+                if (prm.m > 0 && m != prm.m) continue;
+                if (2 * m > n) break;
+                const double avail = budget - est_round(prec, n, m, dA);
+                if (avail <= 0) continue;
+                const int M0 = prm.M > 0 ? prm.M : 4;
+                const int M1 = prm.M > 0 ? prm.M : (4 * n) / 5;
+                for (int M = M0; M <= M1; M += 2) {
+                    const double et = etr(M);
+                    if (et > avail) continue;
+                    const double ew = est_window_b(coeffs(M), n, m, dA);
+                    if (et + ew > avail) {
+                        if (et < 1e-3 * avail) break;  // only the window error grows from here
+                        continue;
+                    }
+                    fill(c, M, n, m);
+                    found = true;
+                    break;
+                }
+            }
+            if (found) out.push_back(c);
+        }
+    }
+    if (out.empty())
+        throw Error{ANOVA_E_ACCURACY,
+                    "no (M, n, m) with n <= 256 and m <= 8 meets target_err for this window"};
+    // fixed parameters: the period with the smallest estimate
+    std::stable_sort(out.begin(), out.end(), [&](const Choice &x, const Choice &y) {
+        return fixed ? x.e_trunc + x.e_win < y.e_trunc + y.e_win : x.cost < y.cost;
+    });
+    if (fixed) out.resize(1);
+    return out;
+}
+
 std::vector<Choice> candidates(const anova_params &prm, double D, int dA, double budget,
                                int64_t N, int share) {
+    if (prm.reg_q > 0) return candidates_reg(prm, D, dA, budget, N);
     const int prec = prm.precision;
     double h0;
     if (prm.h > 0) {
@@ -652,7 +835,8 @@ void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int p
     // per-axis multiplier: b1_k / phihat(k/n)^2 for |k| < M/2, else 0
     std::vector<double> bd(n, 0.0);
     const double i0b = bessel_i0(w.kb_b);
-    const std::vector<double> bk = sampled_coeffs_1d(w.M, w.ell, w.h);
+    const std::vector<double> bk = w.reg_q > 0 ? reg_coeffs_1d(w.M, w.ell, w.h, w.extent, w.reg_q)
+                                               : sampled_coeffs_1d(w.M, w.ell, w.h);
     for (int k = 0; k < n; ++k) {
         const int ks = k < n / 2 ? k : k - n;
         if (std::abs(ks) >= w.M / 2) continue;
@@ -707,6 +891,7 @@ void validate(const double *X, int64_t N, int32_t d, int64_t ldx, const anova_wi
     ANOVA_REQUIRE(prm->residual == ANOVA_RESIDUAL_FP64 || prm->residual == ANOVA_RESIDUAL_SAME,
                   "residual must be ANOVA_RESIDUAL_FP64 or ANOVA_RESIDUAL_SAME");
     ANOVA_REQUIRE(prm->tune == 0 || prm->tune == 1, "tune must be 0 or 1");
+    ANOVA_REQUIRE(prm->reg_q >= 0 && prm->reg_q <= 12, "reg_q must be in [0, 12]");
     for (int l = 0; l < P; ++l) {
         const anova_window &w = win[l];
         ANOVA_REQUIRE(w.d_A >= 1 && w.d_A <= 3, "window d_A must be 1, 2 or 3");
@@ -839,6 +1024,7 @@ static void apply_choice(WindowPlan &w, const Choice &c, const anova_params &prm
     w.err_round = ae * c.e_round;
     w.err_total = w.err_images + w.err_trunc + w.err_window + w.err_round;
     w.ell = prm.ell;
+    w.reg_q = prm.reg_q;
 }
 
 static void build_for(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int prec) {
@@ -949,9 +1135,12 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
             w.extent = D;
             w.launch_windows = P;
             const std::vector<Choice> cands = candidates(*prm, D, w.dA, budget, N, P);
-            for (const Choice &c : cands)
+            for (const Choice &c : cands) {
                 ANOVA_REQUIRE(c.h > D || (D == 0 && c.h > 0),
                               "h must exceed the extent of the points");
+                ANOVA_REQUIRE(prm->reg_q == 0 || c.h > 2.0 * D,
+                              "with reg_q, h must exceed twice the extent of the points");
+            }
             if (prm->tune == 0 || cands.size() == 1) {
                 set_centers(w, cands.front(), lo, hi, *prm);
                 apply_choice(w, cands.front(), *prm);
@@ -995,7 +1184,7 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
                 const WindowPlan &w = p->win[l];
                 WindowPlan &v = p->win64[l];
                 v.dA = w.dA; v.eta = w.eta; v.ell = w.ell; v.h = w.h; v.extent = w.extent;
-                v.M = w.M; v.n = w.n; v.m = w.m; v.kb_b = w.kb_b;
+                v.M = w.M; v.n = w.n; v.m = w.m; v.kb_b = w.kb_b; v.reg_q = w.reg_q;
                 for (int t = 0; t < 3; ++t) { v.feat[t] = w.feat[t]; v.center[t] = w.center[t]; }
                 build_window<double, NodeF64>(v, Xh, N, ldx, ANOVA_FP64);
             }
@@ -1007,7 +1196,7 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
                 const WindowPlan &w = p->win[l];
                 WindowPlan &v = p->tgt[l];
                 v.dA = w.dA; v.eta = w.eta; v.ell = w.ell; v.h = w.h; v.extent = w.extent;
-                v.M = w.M; v.n = w.n; v.m = w.m; v.kb_b = w.kb_b;
+                v.M = w.M; v.n = w.n; v.m = w.m; v.kb_b = w.kb_b; v.reg_q = w.reg_q;
                 v.launch_windows = w.launch_windows;
                 v.err_images = w.err_images; v.err_trunc = w.err_trunc;
                 v.err_window = w.err_window; v.err_round = w.err_round;

@@ -152,3 +152,14 @@ def test_shifted_cg_validates_before_device_work(lib):
     assert lib.krr_cg_solve_shifts(None, None, None, 2, sh, 10, 1e-6, 10, info,
                                    None) == _lib.ANOVA_E_INVALID
     assert "plan" in _lib.anova_last_error()
+
+
+def test_reg_q_validated(lib):
+    from paper_2111_10140_amd import _lib
+    h = ctypes.c_void_p()
+    w = _lib.make_windows([((0, 1, 2), 1.0)])
+    for bad in (-1, 13):
+        prm = _lib.make_params(0.1, reg_q=bad)
+        st = lib.anova_fastsum_plan(ctypes.byref(h), ctypes.c_void_p(16), 10, 3, 3, w, 1,
+                                    ctypes.byref(prm), None)
+        assert st == _lib.ANOVA_E_INVALID and "reg_q" in _lib.anova_last_error()
