@@ -384,8 +384,29 @@ std::vector<Choice> candidates_reg(const anova_params &prm, double D, int dA, do
     else
         for (double f : {2.5, 3.0, 4.0}) hs.push_back(f * base);
     const bool fixed = prm.M > 0 && prm.m > 0 && prm.n > 0;
+    // float32 (per-cell kernels): also periods for which the points span a
+    // whole number k of tiles of the per-cell kernels at FFT length n, with
+    // the data's lower edge on a tile boundary (centre chosen in make_plan),
+    // between 2.4 and 4 times the extent; listed first, so that at equal
+    // model cost they are preferred
+    struct Period {
+        double h;
+        int n, align;  // n = 0: any FFT length
+    };
+    std::vector<Period> periods;
+    const int T = cell_tile(dA);
+    if (prm.h <= 0 && prm.center == 0 && !fixed && prec == ANOVA_FP32_NFFT && D > 0)
+        for (int n = 2 * T; n <= 256; n *= 2) {
+            if (prm.n > 0 && n != prm.n) continue;
+            for (int k = 1; k * T <= n; ++k) {
+                const double h = n * D / (k * T * (1.0 - 4e-5));
+                if (h >= 2.4 * D && h <= 4.0 * D) periods.push_back(Period{h, n, T});
+            }
+        }
+    for (double h : hs) periods.push_back(Period{h, 0, 0});
     std::vector<Choice> out;
-    for (double h : hs) {
+    for (const Period &per : periods) {
+        const double h = per.h;
         std::map<int, std::vector<double>> bc;
         std::map<int, double> ec;
         auto coeffs = [&](int M) -> const std::vector<double> & {
@@ -417,6 +438,7 @@ std::vector<Choice> candidates_reg(const anova_params &prm, double D, int dA, do
         }
         for (int n = 8; n <= 256; n *= 2) {
             if ((prm.n > 0 && n != prm.n) || prm.M > n) continue;
+            if (per.n > 0 && n != per.n) continue;
             bool found = false;
             Choice c;
             for (int m = 2; m <= 8 && !found; ++m) {
@@ -439,7 +461,12 @@ std::vector<Choice> candidates_reg(const anova_params &prm, double D, int dA, do
                     break;
                 }
             }
-            if (found) out.push_back(c);
+            if (!found) continue;
+            // the wide 3-D kernels walk every point of a cell per lane and
+            // gain nothing from alignment
+            if (per.align > 0 && !(dA == 3 && 2 * c.m > 6)) c.align = per.align;
+            if (per.align > 0 && c.align == 0) continue;
+            out.push_back(c);
         }
     }
     if (out.empty())
