@@ -12,7 +12,11 @@ kernel (per-launch durations from HIP events recorded on the launching
 stream over the timed region), the same product at the fixed bandwidth
 M = 64, m = 6, n = 128, and the oracle's CPU time on a bounded sample of
 rows (the only use of the oracle here), whose rows also give the error of
-the GPU result.
+the GPU result.  Further legs (each can be skipped): the measured
+parameter choice, the precision split, the batched and large
+configurations, the lambda grid by shifted CG, the regularised kernel,
+the end-to-end classifier (fit / predict / accuracy), prediction at 1e6
+test points, and served solves.
 """
 from __future__ import annotations
 
