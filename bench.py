@@ -581,11 +581,12 @@ def main():
     if not args.skip_cpu:
         import oracle
         rng = np.random.default_rng(7)
-        probe = rng.choice(N, 8, replace=False)
+        # the probe holds enough rows to occupy every host thread
+        probe = rng.choice(N, 256, replace=False)
         t1 = time.perf_counter()
         oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a_np, rows=probe)
-        per_row = (time.perf_counter() - t1) / 8
-        S = int(max(16, min(4096, args.cpu_seconds / max(per_row, 1e-6))))
+        per_row = (time.perf_counter() - t1) / 256
+        S = int(max(64, min(32768, args.cpu_seconds / max(per_row, 1e-6))))
         rows = rng.choice(N, S, replace=False)
         t1 = time.perf_counter()
         ref, threads = oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a_np, rows=rows,
