@@ -55,3 +55,22 @@ def test_grid_search(K):
     cell = [r for r in cells if r["sigma"] == 1.0 and r["lam"] == 10.0][0]
     print(f"cell accuracy {cell['accuracy']:.4f}, own fit {acc1:.4f}", flush=True)
     assert abs(cell["accuracy"] - acc1) <= 0.01
+
+
+def test_full_size_decision_values(K):
+    # the benchmark's end-to-end leg: 1e6 training and 1e6 test points;
+    # decision values on 256 sampled test rows against the oracle's sum with
+    # the GPU's coefficients, and the accuracy
+    X, y, Z, yz = workloads.labelled(1_000_000, 1_000_000)
+    m = K.KernelRidge(sigma=1.0, lam=1.0, tol=1e-3).fit(X, y)
+    s = m.decision_function(Z)
+    alpha = m.alpha_.cpu().numpy()
+    rows = np.sort(np.random.default_rng(61).choice(Z.shape[0], 256, replace=False))
+    ref = oracle.direct.anova_predict(m._scaled(Z), m.X_, m.windows_, m.sigma, alpha, rows=rows)
+    e = float(np.max(np.abs(s[rows] - ref)) / np.abs(alpha).sum())
+    acc = float(np.mean(np.where(s >= 0, 1.0, -1.0) == yz))
+    print(f"N=1e6: CG {m.fit_info_['iters']} iterations, accuracy {acc:.4f}, decision E = {e:.3e}",
+          flush=True)
+    assert m.fit_info_["converged"]
+    assert e <= 1e-4
+    assert acc >= 0.9

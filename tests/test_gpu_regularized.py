@@ -96,3 +96,21 @@ def test_prediction_with_regularised_kernel(A):
     e = rel_err(to_np(out), ref, p.alpha[:, 0])
     print(f"prediction E = {e:.3e}, estimate {plan.err_estimate():.3e}", flush=True)
     assert e <= 1e-4 and e <= plan.err_estimate()
+
+
+def test_headline_size_sampled_rows(A):
+    # the benchmark's regularised leg: headline points (N = 1e6), reg_q = 8,
+    # float32, per-entry estimate <= 1e-4; 512 sampled rows
+    p = workloads.headline()
+    plan = A.anova_fastsum_plan(dev_rows(p.X), p.windows,
+                                A.make_params(p.ell, F32, target_err=1e-4, reg_q=8))
+    a = np.ascontiguousarray(p.alpha[:, 0])
+    out = product(A, plan, a, p.beta)
+    rows = np.sort(np.random.default_rng(75).choice(p.N, 512, replace=False))
+    ref = oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a, rows=rows)
+    e = float(np.max(np.abs(out[rows] - ref)) / np.abs(a).sum())
+    est = plan.err_estimate()
+    print(f"N=1e6 reg_q=8: E = {e:.3e}, estimate {est:.3e}, params",
+          [(i.M, i.n, i.m, round(i.h, 4), i.per_cell) for i in
+           (plan.info(l) for l in range(plan.P))], flush=True)
+    assert e <= 1e-4 and e <= est
