@@ -35,7 +35,10 @@ HBM_PEAK_GBS = 8000.0
 # float32 FMA without packed instructions (the library is built without
 # them): 256 CUs x 64 lanes x 2 flop x 2.4 GHz
 VALU_FP32_PEAK_TFLOPS = 78.6
-POLY_DEG_FP32 = 8  # degree of the float32 window polynomials
+# the chip's float32 vector peak counting packed instructions (which this
+# library does not emit), reported beside the fraction for reference
+VALU_FP32_PACKED_PEAK_TFLOPS = 157.3
+C_EVAL = 8  # flops charged per window evaluation (degree-8 polynomial)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "headline_pmc_traffic.txt")
 
 
@@ -103,20 +106,13 @@ def alg_bytes(stage: str, N: int, G: int, elem: int, P: int = 3, per_cell: bool 
     return float(G * elem)  # tile_sum, fold
 
 
-def alg_flops(stage: str, N: int, dA: int, W: int, deg: int = POLY_DEG_FP32) -> float:
-    """Algorithmic flops per window of the float32 spread and gather (an FMA
-    counts 2): per point, the W window weights in each of the d_A
-    dimensions by Horner's rule (deg FMAs each, plus the argument map), and
-    the tensor-product weights: spread multiplies alpha by the weight
-    products (W^(d_A-1) + ... products) and accumulates W^d_A FMAs; gather
-    contracts W^d_A + ... + W FMAs."""
-    horner = 2 * dA * (W * deg + 1)
-    if stage == "spread":
-        prods = sum(W ** k for k in range(1, dA))  # W + W^2 for d_A = 3
-        return N * (horner + prods + 2 * W ** dA)
-    if stage == "gather":
-        return N * (horner + 2 * sum(W ** k for k in range(1, dA + 1)))
-    return 0.0
+def alg_flops(N: int, dA: int, W: int) -> float:
+    """Algorithmic flops of one window's spread or gather (an FMA counts 2):
+    per point, 2 W^d_A for the tensor-product sum over the W^d_A support
+    points, plus d_A W window evaluations at C_EVAL flops each (degree-8
+    polynomials per support offset).  The kernels' own instruction counts
+    (mirror pairs, weight products) are not what is charged."""
+    return float(N) * (2 * W ** dA + dA * W * C_EVAL)
 
 
 def measured_traffic(kernel_stage: str):
@@ -148,6 +144,60 @@ def time_matvecs(A, torch, plan, a, out, beta, steps, warmup):
     e.record()
     torch.cuda.synchronize()
     return s.elapsed_time(e) / steps
+
+
+def graph_timing(A, torch, plan, a, out, beta, steps, warmup):
+    """One product captured into a graph (the launch tables are built by an
+    eager product first, so nothing is allocated or uploaded inside the
+    capture), `warmup` replays, then `steps` replays each bracketed by
+    events on the replaying stream.  Returns (graph, mean ms over the timed
+    region, sorted per-replay ms, every replay equal to the eager result)."""
+    A.anova_matvec(plan, a, out, beta)
+    torch.cuda.synchronize()
+    ref = out.clone()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        A.anova_matvec(plan, a, out, beta)
+    ok = True
+    for _ in range(max(warmup, 1)):
+        out.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        ok = ok and torch.equal(out, ref)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for e0, e1 in ev:
+        e0.record()
+        g.replay()
+        e1.record()
+    t1.record()
+    torch.cuda.synchronize()
+    per = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+    ok = ok and torch.equal(out, ref)
+    return g, t0.elapsed_time(t1) / steps, per, ok
+
+
+def cold_timing(torch, g, reps=20):
+    """Replays of the captured product, each after 512 MiB of writes that
+    evict the 256 MB Infinity Cache and the L2 caches: sorted ms."""
+    flush = torch.empty(128 << 20, dtype=torch.float32, device="cuda")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(reps)]
+    for r, (e0, e1) in enumerate(ev):
+        flush.fill_(float(r))
+        e0.record()
+        g.replay()
+        e1.record()
+    torch.cuda.synchronize()
+    del flush
+    return sorted(e0.elapsed_time(e1) for e0, e1 in ev)
+
+
+def pct(v, q):
+    return float(np.percentile(np.asarray(v), q))
 
 
 def stage_profile(A, torch, plan, a, out, beta, steps):
@@ -524,7 +574,12 @@ def main():
     plan_s = time.perf_counter() - t0
     infos = [plan.info(l) for l in range(plan.P)]
 
-    ms = time_matvecs(A, torch, plan, a, out, p.beta, args.steps, args.warmup)
+    ms_eager = time_matvecs(A, torch, plan, a, out, p.beta, max(10, args.steps // 2),
+                            args.warmup)
+    graph, ms, per_replay, graph_ok = graph_timing(A, torch, plan, a, out, p.beta, args.steps,
+                                                   args.warmup)
+    cold = cold_timing(torch, graph)
+    del graph
     stages = stage_profile(A, torch, plan, a, out, p.beta, max(10, args.steps // 2))
     A.anova_matvec(plan, a, out, p.beta)
     torch.cuda.synchronize()
@@ -539,29 +594,55 @@ def main():
             avg_ms = tot / cnt
             b = alg_bytes(k, N, G, 4, P, bool(infos[0].per_cell)) * (1 if k == "combine" else P)
             per_launch[k] = dict(avg_us=avg_ms * 1e3, launches=cnt, alg_bytes=b,
-                                 gbs=b / (avg_ms * 1e-3) / 1e9)
+                                 gbs=b / (avg_ms * 1e-3) / 1e9,
+                                 hbm_frac=b / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
     W = 2 * infos[0].m
     for k in ("spread", "gather"):
         if k in per_launch:
-            f = alg_flops(k, N, infos[0].d_A, W) * P
+            f = alg_flops(N, infos[0].d_A, W) * P
             per_launch[k]["alg_flops"] = f
             per_launch[k]["tflops"] = f / (per_launch[k]["avg_us"] * 1e-6) / 1e12
-            per_launch[k]["hbm_frac"] = per_launch[k]["gbs"] / HBM_PEAK_GBS
+            per_launch[k]["valu_frac"] = per_launch[k]["tflops"] / VALU_FP32_PEAK_TFLOPS
     dom = max(per_launch, key=lambda k: per_launch[k]["avg_us"])
+    traffic = measured_traffic(dom)
+    count = (f"spread/gather: 2 W^d_A + {C_EVAL} d_A W flop per point and window (W = {W}, "
+             f"d_A = {infos[0].d_A}: {2 * W ** infos[0].d_A + C_EVAL * infos[0].d_A * W}); "
+             "bytes as alg_bytes in bench.py")
+    kernels = {k: {"avg_us": round(v["avg_us"], 3), "tflops": round(v["tflops"], 3),
+                   "valu_frac": round(v["valu_frac"], 4), "gbs": round(v["gbs"], 1),
+                   "hbm_frac": round(v["hbm_frac"], 4)}
+               for k, v in per_launch.items() if "tflops" in v}
     if "tflops" in per_launch[dom]:
-        # spread and gather at these parameters do ~40 flop per algorithmic
-        # byte, above the float32 ridge (78.6 TFLOP/s / 8 TB/s ~ 10): ALU-bound
+        # at m = 3 spread and gather do ~24 flop per algorithmic byte, above
+        # the float32 ridge (78.6 TFLOP/s / 8 TB/s ~ 10): the vector ALUs bind
         roof = {"bound": "alu", "kernel": dom, "achieved": round(per_launch[dom]["tflops"], 2),
                 "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(per_launch[dom]["tflops"] / VALU_FP32_PEAK_TFLOPS, 4),
-                "traffic": measured_traffic(dom),
-                "alg_bytes": per_launch[dom]["alg_bytes"],
-                "hbm_frac_of_alg_bytes": round(per_launch[dom]["hbm_frac"], 4)}
+                "frac": round(per_launch[dom]["valu_frac"], 4),
+                "frac_of_packed_fp32_peak": round(per_launch[dom]["tflops"] /
+                                                  VALU_FP32_PACKED_PEAK_TFLOPS, 4),
+                "traffic": traffic,
+                "traffic_source": ("FETCH_SIZE + WRITE_SIZE per launch from the committed "
+                                   "counter runs in profiles/headline_pmc_traffic.txt, taken "
+                                   "on this kernel source (not measured in this run)")
+                if traffic is not None else "none for this kernel source",
+                "alg_flops": per_launch[dom]["alg_flops"], "alg_bytes": per_launch[dom]["alg_bytes"],
+                "hbm_achieved_gbs": round(per_launch[dom]["gbs"], 1),
+                "hbm_frac": round(per_launch[dom]["hbm_frac"], 4),
+                "count": count, "kernels": kernels}
     else:
         roof = {"bound": "hbm", "kernel": dom, "achieved": round(per_launch[dom]["gbs"], 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(per_launch[dom]["gbs"] / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dom)}
+                "frac": round(per_launch[dom]["hbm_frac"], 4), "traffic": traffic}
+    timing = {"unit": "ms per product", "graph_replays": args.steps,
+              "median": round(pct(per_replay, 50), 4), "p10": round(pct(per_replay, 10), 4),
+              "p90": round(pct(per_replay, 90), 4),
+              "matvecs_per_s_at_median": round(1e3 / pct(per_replay, 50), 2),
+              "replays_equal_eager_product": bool(graph_ok),
+              "eager_mean": round(ms_eager, 4),
+              "cold_cache": {"reps": len(cold), "median": round(pct(cold, 50), 4),
+                             "p10": round(pct(cold, 10), 4), "p90": round(pct(cold, 90), 4),
+                             "matvecs_per_s": round(1e3 / pct(cold, 50), 2),
+                             "flush": "512 MiB written before each replay"}}
 
     fixed = None
     if not args.skip_fixed:
@@ -593,14 +674,24 @@ def main():
                                                   return_threads=True)
         t_cpu = time.perf_counter() - t1
         err = float(np.max(np.abs(gpu_out[rows] - ref)) / np.abs(a_np).sum())
+        rel = float(np.max(np.abs(gpu_out[rows] - ref)) / np.max(np.abs(ref)))
+        # one thread, on a sample sized for about a third of the time
+        S1 = int(max(16, min(S, S / max(threads, 1) / 3)))
+        oracle.direct.set_threads(1)
+        t1 = time.perf_counter()
+        oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a_np, rows=rows[:S1])
+        t_one = time.perf_counter() - t1
+        oracle.direct.set_threads(threads)
         cpu = {"value": S / (t_cpu * N), "unit": "matvecs/s", "cores": int(threads),
                "kind": "oracle",
                "sample": f"{S} random rows of the N={N} direct float64 sum ({t_cpu:.1f} s), "
-                         f"extrapolated as rows/(time*N)"}
+                         f"extrapolated as rows/(time*N)",
+               "single_core_value": S1 / (t_one * N),
+               "single_core_sample": f"{S1} of those rows on one thread ({t_one:.1f} s)"}
         if fixed is not None:
             fixed["err_sampled_rows"] = float(np.max(np.abs(fixed_out[rows] - ref)) / np.abs(a_np).sum())
     else:
-        err = None
+        err = rel = None
 
     # the measured parameter choice on the same points
     tuned = None
@@ -655,8 +746,9 @@ def main():
                    "precision": "fp32 spread/FFT/gather, fp64 accumulation",
                    "params": [dict(M=i.M, n=i.n, m=i.m, h=round(i.h, 4)) for i in infos],
                    "err_estimate": plan.err_estimate(), "err_sampled_rows": err,
-                   "plan_seconds": round(plan_s, 3)},
+                   "rel_err_sampled_rows": rel, "plan_seconds": round(plan_s, 3)},
         "roofline": roof,
+        "timing": timing,
         "stages_per_launch": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
                                   for kk, vv in v.items()} for k, v in per_launch.items()},
         "fixed_params": fixed,

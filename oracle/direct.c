@@ -175,3 +175,14 @@ int oracle_max_threads(void)
     return 1;
 #endif
 }
+
+/* Threads of the following calls (the host-baseline timing reports a
+ * one-thread figure beside the all-threads one). */
+void oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

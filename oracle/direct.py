@@ -48,6 +48,8 @@ def _load():
             ctypes.c_double, P(ctypes.c_int64), ctypes.c_int64, P(ctypes.c_int64),
             ctypes.c_int64, P(ctypes.c_double)]
         lib.oracle_max_threads.restype = ctypes.c_int
+        lib.oracle_set_threads.restype = None
+        lib.oracle_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -74,6 +76,11 @@ def _windows(windows):
 
 def max_threads() -> int:
     return int(_load().oracle_max_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of later oracle calls (n >= 1)."""
+    _load().oracle_set_threads(int(n))
 
 
 def anova_matvec(X: np.ndarray, windows, ell: float, beta: float, alpha: np.ndarray,

@@ -181,9 +181,9 @@ struct anova_plan_s {
     std::vector<anova::WindowPlan> tgt;
     int device = 0;
     // batched launches of this plan's own products (anova_matvec) and
-    // predictions (anova_predict), reused while the vectors and the shift
-    // stay the same
-    std::unique_ptr<anova::Batch> mv_batch, pred_batch;
+    // predictions (anova_predict), one per recently used set of vectors and
+    // shift (least recently used last to be rebuilt)
+    std::vector<std::unique_ptr<anova::Batch>> mv_cache, pred_cache;
     // optional per-stage timing (events on the launching stream)
     bool timing = false;
     struct TimedLaunch {
@@ -307,7 +307,34 @@ class Batch {
     size_t device_bytes() const;
     // stage mask: bit k = stage kind k
     void run(hipStream_t s, anova_plan_s *timing = nullptr, unsigned mask = 0xffu) const;
+
+    // A cached batch (a plan's own products) may be rebuilt in place for
+    // other vectors.  The synchronous table uploads are not ordered after
+    // work on the caller's stream, so a rebuild first waits for the batch's
+    // last eager run; a batch that has run on a capturing stream is never
+    // rebuilt (a graph holds its tables).
+    void record_run(hipStream_t s);
+    void wait_last_run();
+    bool captured() const { return captured_; }
+    Batch() = default;
+    Batch(const Batch &) = delete;
+    Batch &operator=(const Batch &) = delete;
+    ~Batch();
+
+  private:
+    hipEvent_t last_run_ = nullptr;
+    bool run_recorded_ = false;
+    bool captured_ = false;
 };
+
+// Run the problems through a plan's cache of batches: the batch built for
+// the same problems if there is one; else a new one while the cache holds
+// fewer than kBatchCache, else the least recently used batch not captured
+// by a graph, rebuilt after its last run has finished (a new one when every
+// batch is captured).
+constexpr size_t kBatchCache = 4;
+void run_cached(std::vector<std::unique_ptr<Batch>> &cache, const std::vector<BatchProblem> &probs,
+                hipStream_t s, anova_plan_s *timing);
 
 // kernel-side entry points (kernels.hip)
 void run_group(const BatchGroup &g, int precision, const WinInst *insts, hipStream_t s);

@@ -347,6 +347,57 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
     probs = problems;
 }
 
+Batch::~Batch() {
+    if (last_run_) (void)hipEventDestroy(last_run_);
+}
+
+void Batch::record_run(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    ANOVA_HIP_CHECK(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone) {
+        captured_ = true;
+        return;
+    }
+    if (!last_run_) ANOVA_HIP_CHECK(hipEventCreateWithFlags(&last_run_, hipEventDisableTiming));
+    ANOVA_HIP_CHECK(hipEventRecord(last_run_, s));
+    run_recorded_ = true;
+}
+
+void Batch::wait_last_run() {
+    if (run_recorded_) ANOVA_HIP_CHECK(hipEventSynchronize(last_run_));
+    run_recorded_ = false;
+}
+
+void run_cached(std::vector<std::unique_ptr<Batch>> &cache, const std::vector<BatchProblem> &probs,
+                hipStream_t s, anova_plan_s *timing) {
+    // most recently used last
+    size_t k = cache.size();
+    for (size_t i = 0; i < cache.size(); ++i)
+        if (cache[i]->same(probs)) k = i;
+    if (k == cache.size()) {
+        size_t victim = cache.size();
+        if (cache.size() >= kBatchCache)
+            for (size_t i = 0; i < cache.size() && victim == cache.size(); ++i)
+                if (!cache[i]->captured()) victim = i;
+        if (victim == cache.size()) {
+            std::unique_ptr<Batch> b(new Batch());
+            b->build(probs);
+            cache.push_back(std::move(b));
+        } else {
+            cache[victim]->wait_last_run();
+            cache[victim]->build(probs);
+            k = victim;
+        }
+    }
+    if (k < cache.size()) {
+        std::unique_ptr<Batch> b = std::move(cache[k]);
+        cache.erase(cache.begin() + k);
+        cache.push_back(std::move(b));
+    }
+    cache.back()->run(s, timing);
+    cache.back()->record_run(s);
+}
+
 void Batch::run(hipStream_t s, anova_plan_s *timing, unsigned mask) const {
     const WinInst *di = d_insts.as<WinInst>();
     size_t k = 0;

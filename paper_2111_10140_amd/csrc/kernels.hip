@@ -182,18 +182,48 @@ __device__ __forceinline__ float block_max(float v, float *sh) {
     return r;
 }
 
+__device__ __forceinline__ double block_max(double v, double *sh) {
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = sh[0];
+    for (int i = 1; i < kBlock / 64; ++i) r = fmax(r, sh[i]);
+    __syncthreads();
+    return r;
+}
+
+// |a| for the largest-coefficient search of the float32 kernels: values
+// beyond the float range (and NaN) become infinity, which marks the region
+// as non-finite.
 __device__ __forceinline__ float abs_for_max(double a) {
     const float va = (float)fabs(a);
-    return va <= 3.0e38f ? va : INFINITY;  // NaN or out of range: propagate as NaN
+    return va <= 3.0e38f ? va : INFINITY;
+}
+// The float64 kernels search in float64, so every finite coefficient,
+// however small or large, sets a finite scale.
+__device__ __forceinline__ double abs_for_max64(double a) {
+    return fabs(a) <= 1.79e308 ? fabs(a) : INFINITY;
 }
 
 // Region of a workgroup with non-finite or all-zero coefficients.
-template <typename T>
-__device__ __forceinline__ bool trivial_region(float amax, T *out, int vol) {
-    if (amax > 0.0f && isfinite(amax)) return false;
-    const T fill = amax > 0.0f ? T(NAN) : T(0);
+template <typename T, typename A>
+__device__ __forceinline__ bool trivial_region(A amax, T *out, int vol) {
+    if (amax > A(0) && isfinite(amax)) return false;
+    const T fill = amax > A(0) ? T(NAN) : T(0);
     for (int e = threadIdx.x; e < vol; e += kBlock) out[e] = fill;
     return true;
+}
+
+// Exponent e with amax (1 + margin) < 2^e, for the fixed-point scale.
+__device__ __forceinline__ int scale_exponent(float amax) {
+    int e;
+    (void)frexpf(amax * 1.0000002f, &e);
+    return e;
+}
+__device__ __forceinline__ int scale_exponent(double amax) {
+    int e;
+    (void)frexp(amax * (1.0 + 0x1p-40), &e);
+    return e;
 }
 
 // ------------------------------------------------------------------ spread, per point
@@ -205,7 +235,10 @@ __global__ __launch_bounds__(kBlock) void spread_pt_kernel(const WinInst *__rest
                                                            int cnt) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     unsigned long long *acc = reinterpret_cast<unsigned long long *>(smem_raw);
-    __shared__ float red[kBlock / 64];
+    // the largest |coefficient| is searched in float32 on the float32 path
+    // (its coefficients are floats) and in float64 on the float64 path
+    using AM = typename std::conditional<std::is_same<T, double>::value, double, float>::type;
+    __shared__ AM red[kBlock / 64];
     const Located loc = locate(insts, members, prefix, cnt);
     const WinInst &wi = *loc.w;
     using Node = typename NodeOf<T>::type;
@@ -219,15 +252,15 @@ __global__ __launch_bounds__(kBlock) void spread_pt_kernel(const WinInst *__rest
     for (int e = threadIdx.x; e < vol; e += kBlock) acc[e] = 0ull;
     const SubProblem sp = wi.subs[loc.lb];
     const int end = sp.start + sp.count;
-    float amax = 0.0f;
-    for (int j = sp.start + threadIdx.x; j < end; j += kBlock)
-        amax = fmaxf(amax, abs_for_max((double)as[j]));
+    AM amax = AM(0);
+    for (int j = sp.start + threadIdx.x; j < end; j += kBlock) {
+        if constexpr (std::is_same<T, double>::value) amax = fmax(amax, abs_for_max64(as[j]));
+        else amax = fmaxf(amax, abs_for_max((double)as[j]));
+    }
     amax = block_max(amax, red);  // also orders the zero fill before the adds
     T *out = static_cast<T *>(wi.priv) + (size_t)loc.lb * vol;
     if (trivial_region(amax, out, vol)) return;
-    int ex2;
-    (void)frexpf(amax * 1.0000002f, &ex2);  // amax * (1 + margin) < 2^ex2
-    const int S = FixedBits<T>::value - ex2;
+    const int S = FixedBits<T>::value - scale_exponent(amax);
     const int ox = (sp.tile % tpd) * tile;
     const int oy = ((sp.tile / tpd) % tpd) * tile;
     const int oz = (sp.tile / (tpd * tpd)) * tile;
@@ -273,9 +306,11 @@ __global__ __launch_bounds__(kBlock) void spread_pt_kernel(const WinInst *__rest
         }
     }
     __syncthreads();
-    const double inv = ldexp(1.0, -S);
+    // ldexp rather than a product with 2^-S: S can exceed 1022 for float64
+    // coefficients near the bottom of the range, where 2^-S is no longer a
+    // normal double
     for (int e = threadIdx.x; e < vol; e += kBlock)
-        out[e] = static_cast<T>((double)(long long)acc[e] * inv);
+        out[e] = static_cast<T>(ldexp((double)(long long)acc[e], -S));
 }
 
 // ------------------------------------------------------------------ per-cell kernels

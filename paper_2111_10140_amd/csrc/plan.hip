@@ -951,7 +951,8 @@ hipEvent_t pool_event(anova_plan_s *p) {
 
 // out = (K~ + beta I) alpha for nrhs columns: one batched launch per stage
 // over all windows and columns; the launch tables are rebuilt only when the
-// vectors, their layout or the shift change.
+// vectors, their layout or the shift change (after the previous product on
+// the caller's stream has finished reading them).
 void plan_matvec(anova_plan_s *p, const double *alpha, double *out, int nrhs, int64_t ld,
                  double beta, hipStream_t s) {
     BatchProblem bp;
@@ -961,10 +962,7 @@ void plan_matvec(anova_plan_s *p, const double *alpha, double *out, int nrhs, in
     bp.nrhs = nrhs;
     bp.ld = ld;
     bp.beta = beta;
-    const std::vector<BatchProblem> probs{bp};
-    if (!p->mv_batch) p->mv_batch.reset(new Batch());
-    if (!p->mv_batch->same(probs)) p->mv_batch->build(probs);
-    p->mv_batch->run(s, p);
+    run_cached(p->mv_cache, {bp}, s, p);
 }
 
 // out = K~(Z, X) alpha for nrhs columns (rows: the plan's targets), batched
@@ -979,10 +977,7 @@ void plan_predict(anova_plan_s *p, const double *alpha, double *out, int nrhs, i
     bp.ld = lda;
     bp.ld_out = ldo;
     bp.predict = true;
-    const std::vector<BatchProblem> probs{bp};
-    if (!p->pred_batch) p->pred_batch.reset(new Batch());
-    if (!p->pred_batch->same(probs)) p->pred_batch->build(probs);
-    p->pred_batch->run(s, p);
+    run_cached(p->pred_cache, {bp}, s, p);
 }
 
 }  // namespace anova
@@ -1014,8 +1009,8 @@ size_t anova::plan_device_bytes(const anova_plan_s *p) {
                                 &w.src_sub, &w.cell_start, &w.tiles_ne, &w.fold_pairs,
                                 &w.fold_start, &w.fold_tiles})
             b += d->bytes;
-    if (p->mv_batch) b += p->mv_batch->device_bytes();
-    if (p->pred_batch) b += p->pred_batch->device_bytes();
+    for (const auto &c : {&p->mv_cache, &p->pred_cache})
+        for (const auto &bt : *c) b += bt->device_bytes();
     return b;
 }
 

@@ -46,14 +46,15 @@ def zscore_apply(X: np.ndarray, mean: np.ndarray, std: np.ndarray) -> np.ndarray
 
 
 def quantile_bins(x: np.ndarray, n_bins: int) -> np.ndarray:
-    """Bin index in [0, n_bins) of every value: ranks (ties by position)
-    split into n_bins runs of equal length up to one.  Equal values can land
-    in neighbouring bins."""
+    """Bin index in [0, n_bins) of every value: the value's rank r (the
+    number of values strictly below it, so equal values share a rank) gives
+    bin floor(r n_bins / N).  Distinct values split into n_bins runs of
+    equal length up to one; equal values always share a bin, so a binned
+    feature carries no information about where its rows sit."""
     x = np.asarray(x)
     N = x.shape[0]
-    order = np.argsort(x, kind="stable")
-    ranks = np.empty(N, dtype=np.int64)
-    ranks[order] = np.arange(N)
+    srt = np.sort(x, kind="stable")
+    ranks = np.searchsorted(srt, x, side="left").astype(np.int64)
     return (ranks * n_bins) // max(N, 1)
 
 

@@ -86,3 +86,29 @@ def test_informative_features_rank_first():
     assert top == {2, 5, 7}
     w = F.group_windows(sc)
     assert set(w[0][0]) == {2, 5, 7} and len(w) == 3
+
+
+def test_tied_values_share_a_bin():
+    # equal values must land in one bin whatever the rows' order
+    x = np.repeat(np.array([0.0, 1.0, 2.0, 3.0]), [10, 300, 40, 250])
+    b = F.quantile_bins(x, 8)
+    for v in (0.0, 1.0, 2.0, 3.0):
+        assert np.unique(b[x == v]).size == 1
+    assert np.all(F.quantile_bins(np.full(77, 4.2), 5) == 0)
+
+
+def test_rows_sorted_by_label_give_no_spurious_information():
+    # rows ordered by class: a constant feature and a feature independent of
+    # the label must score about 0 (position-based tie-breaks once split
+    # the tied values by row and scored them near log 2)
+    rng = np.random.default_rng(4)
+    N = 3000
+    y = np.sort(np.where(rng.random(N) < 0.5, -1, 1))
+    const = np.full(N, 3.0)
+    indep = (rng.random(N) < 0.5).astype(np.float64)
+    informative = y + 2.0 * rng.standard_normal(N)
+    assert F.mutual_information(const, y) == 0.0
+    assert F.mutual_information(indep, y) < 5e-3
+    assert F.mutual_information(informative, y) > 10 * F.mutual_information(indep, y)
+    sc = F.mis_scores(np.stack([const, indep, informative], axis=1), y)
+    assert int(np.argmax(sc)) == 2

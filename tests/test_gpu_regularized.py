@@ -109,8 +109,10 @@ def test_headline_size_sampled_rows(A):
     rows = np.sort(np.random.default_rng(75).choice(p.N, 512, replace=False))
     ref = oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a, rows=rows)
     e = float(np.max(np.abs(out[rows] - ref)) / np.abs(a).sum())
+    rel = float(np.max(np.abs(out[rows] - ref)) / np.max(np.abs(ref)))
     est = plan.err_estimate()
-    print(f"N=1e6 reg_q=8: E = {e:.3e}, estimate {est:.3e}, params",
+    assert rel <= 1e-4, rel
+    print(f"N=1e6 reg_q=8: E = {e:.3e}, relative {rel:.3e}, estimate {est:.3e}, params",
           [(i.M, i.n, i.m, round(i.h, 4), i.per_cell) for i in
            (plan.info(l) for l in range(plan.P))], flush=True)
     assert e <= 1e-4 and e <= est
