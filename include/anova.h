@@ -193,6 +193,30 @@ anova_status anova_matvec(anova_plan_t plan, const double *alpha, double *out, i
                           int64_t ld, double beta, void *stream);
 
 /*
+ * anova_matvec for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same product and kernels, bit for bit, with the work space (grids,
+ * spread regions, interpolated values) and launch tables in a static device
+ * array of anova_matvec_noalloc_max_bytes() bytes (64 MiB) that each device
+ * holds until the process ends.  The call allocates no device memory; it
+ * synchronises `stream` (an earlier call may still read the array), copies
+ * its launch tables with synchronous host-to-device copies, and then
+ * launches on `stream` asynchronously.  Every call on a device shares that
+ * device's array: calls that overlap on one device (other streams or host
+ * threads) race.  About 4 bytes per point per window and column in float32
+ * (8 in float64) plus the grids: a float32 product over three 3-D windows of
+ * 1e6 points and one column needs about 14 MB.
+ * Errors: as anova_matvec; ANOVA_E_INVALID also when the work space of this
+ * plan and nrhs exceeds the maximum (nothing is launched then) or when the
+ * current device is not the plan's.
+ */
+anova_status anova_matvec_noalloc(anova_plan_t plan, const double *alpha, double *out,
+                                  int32_t nrhs, int64_t ld, double beta, void *stream);
+
+/* Size in bytes of anova_matvec_noalloc's static work space. */
+int64_t anova_matvec_noalloc_max_bytes(void);
+
+/*
  * Plan for prediction at new points: the sum over training points
  * s(z_i) = sum_j alpha_j kappa(z_i, x_j) at targets z_i (Sec. 4.2, the fast
  * summation with target set Z and source set X; Sec. 4.3 evaluates the

@@ -83,6 +83,7 @@ def load():
         "anova_fastsum_plan": [ctypes.POINTER(VP), VP, i64, i32, i64, ctypes.POINTER(anova_window),
                                i32, ctypes.POINTER(anova_params), VP],
         "anova_matvec": [VP, VP, VP, i32, i64, dbl, VP],
+        "anova_matvec_noalloc": [VP, VP, VP, i32, i64, dbl, VP],
         "krr_cg_solve": [VP, VP, VP, i32, i64, dbl, dbl, i32, ctypes.POINTER(krr_cg_info), VP],
         "anova_plan_destroy": [VP],
         "anova_plan_query": [VP, i32, ctypes.POINTER(anova_window_info)],
@@ -119,6 +120,8 @@ def load():
         fn.restype = ctypes.c_int
     lib.anova_last_error.argtypes = []
     lib.anova_last_error.restype = ctypes.c_char_p
+    lib.anova_matvec_noalloc_max_bytes.argtypes = []
+    lib.anova_matvec_noalloc_max_bytes.restype = ctypes.c_int64
     _lib = lib
     return lib
 
@@ -336,6 +339,22 @@ def anova_matvec(plan: Plan, alpha, out, beta: float, stream=None) -> None:
     if nrhs != nrhs2 or lda != ldo:
         raise ValueError("alpha and out must have the same shape and leading dimension")
     _check(load().anova_matvec(plan.handle, pa, po, nrhs, lda, float(beta), _stream(stream)))
+
+
+def anova_matvec_noalloc(plan: Plan, alpha, out, beta: float, stream=None) -> None:
+    """anova_matvec with its work space in the library's static device array
+    (no device allocation; synchronises the stream first)."""
+    pa, nrhs, lda = _colmajor(alpha, "alpha", plan.N)
+    po, nrhs2, ldo = _colmajor(out, "out", plan.N)
+    if nrhs != nrhs2 or lda != ldo:
+        raise ValueError("alpha and out must have the same shape and leading dimension")
+    _check(load().anova_matvec_noalloc(plan.handle, pa, po, nrhs, lda, float(beta),
+                                       _stream(stream)))
+
+
+def anova_matvec_noalloc_max_bytes() -> int:
+    """Size of the static work space of anova_matvec_noalloc."""
+    return int(load().anova_matvec_noalloc_max_bytes())
 
 
 def krr_cg_solve(plan: Plan, y, alpha, beta: float, tol: float, maxit: int, stream=None,

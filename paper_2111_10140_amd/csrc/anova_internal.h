@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <exception>
 #include <memory>
+#include <new>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -34,6 +36,25 @@ struct Error {
     do {                                                                                   \
         if (!(cond)) throw ::anova::Error{ANOVA_E_INVALID, (msg)};                         \
     } while (0)
+
+// Runs an entry point's body: a thrown Error becomes its status (message
+// kept for anova_last_error), nothing else crosses the C ABI either.
+template <typename F>
+anova_status guarded(F &&f) {
+    try {
+        f();
+        return ANOVA_OK;
+    } catch (const Error &e) {
+        set_error(e.msg);
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return ANOVA_E_NOMEM;
+    } catch (const std::exception &e) {
+        set_error(e.what());
+        return ANOVA_E_HIP;
+    }
+}
 
 // ---------------------------------------------------------------- device buffer
 // Serialises the library's device allocations, frees and synchronous
@@ -286,6 +307,13 @@ size_t problem_work_bytes(const BatchProblem &bp);
 // Device bytes held by a plan's own buffers.
 size_t plan_device_bytes(const anova_plan_s *p);
 
+// Device memory a batch may use instead of allocating: its work space and
+// launch tables are laid out from base, within bytes.
+struct ExternalSpace {
+    char *base;
+    size_t bytes;
+};
+
 // A set of products run with one launch per stage and kernel signature.
 class Batch {
   public:
@@ -300,8 +328,17 @@ class Batch {
     const int32_t *comb_prefix = nullptr;
     std::vector<BatchProblem> probs;
 
-    // (re)build for the given problems; workspace is reused when it fits
-    void build(const std::vector<BatchProblem> &problems);
+    // device addresses of the instance and combine tables (the batch's own
+    // buffers, or inside the external space)
+    const WinInst *dev_insts = nullptr;
+    const CombInst *dev_combs = nullptr;
+    const CombineWin *dev_cwins = nullptr;
+
+    // (re)build for the given problems; workspace is reused when it fits.
+    // With ext, nothing is allocated: work space and tables go into ext
+    // (uploaded with synchronous copies; ANOVA_E_INVALID when they do not
+    // fit), and the caller keeps ext's contents until the batch has run.
+    void build(const std::vector<BatchProblem> &problems, const ExternalSpace *ext = nullptr);
     bool same(const std::vector<BatchProblem> &problems) const;
     // device bytes of the tables and of the batch-owned work space
     size_t device_bytes() const;

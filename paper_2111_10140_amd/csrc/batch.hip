@@ -102,7 +102,7 @@ bool Batch::same(const std::vector<BatchProblem> &problems) const {
     return true;
 }
 
-void Batch::build(const std::vector<BatchProblem> &problems) {
+void Batch::build(const std::vector<BatchProblem> &problems, const ExternalSpace *ext) {
     ANOVA_REQUIRE(!problems.empty(), "empty batch");
     precision = problem_precision(problems[0]);
     for (const BatchProblem &bp : problems) {
@@ -177,12 +177,21 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
             combs.push_back(ci);
         }
     }
-    if (total == 0)
+    // batch-owned work space: an allocation of the batch's own, or the
+    // start of the external space (the tables follow it there)
+    char *own_work = nullptr;
+    if (ext) {
         work.release();
-    else if (!work.ptr || work.bytes < total)
-        work.alloc(total);
+        own_work = ext->base;
+    } else {
+        if (total == 0)
+            work.release();
+        else if (!work.ptr || work.bytes < total)
+            work.alloc(total);
+        own_work = static_cast<char *>(work.ptr);
+    }
     for (size_t i = 0; i < insts.size(); ++i) {
-        char *base = slot_base[i] ? slot_base[i] : static_cast<char *>(work.ptr);
+        char *base = slot_base[i] ? slot_base[i] : own_work;
         if (grid_of[i] >= 0)
             insts[i].grid = insts[(size_t)grid_of[i]].grid;  // built before it
         else if (!insts[i].grid)
@@ -333,11 +342,47 @@ void Batch::build(const std::vector<BatchProblem> &problems) {
         comb_blocks = acc;
         comb_cnt = (int)combs.size();
     }
-    upload(d_tables, table);
-    upload(d_insts, insts);
-    upload(d_combs, combs);
-    upload(d_cwins, cwins);
-    const int32_t *tb = d_tables.as<int32_t>();
+    const int32_t *tb = nullptr;
+    if (ext) {
+        // layout of the external space: work, tables, instances, combine
+        // columns, combine windows (each 256-byte aligned); every size is
+        // checked before anything is written
+        const size_t o_tab = align256(total);
+        const size_t o_ins = o_tab + align256(table.size() * sizeof(int32_t));
+        const size_t o_cmb = o_ins + align256(insts.size() * sizeof(WinInst));
+        const size_t o_cwn = o_cmb + align256(combs.size() * sizeof(CombInst));
+        const size_t end = o_cwn + align256(cwins.size() * sizeof(CombineWin));
+        if (end > ext->bytes)
+            throw Error{ANOVA_E_INVALID,
+                        "the product needs " + std::to_string(end) +
+                            " bytes of static work space, above its maximum of " +
+                            std::to_string(ext->bytes)};
+        auto put = [&](size_t off, const void *src, size_t bytes) {
+            if (bytes)
+                ANOVA_HIP_CHECK(hipMemcpy(ext->base + off, src, bytes, hipMemcpyHostToDevice));
+        };
+        put(o_tab, table.data(), table.size() * sizeof(int32_t));
+        put(o_ins, insts.data(), insts.size() * sizeof(WinInst));
+        put(o_cmb, combs.data(), combs.size() * sizeof(CombInst));
+        put(o_cwn, cwins.data(), cwins.size() * sizeof(CombineWin));
+        d_tables.release();
+        d_insts.release();
+        d_combs.release();
+        d_cwins.release();
+        tb = reinterpret_cast<const int32_t *>(ext->base + o_tab);
+        dev_insts = reinterpret_cast<const WinInst *>(ext->base + o_ins);
+        dev_combs = reinterpret_cast<const CombInst *>(ext->base + o_cmb);
+        dev_cwins = reinterpret_cast<const CombineWin *>(ext->base + o_cwn);
+    } else {
+        upload(d_tables, table);
+        upload(d_insts, insts);
+        upload(d_combs, combs);
+        upload(d_cwins, cwins);
+        tb = d_tables.as<int32_t>();
+        dev_insts = d_insts.as<WinInst>();
+        dev_combs = d_combs.as<CombInst>();
+        dev_cwins = d_cwins.as<CombineWin>();
+    }
     for (size_t k = 0; k < pending.size(); ++k) {
         pending[k].g.members = tb + moff[k];
         pending[k].g.prefix = tb + poff[k];
@@ -399,7 +444,7 @@ void run_cached(std::vector<std::unique_ptr<Batch>> &cache, const std::vector<Ba
 }
 
 void Batch::run(hipStream_t s, anova_plan_s *timing, unsigned mask) const {
-    const WinInst *di = d_insts.as<WinInst>();
+    const WinInst *di = dev_insts;
     size_t k = 0;
     // groups are stored stage by stage in execution order
     while (k < groups.size()) {
@@ -417,7 +462,7 @@ void Batch::run(hipStream_t s, anova_plan_s *timing, unsigned mask) const {
     }
     if ((mask & (1u << kStageCombine)) && comb_cnt > 0) {
         timed_launch(timing, kStageCombine, s, [&] {
-            run_combine(d_combs.as<CombInst>(), d_cwins.as<CombineWin>(), comb_prefix, comb_cnt,
+            run_combine(dev_combs, dev_cwins, comb_prefix, comb_cnt,
                         comb_blocks, precision, s);
         });
     }

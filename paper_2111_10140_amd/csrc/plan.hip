@@ -984,23 +984,6 @@ void plan_predict(anova_plan_s *p, const double *alpha, double *out, int nrhs, i
 
 using namespace anova;
 
-template <typename F>
-static anova_status guarded(F &&f) {
-    try {
-        f();
-        return ANOVA_OK;
-    } catch (const Error &e) {
-        set_error(e.msg);
-        return e.st;
-    } catch (const std::bad_alloc &) {
-        set_error("host allocation failed");
-        return ANOVA_E_NOMEM;
-    } catch (const std::exception &e) {
-        set_error(e.what());
-        return ANOVA_E_HIP;
-    }
-}
-
 size_t anova::plan_device_bytes(const anova_plan_s *p) {
     size_t b = 0;
     for (const std::vector<WindowPlan> *ws : {&p->win, &p->win64, &p->tgt})
