@@ -77,6 +77,11 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with paper_2111_10140_amd/build.py "
                           "(there is no CPU fallback)")
+    # torch ships its own HIP runtime; it has to be the one loaded first, so
+    # that the library's HIP calls and torch's tensors and streams share one
+    # runtime (loading the library first pulls in the system runtime, and
+    # the two then disagree about the devices)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sigs = {
