@@ -149,9 +149,10 @@ def time_matvecs(A, torch, plan, a, out, beta, steps, warmup):
 def graph_timing(A, torch, plan, a, out, beta, steps, warmup):
     """One product captured into a graph (the launch tables are built by an
     eager product first, so nothing is allocated or uploaded inside the
-    capture), `warmup` replays, then `steps` replays each bracketed by
-    events on the replaying stream.  Returns (graph, mean ms over the timed
-    region, sorted per-replay ms, every replay equal to the eager result)."""
+    capture), `warmup` replays, then `steps` back-to-back replays timed
+    together, then `steps` more each bracketed by events on the replaying
+    stream.  Returns (graph, mean ms over the timed region, sorted
+    per-replay ms, every replay equal to the eager result)."""
     A.anova_matvec(plan, a, out, beta)
     torch.cuda.synchronize()
     ref = out.clone()
@@ -164,16 +165,22 @@ def graph_timing(A, torch, plan, a, out, beta, steps, warmup):
         g.replay()
         torch.cuda.synchronize()
         ok = ok and torch.equal(out, ref)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
+    # the timed region: `steps` back-to-back replays between two events
     t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record()
+    for _ in range(steps):
+        g.replay()
+    t1.record()
+    torch.cuda.synchronize()
+    # the distribution: the same number of replays, each between events of
+    # its own (the extra event records are outside the timed region above)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
     for e0, e1 in ev:
         e0.record()
         g.replay()
         e1.record()
-    t1.record()
     torch.cuda.synchronize()
     per = sorted(e0.elapsed_time(e1) for e0, e1 in ev)
     ok = ok and torch.equal(out, ref)
