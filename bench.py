@@ -63,6 +63,10 @@ def parse():
                     help="device memory the live requests may hold together")
     ap.add_argument("--serve-round", type=int, default=4,
                     help="CG iterations per scheduling round of the serving loop")
+    ap.add_argument("--sweep-requests", type=int, default=300,
+                    help="requests per arrival rate of the serving rate sweep (0: no sweep)")
+    ap.add_argument("--sweep-n-hi", type=int, default=50_000,
+                    help="largest N of the rate sweep's requests")
     ap.add_argument("--skip-batched", action="store_true")
     ap.add_argument("--skip-tuned", action="store_true")
     ap.add_argument("--skip-large", action="store_true")
@@ -279,6 +283,31 @@ def precision_split(A, torch, X, p, a, out, plan32, target):
                  "parameters for the same error target, so the solutions differ by both "
                  "approximations as well as by precision")
     return res
+
+
+def cg_iteration_timing(A, torch, plan, p, product_ms, iters=400, warmup=20):
+    """Device time of CG iterations on the headline system: one solve
+    advanced by krr_cg_iterate (one captured graph per iteration: the
+    product, whose combine also reduces p.q, the fused x/r update with its
+    r.r reduction, and the p update; every 50th iteration adds the float64
+    residual product), timed with events on the stream over `iters`
+    iterations after `warmup`; tol 0 keeps every iteration active."""
+    y = torch.from_numpy(np.ascontiguousarray(p.y[:, 0])).cuda()
+    x = torch.empty_like(y)
+    sv = A.Solve(plan, y, x, p.beta, 0.0, iters + warmup + 10)
+    A.krr_cg_iterate([sv], warmup)
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    A.krr_cg_iterate([sv], iters)
+    t1.record()
+    torch.cuda.synchronize()
+    us = t0.elapsed_time(t1) * 1e3 / iters
+    sv.destroy()
+    return {"us_per_iteration": round(us, 2), "iterations": iters,
+            "product_us": round(product_ms * 1e3, 2),
+            "iteration_over_product": round(us / (product_ms * 1e3), 3),
+            "includes": "float64 residual product every 50th iteration"}
 
 
 def batched_config(A, torch):
@@ -544,6 +573,43 @@ def serving(args, A):
     }
 
 
+SWEEP_LOADS = (0.25, 0.5, 0.75, 0.9, 1.0, 1.2)
+
+
+def serving_sweep(args, A):
+    """Served solves at Poisson arrival rates of SWEEP_LOADS x the measured
+    closed-loop capacity, the same `--sweep-requests` requests at every rate
+    (N uniform in [1000, --sweep-n-hi], the request mix of the serving
+    stream otherwise); p50/p99 over the requests after the first 10%."""
+    import workloads
+    from paper_2111_10140_amd.serve import HipExecutor, Server
+    R = args.sweep_requests
+    reqs = workloads.serving_stream(R, rate=1.0, n_hi=args.sweep_n_hi)
+    ex = HipExecutor(A.ANOVA_FP32_NFFT, target_err=1e-4)
+    budget = int(args.serve_budget_gb * (1 << 30))
+    closed = serve_stream(Server, ex, reqs, [0.0] * R, budget, 64, args.serve_round)
+    cap = closed.stats(0.0)["solves_per_s"]
+    rows = []
+    for f in SWEEP_LOADS:
+        rate = f * cap
+        srv = serve_stream(Server, ex, reqs, [r.arrival / rate for r in reqs], budget, 64,
+                           args.serve_round)
+        st = srv.stats(0.1)
+        ok = sum(1 for r in srv.results.values() if r.status == "OK")
+        rows.append({"load": f, "rate_per_s": round(rate, 3),
+                     "p50_ms": round(st["p50_s"] * 1e3, 2), "p99_ms": round(st["p99_s"] * 1e3, 2),
+                     "mean_ms": round(st["mean_s"] * 1e3, 2),
+                     "solves_per_s": round(st["solves_per_s"], 3), "peak_live": st["peak_live"],
+                     "ok": ok})
+        print(f"# serving sweep: {json.dumps(rows[-1])}", file=sys.stderr, flush=True)
+    return {"workload": f"{R} KRR solves per rate: N uniform in [1000, {args.sweep_n_hi}], "
+                        "d in {6,9,12}, ell uniform in [0.1, 0.4], beta=1, 1-8 RHS, fp32 NFFT + "
+                        "fp64 CG, tol 1e-6, plan for err<=1e-4",
+            "requests_per_rate": R, "capacity_solves_per_s": round(cap, 3),
+            "latency_from": "arrival (queueing, planning, CG, result copy); first 10% excluded",
+            "rates": rows}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -651,6 +717,9 @@ def main():
                              "matvecs_per_s": round(1e3 / pct(cold, 50), 2),
                              "flush": "512 MiB written before each replay"}}
 
+    cg_iter = cg_iteration_timing(A, torch, plan, p, pct(per_replay, 50))
+    print(f"# cg iteration: {json.dumps(cg_iter)}", file=sys.stderr, flush=True)
+
     fixed = None
     if not args.skip_fixed:
         plan_f = A.anova_fastsum_plan(X, p.windows, A.make_params(p.ell, A.ANOVA_FP32_NFFT, M=64,
@@ -742,6 +811,8 @@ def main():
         predicted = predict_config(A, torch, max(10, args.steps // 2))
         print(f"# predict: {json.dumps(predicted)}", file=sys.stderr, flush=True)
     served = None if args.skip_serve else serving(args, A)
+    if served is not None and args.sweep_requests > 0:
+        served["rate_sweep"] = serving_sweep(args, A)
 
     res = {
         "metric": "ANOVA matvecs/s N=1M,3 windows d_A=3 (err<=1e-4)",
@@ -756,6 +827,7 @@ def main():
                    "rel_err_sampled_rows": rel, "plan_seconds": round(plan_s, 3)},
         "roofline": roof,
         "timing": timing,
+        "cg_iteration": cg_iter,
         "stages_per_launch": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv)
                                   for kk, vv in v.items()} for k, v in per_launch.items()},
         "fixed_params": fixed,

@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libanova.so")
-SOURCES = ["plan.hip", "kernels.hip", "batch.hip", "cg.hip", "shifts.hip", "noalloc.hip"]
+SOURCES = ["plan.hip", "kernels.hip", "batch.hip", "cg.hip", "shifts.hip", "noalloc.hip",
+           "binning.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -140,6 +140,8 @@ struct WindowPlan {
     double fit_err = 0;          // max error of the window polynomials
     // tiling
     int tile = 0;                // tile edge in grid points (same in every dimension)
+    int tile_cap = 0;            // > 0: per-point kernels take tiles of at most this
+                                 // edge (the measured parameter choice tries halves)
     int tiles_per_dim = 0;
     int64_t n_tiles = 0, n_nonempty = 0, n_sub = 0;
     int poly_deg = 0;
@@ -245,12 +247,37 @@ struct WinInst {
     int32_t fold_act, fold_len;  // entries of fold_tiles: tiles with regions, all
 };
 
+// CG state of one column (device memory): the scalars of Sec. 2's
+// conjugate-gradient recurrence and the column's stopping state.
+struct CgScal {
+    double rho;      // r.r of the current residual
+    double ynorm2;   // y.y
+    double tol2;     // tol^2
+    double a, b;     // step length and direction update
+    double pq;       // p.q of the current iteration
+    int32_t active;  // 1 while the column iterates
+    int32_t status;  // 0 running, 1 converged, 2 breakdown, 3 maxit reached
+    int32_t iters;
+    int32_t maxit;
+    int32_t period;      // residual recomputed at iterations period, 2 period, ...
+    int32_t exact_only;  // 1: stop only on a recomputed (float64) residual
+};
+
+// A product inside a CG iteration, q = (K~ + beta I) p: for each output
+// column the combine kernel also forms the partial sums of p.q (one per
+// combine workgroup of the column), so the iteration needs no separate pass
+// over p and q for the step length.
+struct CgHook {
+    double *partial;
+};
+
 // One output column of the combine kernel.
 struct CombInst {
     double *out;
     const double *alpha;
     double beta;
     int32_t N, win0, P, accumulate;
+    CgHook hook;  // partial == nullptr: a plain product
 };
 
 // Stage identifiers; the first five are the reported timing kinds.
@@ -291,6 +318,8 @@ struct BatchProblem {
                                     // when it has them
     bool predict = false;           // out (plan->Nz rows) = K~(Z, X) alpha: spread
                                     // at the plan's points, gather at its targets
+    const CgHook *hooks = nullptr;  // host array of nrhs: the columns' CG
+                                    // reductions fused into the combine
 };
 
 // Windows and arithmetic precision a batch problem runs with.
@@ -377,12 +406,12 @@ void run_cached(std::vector<std::unique_ptr<Batch>> &cache, const std::vector<Ba
 void run_group(const BatchGroup &g, int precision, const WinInst *insts, hipStream_t s);
 void run_combine(const CombInst *cis, const CombineWin *wins, const int32_t *prefix, int cnt,
                  int blocks, int precision, hipStream_t s);
-int convolve_lines_per_block(int n, int nq);
+int convolve_lines_per_block(int n, int nq, int elem_bytes);
 int cell_tile(int dA);
-bool cell_width_supported(int dA, int W);
-int cell_point_splits(int dA, int W);
+bool cell_width_supported(int dA, int W, int precision);
+int cell_point_splits(int dA, int W, int precision);
 bool convolve_direct(int n, int dA);  // small grids: circular convolution by taps, planes then z
-int cell_resident_blocks(int dA, int W);  // per-cell spreading workgroups held at once
+int cell_resident_blocks(int dA, int W, int precision);  // per-cell spreading workgroups held at once
 int fold_blocks(const WinInst &w);  // fold workgroups of an instance
 int combine_span();
 int permute_span();
@@ -401,6 +430,35 @@ void upload(DevBuf &buf, const std::vector<T> &v) {
     if (!v.empty())
         ANOVA_HIP_CHECK(hipMemcpy(buf.ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
 }
+
+// Points of a plan: rows of `ld` doubles in host memory (host != nullptr) or
+// in device memory (dev != nullptr; kernels on stream s).
+struct Points {
+    const double *host = nullptr;
+    const double *dev = nullptr;
+    int64_t N = 0, ld = 0;
+    hipStream_t s = nullptr;
+};
+
+// Device binning (binning.hip): per-point cells and offsets, the points'
+// count per grid cell, and the sorted node records and permutation.
+struct DeviceBins {
+    DevBuf cellw, frac, hist, nodes, perm;
+};
+// Minimum and maximum of each of the d columns of device X; finite is
+// false if some entry is not finite.  Synchronises s.
+void device_bounds(const double *X, int64_t N, int64_t ld, int d, double *lo, double *hi,
+                   bool &finite, hipStream_t s);
+// Cells and offsets of every point of window w (its n, h, centre,
+// features), and hist[cell] = points per grid cell (host copy).  Synchronises s.
+template <typename T>
+void device_bin(const double *X, int64_t N, int64_t ld, const WindowPlan &w, DeviceBins &b,
+                std::vector<int32_t> &hist, hipStream_t s);
+// Points sorted by (tile, cell inside the tile) when dense, else by tile,
+// ties by original index: b.nodes (Node records) and b.perm.  Synchronises s.
+template <typename T, typename Node>
+void device_sort_nodes(const WindowPlan &w, int64_t N, int64_t cells_per_tile, bool dense,
+                       DeviceBins &b, hipStream_t s);
 
 // optional per-stage timing
 hipEvent_t pool_event(anova_plan_s *p);

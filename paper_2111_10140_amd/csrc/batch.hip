@@ -96,7 +96,7 @@ bool Batch::same(const std::vector<BatchProblem> &problems) const {
             a.ld != b.ld || a.ld_out != b.ld_out || a.beta != b.beta ||
             a.only_window != b.only_window ||
             a.grid_override != b.grid_override || a.work != b.work ||
-            a.residual != b.residual || a.predict != b.predict)
+            a.residual != b.residual || a.predict != b.predict || a.hooks || b.hooks)
             return false;
     }
     return true;
@@ -141,6 +141,7 @@ void Batch::build(const std::vector<BatchProblem> &problems, const ExternalSpace
             ci.N = (int32_t)(bp.predict ? p->Nz : p->N);
             ci.win0 = (int32_t)cwins.size();
             ci.accumulate = bp.only_window >= 0 ? 1 : 0;
+            if (bp.hooks) ci.hook = bp.hooks[c];
             int nw = 0;
             for (int l = 0; l < p->P; ++l) {
                 if (bp.only_window >= 0 && l != bp.only_window) continue;
@@ -276,7 +277,7 @@ void Batch::build(const std::vector<BatchProblem> &problems, const ExternalSpace
     for (int pass = 0; pass < 3; ++pass) {
         add_stage(
             kStageConvolve, [](const WinInst &w) { return std::make_tuple(w.n, w.dA, 0, 0, 0, 0); },
-            [pass](const WinInst &w, int &b) {
+            [pass, es](const WinInst &w, int &b) {
                 if (pass >= w.dA) return false;
                 if (convolve_direct(w.n, w.dA)) {
                     if (pass == 1) return false;  // done with axis 0
@@ -286,17 +287,17 @@ void Batch::build(const std::vector<BatchProblem> &problems, const ExternalSpace
                 int nlines = 1;
                 for (int t = 1; t < w.dA; ++t) nlines *= w.n;
                 const int nq = (nlines + 1) / 2;
-                const int np = convolve_lines_per_block(w.n, nq);
+                const int np = convolve_lines_per_block(w.n, nq, (int)es);
                 b = (nq + np - 1) / np;
                 return true;
             },
-            [pass](BatchGroup &g, const WinInst &w) {
+            [pass, es](BatchGroup &g, const WinInst &w) {
                 g.n = w.n;
                 g.axis = convolve_direct(w.n, w.dA) ? (pass == 0 ? -1 : -2) : pass;
                 // instances of one group share n and d_A, hence the line count
                 int nlines = 1;
                 for (int t = 1; t < w.dA; ++t) nlines *= w.n;
-                g.np = convolve_lines_per_block(w.n, (nlines + 1) / 2);
+                g.np = convolve_lines_per_block(w.n, (nlines + 1) / 2, (int)es);
             });
     }
     // gather

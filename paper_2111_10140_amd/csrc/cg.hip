@@ -33,20 +33,6 @@ constexpr int kSpan = 4 * kRedBlock;  // elements per block and column
 constexpr int kResidualPeriod = 50;        // replacement with the plan's own product
 constexpr int kResidualPeriodExact = 50;   // float64 residuals of float32 plans
 
-struct CgScal {
-    double rho;      // r.r of the current residual
-    double ynorm2;   // y.y
-    double tol2;     // tol^2
-    double a, b;     // step length and direction update
-    double pq;       // p.q of the current iteration
-    int32_t active;  // 1 while the column iterates
-    int32_t status;  // 0 running, 1 converged, 2 breakdown, 3 maxit reached
-    int32_t iters;
-    int32_t maxit;
-    int32_t period;      // residual recomputed at iterations period, 2 period, ...
-    int32_t exact_only;  // 1: stop only on a recomputed (float64) residual
-};
-
 // One column of one solve, as seen by the vector kernels.
 struct CgCol {
     double *x;             // caller's alpha column
@@ -55,9 +41,11 @@ struct CgCol {
     double *partial;       // nblk partial sums
     double *partial2;      // nblk partial sums of the replaced (recursive) residual
     CgScal *sc;
+    double *cpartial;      // ncomb partial sums of p.q, written by the product's
+                           // combine kernel
     int64_t N;
     int32_t nblk;
-    int32_t pad;
+    int32_t ncomb;
 };
 
 // ---------------------------------------------------------------- device helpers
@@ -145,23 +133,11 @@ __global__ __launch_bounds__(kRedBlock) void cg_init_scal_kernel(const CgCol *__
     }
 }
 
-// partial p.q
-__global__ __launch_bounds__(kRedBlock) void cg_dot_pq_kernel(const CgCol *__restrict__ cols,
-                                                              const int32_t *__restrict__ prefix,
-                                                              int cnt) {
-    __shared__ double sh[kRedBlock / 64];
-    const ColRange cr = col_range(cols, prefix, cnt);
-    double v = 0.0;
-    for (int64_t i = cr.i0 + threadIdx.x; i < cr.i1; i += kRedBlock) v += cr.col.p[i] * cr.col.q[i];
-    v = block_sum(v, sh);
-    if (threadIdx.x == 0) cr.col.partial[cr.lb] = v;
-}
-
-// a = rho / (p.q)
+// a = rho / (p.q), p.q from the partial sums of the product's combine kernel
 __global__ __launch_bounds__(kRedBlock) void cg_alpha_kernel(const CgCol *__restrict__ cols) {
     __shared__ double sh[kRedBlock / 64];
     const CgCol col = cols[blockIdx.x];
-    const double pq = sum_partials(col.partial, col.nblk, sh);
+    const double pq = sum_partials(col.cpartial, col.ncomb, sh);
     if (threadIdx.x == 0) {
         CgScal s = *col.sc;
         s.pq = pq;
@@ -177,6 +153,41 @@ __global__ __launch_bounds__(kRedBlock) void cg_alpha_kernel(const CgCol *__rest
         }
         *col.sc = s;
     }
+}
+
+// rho' = r.r; convergence and iteration-limit tests; b = rho'/rho.
+// `replaced`: this iteration recomputed the residual of the columns whose
+// period is due (rr_rec: r.r of the recursive residual it replaced); an
+// exact_only column may stop only then.  When such a recomputed (float64)
+// residual has drifted above the recursive one (r.r more than 4 times
+// larger), the float32 recursion has reached its rounding floor:
+// continuing its directions would scale p by rho'/rho and the product's
+// rounding with it, so the column restarts with p = r.
+__device__ __forceinline__ void cg_direction_update(CgScal *sc, double rr, double rr_rec,
+                                                    bool replaced) {
+    CgScal s = *sc;
+    if (s.active) {
+        const bool now = replaced && (s.iters + 1) % s.period == 0;
+        const bool checked = !s.exact_only || now;
+        const bool restart = s.exact_only && now && rr > 4.0 * rr_rec;
+        s.iters += 1;
+        if (!isfinite(rr)) {
+            s.active = 0;
+            s.status = 2;
+        } else if (checked && rr <= s.tol2 * s.ynorm2) {
+            s.active = 0;
+            s.status = 1;
+            s.rho = rr;
+        } else if (s.iters >= s.maxit) {
+            s.active = 0;
+            s.status = 3;
+            s.rho = rr;
+        } else {
+            s.b = (s.rho > 0.0 && !restart) ? rr / s.rho : 0.0;
+            s.rho = rr;
+        }
+    }
+    *sc = s;
 }
 
 // x += a p; r -= a q; partial r.r
@@ -230,44 +241,15 @@ __global__ __launch_bounds__(kRedBlock) void cg_replace_kernel(const CgCol *__re
     }
 }
 
-// rho' = r.r; convergence and iteration-limit tests; b = rho'/rho.
-// `replaced`: this launch recomputed the residual of the columns whose
-// period is due; an exact_only column may stop only then.  When such a
-// recomputed (float64) residual has drifted above the recursive one
-// (r.r more than 4 times larger), the float32 recursion has reached its
-// rounding floor: continuing its directions would scale p by rho'/rho and
-// the product's rounding with it, so the column restarts with p = r.
+// The scalar update of an iteration (one workgroup per column): r.r of the
+// residual and, when `replaced`, of the recursive one it replaced.
 __global__ __launch_bounds__(kRedBlock) void cg_beta_kernel(const CgCol *__restrict__ cols,
                                                             int replaced) {
     __shared__ double sh[kRedBlock / 64];
     const CgCol col = cols[blockIdx.x];
     const double rr = sum_partials(col.partial, col.nblk, sh);
     const double rr_rec = replaced ? sum_partials(col.partial2, col.nblk, sh) : 0.0;
-    if (threadIdx.x == 0) {
-        CgScal s = *col.sc;
-        if (s.active) {
-            const bool now = replaced && (s.iters + 1) % s.period == 0;
-            const bool checked = !s.exact_only || now;
-            const bool restart = s.exact_only && now && rr > 4.0 * rr_rec;
-            s.iters += 1;
-            if (!isfinite(rr)) {
-                s.active = 0;
-                s.status = 2;
-            } else if (checked && rr <= s.tol2 * s.ynorm2) {
-                s.active = 0;
-                s.status = 1;
-                s.rho = rr;
-            } else if (s.iters >= s.maxit) {
-                s.active = 0;
-                s.status = 3;
-                s.rho = rr;
-            } else {
-                s.b = (s.rho > 0.0 && !restart) ? rr / s.rho : 0.0;
-                s.rho = rr;
-            }
-        }
-        *col.sc = s;
-    }
+    if (threadIdx.x == 0) cg_direction_update(col.sc, rr, rr_rec, replaced != 0);
 }
 
 // p = r + b p
@@ -327,6 +309,8 @@ struct anova_cg_s {
     bool exact_only = false;  // float32 plan with float64 residuals
     int64_t it = 0;  // iterations taken (every active column has taken as many)
     DevBuf r, p, q, partial, scal;
+    DevBuf cpartial;  // p.q partials of the product's combine workgroups
+    std::vector<CgHook> hooks;  // per column: where the combine puts them
     DevBuf work;  // product work space of this solve's (window, column) instances
     ColList own;  // this solve's columns alone (init, final residual)
     std::unique_ptr<Batch> xq;  // q = A x, for the final residual
@@ -353,10 +337,13 @@ struct StepGraph {
     DevBuf d_solve_cols;  // int32 [count + 1]: first column of each solve in `list`
     Batch pq, xq;  // q = A p, q = A x over every solve in the list
     hipStream_t cap = nullptr;
-    hipGraphExec_t g_plain = nullptr, g_replace = nullptr;
+    // one iteration, one with residual recomputation, kGraphIters
+    // iterations without
+    hipGraphExec_t g_plain = nullptr, g_replace = nullptr, g_block = nullptr;
     ~StepGraph() {
         if (g_plain) (void)hipGraphExecDestroy(g_plain);
         if (g_replace) (void)hipGraphExecDestroy(g_replace);
+        if (g_block) (void)hipGraphExecDestroy(g_block);
         if (cap) (void)hipStreamDestroy(cap);
     }
 };
@@ -369,8 +356,8 @@ static void record_iteration(StepGraph &G, bool replace, hipStream_t s) {
     const ColList &L = G.list;
     const CgCol *dc = L.d_cols.as<CgCol>();
     const int32_t *dp = L.d_prefix.as<int32_t>();
+    // q = A p; the product's combine also forms the p.q partial sums
     G.pq.run(s);
-    hipLaunchKernelGGL(cg_dot_pq_kernel, dim3(L.blocks), dim3(kRedBlock), 0, s, dc, dp, L.cnt);
     hipLaunchKernelGGL(cg_alpha_kernel, dim3(L.cnt), dim3(kRedBlock), 0, s, dc);
     hipLaunchKernelGGL(cg_update_xr_kernel, dim3(L.blocks), dim3(kRedBlock), 0, s, dc, dp, L.cnt);
     if (replace) {
@@ -383,11 +370,16 @@ static void record_iteration(StepGraph &G, bool replace, hipStream_t s) {
     ANOVA_HIP_CHECK(hipGetLastError());
 }
 
-static hipGraphExec_t capture(StepGraph &G, bool replace) {
+// Iterations replayed by one graph launch when none of them recomputes a
+// residual: consecutive launches of separate graphs leave a gap of several
+// microseconds between them, which a longer graph pays once.
+constexpr int kGraphIters = 4;
+
+static hipGraphExec_t capture(StepGraph &G, bool replace, int iters = 1) {
     hipGraph_t g = nullptr;
     ANOVA_HIP_CHECK(hipStreamBeginCapture(G.cap, hipStreamCaptureModeThreadLocal));
     try {
-        record_iteration(G, replace, G.cap);
+        for (int k = 0; k < iters; ++k) record_iteration(G, replace, G.cap);
     } catch (...) {
         (void)hipStreamEndCapture(G.cap, &g);
         if (g) (void)hipGraphDestroy(g);
@@ -435,7 +427,9 @@ static StepGraph &step_graph(anova_cg_s *const *solves, int count) {
         anova_cg_s *sv = solves[i];
         G->list.cols.insert(G->list.cols.end(), sv->own.cols.begin(), sv->own.cols.end());
         solve_cols.push_back((int32_t)G->list.cols.size());
-        pq_probs.push_back(product(sv, sv->p.as<double>(), false));
+        BatchProblem bp = product(sv, sv->p.as<double>(), false);
+        bp.hooks = sv->hooks.data();
+        pq_probs.push_back(bp);
         BatchProblem bx = product(sv, sv->x, true);
         bx.ld = sv->ld;      // x columns follow the caller's leading dimension
         bx.ld_out = sv->N;   // q is packed
@@ -448,6 +442,7 @@ static StepGraph &step_graph(anova_cg_s *const *solves, int count) {
     ANOVA_HIP_CHECK(hipStreamCreateWithFlags(&G->cap, hipStreamNonBlocking));
     G->g_plain = capture(*G, false);
     G->g_replace = capture(*G, true);
+    G->g_block = capture(*G, false, kGraphIters);
     if (g_steps.size() >= kStepCache) g_steps.erase(g_steps.begin());
     g_steps.push_back(std::move(G));
     return *g_steps.back();
@@ -532,6 +527,8 @@ extern "C" anova_status krr_cg_start(anova_cg_t *out, anova_plan_t plan, const d
         sv->q.alloc(vec);
         sv->partial.alloc((size_t)2 * nblk * nrhs * sizeof(double));
         sv->scal.alloc(sizeof(CgScal) * nrhs);
+        const int64_t ncomb = (sv->N + combine_span() - 1) / combine_span();
+        sv->cpartial.alloc((size_t)ncomb * nrhs * sizeof(double));
         sv->exact_only = plan->precision == ANOVA_FP32_NFFT && !plan->win64.empty();
         sv->period = sv->exact_only ? kResidualPeriodExact : kResidualPeriod;
         sv->work.alloc(solve_work_bytes(plan, nrhs));
@@ -545,6 +542,9 @@ extern "C" anova_status krr_cg_start(anova_cg_t *out, anova_plan_t plan, const d
             col.partial = sv->partial.as<double>() + (size_t)c * nblk;
             col.partial2 = sv->partial.as<double>() + (size_t)(nrhs + c) * nblk;
             col.sc = sv->scal.as<CgScal>() + c;
+            col.cpartial = sv->cpartial.as<double>() + (size_t)c * ncomb;
+            col.ncomb = (int32_t)ncomb;
+            sv->hooks.push_back(CgHook{col.cpartial});
             col.N = sv->N;
             col.nblk = nblk;
             sv->own.cols.push_back(col);
@@ -576,12 +576,25 @@ extern "C" anova_status krr_cg_iterate(anova_cg_t *solves, int32_t count, int32_
         std::lock_guard<std::mutex> lock(g_step_mu);
         StepGraph &G = step_graph(solves, count);
         hipStream_t s = (hipStream_t)stream;
-        for (int k = 0; k < iters; ++k) {
+        for (int k = 0; k < iters;) {
+            // the next kGraphIters iterations in one launch when no solve
+            // recomputes its residual in them
+            bool block = iters - k >= kGraphIters;
+            for (int i = 0; i < count && block; ++i)
+                for (int j = 1; j <= kGraphIters; ++j)
+                    block = block && (solves[i]->it + j) % solves[i]->period != 0;
+            if (block) {
+                ANOVA_HIP_CHECK(hipGraphLaunch(G.g_block, s));
+                for (int i = 0; i < count; ++i) solves[i]->it += kGraphIters;
+                k += kGraphIters;
+                continue;
+            }
             bool rep = false;
             for (int i = 0; i < count; ++i)
                 rep = rep || (solves[i]->it + 1) % solves[i]->period == 0;
             ANOVA_HIP_CHECK(hipGraphLaunch(rep ? G.g_replace : G.g_plain, s));
             for (int i = 0; i < count; ++i) ++solves[i]->it;
+            ++k;
         }
         return ANOVA_OK;
     });
@@ -696,6 +709,8 @@ extern "C" anova_status anova_plan_footprint(anova_plan_t plan, int32_t nrhs,
             auto dev = [](size_t b) { return (int64_t)std::max<size_t>(b, 256); };
             int64_t b = 3 * dev((size_t)N * nrhs * sizeof(double));
             b += dev((size_t)2 * nblk * nrhs * sizeof(double)) + dev(sizeof(CgScal) * nrhs);
+            const int64_t ncomb = (N + combine_span() - 1) / combine_span();
+            b += dev((size_t)ncomb * nrhs * sizeof(double));
             b += dev(solve_work_bytes(plan, nrhs));
             b += dev(sizeof(CgCol) * nrhs) + dev(sizeof(int32_t) * (nrhs + 1));
             *solve_bytes = b;

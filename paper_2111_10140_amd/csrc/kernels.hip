@@ -192,6 +192,19 @@ __device__ __forceinline__ double block_max(double v, double *sh) {
     return r;
 }
 
+// Sum over the workgroup (kBlock threads) in a fixed order; valid in
+// thread 0.  sh: kBlock / 64 doubles of LDS.
+__device__ __forceinline__ double block_sum_f64(double v, double *sh) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBlock / 64; ++i) t += sh[i];
+    __syncthreads();
+    return t;
+}
+
 // |a| for the largest-coefficient search of the float32 kernels: values
 // beyond the float range (and NaN) become infinity, which marks the region
 // as non-finite.
@@ -580,6 +593,234 @@ __global__ __launch_bounds__(kBlock) void gather_cell_kernel(const WinInst *__re
             acc = DA == 3 ? fmaf(sc, wz[c], acc) : sc;
         }
         tmp[wi.perm[j]] = acc;  // caller order
+    }
+}
+
+// ------------------------------------------------------------------ per-cell, float64
+// Float64 per-cell kernels (d_A = 3, W <= 6, tiles of 4^3 cells): a cell's
+// W^3 float64 support does not fit one thread's registers, so the four
+// lanes of a cell each own a quarter of it, (z half sz) x (y half sy) x all
+// of x, and every lane of the cell walks all of its points.  A lane owning
+// an upper half indexes it mirrored (register c holds offset W-1-c) and
+// evaluates the lower-half polynomials at -z, as the window is even.
+// Spreading stages the cells' lower z halves in LDS, adds them into the
+// region in a fixed order, then the upper halves; gathering adds the four
+// lanes' partial interpolations with DPP quad steps.  No atomics: the
+// results are the same bits for any scheduling.
+__device__ __forceinline__ double dpp_f64(double v, int ctrl_is_xor1) {
+    const long long b = __double_as_longlong(v);
+    int lo, hi;
+    if (ctrl_is_xor1) {
+        lo = __builtin_amdgcn_mov_dpp((int)b, 0xB1, 0xF, 0xF, true);
+        hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0xB1, 0xF, 0xF, true);
+    } else {
+        lo = __builtin_amdgcn_mov_dpp((int)b, 0x4E, 0xF, 0xF, true);
+        hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x4E, 0xF, 0xF, true);
+    }
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+// Sum over the four lanes of a quad, the same bits in every lane.
+__device__ __forceinline__ double quad_sum_f64(double v) {
+    v = v + dpp_f64(v, 1);
+    return v + dpp_f64(v, 0);
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock, 2) void spread_cell64_kernel(const WinInst *__restrict__ insts,
+                                                               const int32_t *__restrict__ members,
+                                                               const int32_t *__restrict__ prefix,
+                                                               int cnt) {
+    constexpr int H = W / 2, TILE = 4, CELLS = 64;
+    constexpr int L = TILE + W - 1, L2 = L * L, VOL = L2 * L;
+    constexpr int VS = H * W * W;  // one z half of a cell's support
+    constexpr int PER = (VOL + kBlock - 1) / kBlock;
+    static_assert(W % 2 == 0 && W <= 6, "supports of 4 or 6 points");
+    __shared__ __align__(16) double stage[CELLS * VS];
+    const Located loc = locate(insts, members, prefix, cnt);
+    const WinInst &wi = *loc.w;
+    const NodeF64 *__restrict__ nodes = static_cast<const NodeF64 *>(wi.nodes);
+    const int32_t *__restrict__ perm = wi.perm;
+    const double *__restrict__ alpha = wi.alpha;
+    WinPoly<double, W> wp;
+    wp.load(static_cast<const double *>(wi.poly));
+    int tk, chunk, K;
+    locate_chunk(wi.src_sub, wi.n_nonempty, loc.lb, tk, chunk, K);
+    const int key0 = wi.tiles_ne[tk] * CELLS;
+    const int cell = threadIdx.x / 4, sub = threadIdx.x % 4;
+    const int sz = sub >> 1, sy = sub & 1;
+    int pb, pe;
+    chunk_range(wi.cell_start[key0 + cell], wi.cell_start[key0 + cell + 1], chunk, K, pb, pe);
+    double acc[H][H][W];
+#pragma unroll
+    for (int c = 0; c < H; ++c)
+#pragma unroll
+        for (int b = 0; b < H; ++b)
+#pragma unroll
+            for (int i = 0; i < W; ++i) acc[c][b][i] = 0.0;
+    // the next point's record and coefficient load while the current one
+    // is accumulated (the permutation index one point earlier still)
+    double rx = 0, ry = 0, rz = 0, an = 0;
+    int pn = 0;
+    if (pb < pe) {
+        const NodeF64 nd = nodes[pb];
+        rx = nd.f[0]; ry = nd.f[1]; rz = nd.f[2];
+        an = alpha[perm[pb]];
+    }
+    if (pb + 1 < pe) pn = perm[pb + 1];
+    for (int j = pb; j < pe; ++j) {
+        const double x = rx, y = ry, z = rz, a = an;
+        if (j + 1 < pe) {
+            const NodeF64 nd = nodes[j + 1];
+            rx = nd.f[0]; ry = nd.f[1]; rz = nd.f[2];
+            an = alpha[pn];
+        }
+        if (j + 2 < pe) pn = perm[j + 2];
+        double wx[W], wy[H], wz[H];
+        wp.eval(x, wx);
+        const double zy = 2.0 * y - 1.0, zz = 2.0 * z - 1.0;
+#pragma unroll
+        for (int b = 0; b < H; ++b) wy[b] = wp.at(sy ? -zy : zy, b);
+#pragma unroll
+        for (int c = 0; c < H; ++c) wz[c] = wp.at(sz ? -zz : zz, c);
+#pragma unroll
+        for (int c = 0; c < H; ++c) {
+            const double wc = a * wz[c];
+#pragma unroll
+            for (int b = 0; b < H; ++b) {
+                const double wbc = wc * wy[b];
+#pragma unroll
+                for (int i = 0; i < W; ++i) acc[c][b][i] = fma(wbc, wx[i], acc[c][b][i]);
+            }
+        }
+    }
+    // the region: element (X, Y, Z) adds cell (dx, dy, dz)'s value at offset
+    // (X - dx, Y - dy, Z - dz); lower z halves (offsets 0 .. H-1) first
+    double sum[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) sum[k] = 0.0;
+    const int lx = cell % TILE, ly = (cell / TILE) % TILE, lz = cell / (TILE * TILE);
+    (void)lx; (void)ly; (void)lz;
+#pragma unroll 1
+    for (int half = 0; half < 2; ++half) {
+        if (half) __syncthreads();  // the first half's reads are done
+        if (sz == half) {
+            // stage[cell][c][oy][ox], c the plane inside the half (mirrored
+            // for the upper half: plane c holds offset W-1-c)
+#pragma unroll
+            for (int c = 0; c < H; ++c)
+#pragma unroll
+                for (int b = 0; b < H; ++b) {
+                    const int oy = sy ? W - 1 - b : b;
+                    double *row = stage + ((size_t)(cell * H + c) * W + oy) * W;
+#pragma unroll
+                    for (int i = 0; i < W; ++i) row[i] = acc[c][b][i];
+                }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const int e = threadIdx.x + k * kBlock;
+            if (e >= VOL) break;
+            const int X = e % L, Y = (e / L) % L, Z = e / L2;
+            double s = sum[k];
+            for (int dz = 0; dz < TILE; ++dz) {
+                const int oz = Z - dz;
+                if (oz < 0 || oz >= W) continue;
+                if ((oz >= H) != (half == 1)) continue;
+                const int c = half ? W - 1 - oz : oz;
+                for (int dy = 0; dy < TILE; ++dy) {
+                    const int oy = Y - dy;
+                    if (oy < 0 || oy >= W) continue;
+#pragma unroll
+                    for (int dx = 0; dx < TILE; ++dx) {
+                        const int ox = X - dx;
+                        if (ox < 0 || ox >= W) continue;
+                        const int cidx = (dz * TILE + dy) * TILE + dx;
+                        s += stage[((size_t)(cidx * H + c) * W + oy) * W + ox];
+                    }
+                }
+            }
+            sum[k] = s;
+        }
+    }
+    double *out = static_cast<double *>(wi.priv) + (size_t)loc.lb * VOL;
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = threadIdx.x + k * kBlock;
+        if (e < VOL) out[e] = sum[k];
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock, 2) void gather_cell64_kernel(const WinInst *__restrict__ insts,
+                                                               const int32_t *__restrict__ members,
+                                                               const int32_t *__restrict__ prefix,
+                                                               int cnt) {
+    constexpr int m = W / 2, H = W / 2, TILE = 4, CELLS = 64;
+    constexpr int L = TILE + W - 1, L2 = L * L, VOL = L2 * L;
+    __shared__ double g_lds[VOL];
+    const Located loc = locate(insts, members, prefix, cnt);
+    const WinInst &wi = *loc.w;
+    const NodeF64 *__restrict__ nodes = static_cast<const NodeF64 *>(wi.nodes);
+    const double *__restrict__ grid = static_cast<const double *>(wi.grid);
+    double *__restrict__ tmp = static_cast<double *>(wi.tmp);
+    WinPoly<double, W> wp;
+    wp.load(static_cast<const double *>(wi.poly));
+    const int n = wi.n, tpd = wi.tpd;
+    int tk, chunk, K;
+    locate_chunk(wi.src_sub, wi.n_nonempty, loc.lb, tk, chunk, K);
+    const int tile_id = wi.tiles_ne[tk];
+    const int key0 = tile_id * CELLS;
+    const int ox = (tile_id % tpd) * TILE;
+    const int oy = ((tile_id / tpd) % tpd) * TILE;
+    const int oz = (tile_id / (tpd * tpd)) * TILE;
+    for (int e = threadIdx.x; e < VOL; e += kBlock) {
+        size_t g = (size_t)wrap_index(ox - m + 1 + e % L, n);
+        g += (size_t)n * (size_t)wrap_index(oy - m + 1 + (e / L) % L, n);
+        g += (size_t)n * (size_t)n * (size_t)wrap_index(oz - m + 1 + e / L2, n);
+        g_lds[e] = grid[g];
+    }
+    __syncthreads();
+    const int cell = threadIdx.x / 4, sub = threadIdx.x % 4;
+    const int sz = sub >> 1, sy = sub & 1;
+    int pb, pe;
+    chunk_range(wi.cell_start[key0 + cell], wi.cell_start[key0 + cell + 1], chunk, K, pb, pe);
+    // the four lanes of a cell share its point count, so they leave together
+    if (pb >= pe) return;
+    const int lx = cell % TILE, ly = (cell / TILE) % TILE, lz = cell / (TILE * TILE);
+    double g[H][H][W];
+#pragma unroll
+    for (int c = 0; c < H; ++c)
+#pragma unroll
+        for (int b = 0; b < H; ++b) {
+            const int zc = sz ? W - 1 - c : c, yb = sy ? W - 1 - b : b;
+            const double *row = g_lds + ((lz + zc) * L + ly + yb) * L + lx;
+#pragma unroll
+            for (int i = 0; i < W; ++i) g[c][b][i] = row[i];
+        }
+    const int32_t *__restrict__ perm = wi.perm;
+    NodeF64 nx = nodes[pb];
+    for (int j = pb; j < pe; ++j) {
+        const NodeF64 nd = nx;
+        if (j + 1 < pe) nx = nodes[j + 1];
+        double wx[W];
+        wp.eval(nd.f[0], wx);
+        const double zy = 2.0 * nd.f[1] - 1.0, zz = 2.0 * nd.f[2] - 1.0;
+        double part = 0.0;
+#pragma unroll
+        for (int c = 0; c < H; ++c) {
+            double sc = 0.0;
+#pragma unroll
+            for (int b = 0; b < H; ++b) {
+                double sr = 0.0;
+#pragma unroll
+                for (int i = 0; i < W; ++i) sr = fma(g[c][b][i], wx[i], sr);
+                sc = fma(sr, wp.at(sy ? -zy : zy, b), sc);
+            }
+            part = fma(sc, wp.at(sz ? -zz : zz, c), part);
+        }
+        const double v = quad_sum_f64(part);
+        if (sub == 0) tmp[perm[j]] = v;  // caller order
     }
 }
 
@@ -1448,6 +1689,18 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(const CombInst *__restr
         const int i = i0 + e * kBlock;
         if (i < ci.N) ci.out[i] = s[e];
     }
+    if (ci.hook.partial == nullptr) return;
+    // CG: this workgroup's partial sum of p.q (p = alpha, q = out), added
+    // by the step-length kernel in index order
+    __shared__ double red[kBlock / 64];
+    double v = 0.0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int i = i0 + e * kBlock;
+        if (i < ci.N) v += ci.alpha[i] * s[e];
+    }
+    v = block_sum_f64(v, red);
+    if (threadIdx.x == 0) ci.hook.partial[blockIdx.x - prefix[q]] = v;
 }
 
 // ================================================================== host side
@@ -1562,7 +1815,10 @@ void spread_group(const BatchGroup &g, const WinInst *insts, hipStream_t s) {
         if constexpr (std::is_same<T, float>::value) {
             ANOVA_DA_SWITCH(g.dA, ANOVA_W_SWITCH(g.W, (spread_cell_launch<DA_, W_>(g, insts, s))));
         } else {
-            throw Error{ANOVA_E_INVALID, "per-cell kernels are float32 only"};
+            if (g.dA != 3 || g.tile != 4 || (g.W != 4 && g.W != 6))
+                throw Error{ANOVA_E_INVALID, "float64 per-cell kernels take d_A = 3, W <= 6"};
+            if (g.W == 4) launch_k(spread_cell64_kernel<4>, g, 0, insts, s);
+            else launch_k(spread_cell64_kernel<6>, g, 0, insts, s);
         }
     } else {
         ANOVA_DA_SWITCH(g.dA, ANOVA_W_SWITCH(g.W, (spread_pt_launch<T, DA_, W_>(g, insts, s))));
@@ -1574,7 +1830,10 @@ void gather_group(const BatchGroup &g, const WinInst *insts, hipStream_t s) {
         if constexpr (std::is_same<T, float>::value) {
             ANOVA_DA_SWITCH(g.dA, ANOVA_W_SWITCH(g.W, (gather_cell_launch<DA_, W_>(g, insts, s))));
         } else {
-            throw Error{ANOVA_E_INVALID, "per-cell kernels are float32 only"};
+            if (g.dA != 3 || g.tile != 4 || (g.W != 4 && g.W != 6))
+                throw Error{ANOVA_E_INVALID, "float64 per-cell kernels take d_A = 3, W <= 6"};
+            if (g.W == 4) launch_k(gather_cell64_kernel<4>, g, 0, insts, s);
+            else launch_k(gather_cell64_kernel<6>, g, 0, insts, s);
         }
     } else {
         ANOVA_DA_SWITCH(g.dA, ANOVA_W_SWITCH(g.W, (gather_pt_launch<T, DA_, W_>(g, insts, s))));
@@ -1625,15 +1884,19 @@ void convolve_group(const BatchGroup &g, const WinInst *insts, hipStream_t s) {
 }  // namespace
 
 bool convolve_direct(int n, int dA) { return dA >= 2 && n <= kConvolveDirectMax; }
-int convolve_lines_per_block(int n, int nq) {
-    // enough butterflies per stage to occupy the block, but at least ~64
-    // workgroups per grid when it has that many line pairs (the launches
-    // cover every window, so several grids share them)
-    const int per_block = std::max(1, 512 / n);
+int convolve_lines_per_block(int n, int nq, int elem_bytes) {
+    // passes along y and z read, for each line position, the workgroup's
+    // 2 NP neighbouring lines: 2 NP elements of 128 contiguous bytes keep
+    // those reads whole cache lines (NP = 16 floats or 8 doubles); the LDS
+    // holds 2 NP n complex values (32 KB at n = 128), and there are at
+    // least ~64 workgroups per grid when it has that many line pairs (the
+    // launches cover every window, so several grids share them)
+    const int per_block = std::max(1, (elem_bytes == 4 ? 2048 : 1024) / n);
     return std::max(1, std::min(per_block, (nq + 63) / 64));
 }
 int cell_tile(int dA) { return dA == 3 ? 4 : (dA == 2 ? 16 : 64); }
-bool cell_width_supported(int dA, int W) {
+bool cell_width_supported(int dA, int W, int precision) {
+    if (precision == ANOVA_FP64) return dA == 3 && (W == 4 || W == 6);
     return dA == 3 ? (W <= 6 || W == 8 || W == 12) : (dA == 2 ? W <= 8 : W <= 16);
 }
 int fold_blocks(const WinInst &w) {
@@ -1642,25 +1905,33 @@ int fold_blocks(const WinInst &w) {
     const int per = (cells >= kBlock ? 1 : kBlock / cells) * kFoldZeroPasses;
     return w.fold_act + (w.fold_len - w.fold_act + per - 1) / per;
 }
-int cell_resident_blocks(int dA, int W) {
+int cell_resident_blocks(int dA, int W, int precision) {
     static std::mutex mu;
-    static std::map<std::tuple<int, int, int>, int> cache;
+    static std::map<std::tuple<int, int, int, int>, int> cache;
     int dev = 0;
     ANOVA_HIP_CHECK(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lock(mu);
-    const auto key = std::make_tuple(dev, dA, W);
+    const auto key = std::make_tuple(dev, dA, W, precision);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
     int nb = 0, cus = 0;
-    ANOVA_DA_SWITCH(dA, ANOVA_W_SWITCH(W, (nb = spread_cell_blocks_per_cu<DA_, W_>())));
+    if (precision == ANOVA_FP64) {
+        const void *k = W == 4 ? reinterpret_cast<const void *>(spread_cell64_kernel<4>)
+                               : reinterpret_cast<const void *>(spread_cell64_kernel<6>);
+        ANOVA_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kBlock, 0));
+    } else {
+        ANOVA_DA_SWITCH(dA, ANOVA_W_SWITCH(W, (nb = spread_cell_blocks_per_cu<DA_, W_>())));
+    }
     ANOVA_HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     const int r = std::max(1, nb) * std::max(1, cus);
     cache[key] = r;
     return r;
 }
-int cell_point_splits(int dA, int W) {
-    // lanes of a cell that split its points (the wide 3-D kernels split the
-    // support instead: every lane of a cell walks all of its points)
+int cell_point_splits(int dA, int W, int precision) {
+    // lanes of a cell that split its points (the wide 3-D kernels and the
+    // float64 ones split the support instead: every lane of a cell walks
+    // all of its points)
+    if (precision == ANOVA_FP64) return 1;
     if (dA == 3) return W <= 6 ? 4 : 1;
     return dA == 2 ? 1 : 4;
 }

@@ -527,7 +527,7 @@ std::vector<Choice> candidates(const anova_params &prm, double D, int dA, double
     };
     const int T = cell_tile(dA);
     auto per_cell_likely = [&](const Choice &c, double span) {
-        return prec == ANOVA_FP32_NFFT && c.n >= 2 * T && cell_width_supported(dA, 2 * c.m) &&
+        return c.n >= 2 * T && cell_width_supported(dA, 2 * c.m, prec) &&
                (double)N >= 3.0 * std::pow(std::max(span, 1.0), dA);
     };
     auto cost = [&](const Choice &c, double eff) {
@@ -536,12 +536,13 @@ std::vector<Choice> candidates(const anova_params &prm, double D, int dA, double
     };
     // lane efficiency of the spreading and gathering kernels: per cell, a
     // lane's points of one cell against the fixed work of a workgroup (about
-    // four points' worth, as in best_chunks); float32 per point, bound by
-    // int64 LDS atomics, a quarter (float64 candidates are all per point)
+    // four points' worth, as in best_chunks); per point, bound by int64 LDS
+    // atomics, a quarter in float32 and 0.4 in float64 (as measured against
+    // the per-cell kernels of each precision)
     auto eff_of = [&](const Choice &c, double span) {
-        if (!per_cell_likely(c, span)) return prec == ANOVA_FP32_NFFT ? 0.25 : 1.0;
+        if (!per_cell_likely(c, span)) return prec == ANOVA_FP32_NFFT ? 0.25 : 0.4;
         const double steps = (double)N / std::pow(std::max(span, 1.0), dA) /
-                             cell_point_splits(dA, 2 * c.m);
+                             cell_point_splits(dA, 2 * c.m, prec);
         return steps / (steps + 4.0);
     };
     std::vector<Choice> out;
@@ -582,8 +583,8 @@ std::vector<Choice> candidates(const anova_params &prm, double D, int dA, double
                         const int64_t maxcnt = (int64_t)std::ceil(avg + 3.0 * std::sqrt(avg));
                         const int64_t tiles = (int64_t)std::pow((double)tiles_dim, dA) * share;
                         double t = 0.0;
-                        best_chunks(tiles, maxcnt, cell_point_splits(dA, 2 * x.m),
-                                    cell_resident_blocks(dA, 2 * x.m), t);
+                        best_chunks(tiles, maxcnt, cell_point_splits(dA, 2 * x.m, prec),
+                                    cell_resident_blocks(dA, 2 * x.m, prec), t);
                         return t * std::pow(2.0 * x.m, dA);
                     };
                     const bool better = launch_time(a, k1 - 1, n * D / h1) < launch_time(c, tp, span);
@@ -658,40 +659,53 @@ void build_fold_lists(const std::vector<int32_t> &src_tiles, int dA, int n, int 
 }
 
 template <typename T, typename Node>
-void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int prec) {
+void build_window(WindowPlan &w, const Points &X, int prec) {
     const int dA = w.dA, n = w.n, m = w.m;
+    const int64_t N = X.N, ldx = X.ld;
+    const double *Xh = X.host;
     // binning: cell index and fractional offset per point and dimension, from
-    // t = n (x - c) / h + n/2 in float64 (periodic on [0, n))
-    std::vector<int32_t> cellc((size_t)N * 3, 0);
-    std::vector<T> frac((size_t)N * 3, T(0));
-    const double scale = (double)n / w.h;
+    // t = n (x - c) / h + n/2 in float64 (periodic on [0, n)); hist counts
+    // the points of each grid cell (cell index x fastest).  Device points
+    // are binned by the device, which keeps the per-point results.
     size_t ncells = 1;
     for (int t = 0; t < dA; ++t) ncells *= (size_t)n;
-    std::vector<char> occupied(ncells, 0);
-    for (int64_t i = 0; i < N; ++i) {
-        size_t lin = 0, mul = 1;
-        for (int t = 0; t < dA; ++t) {
-            double tt = (Xh[(size_t)i * ldx + w.feat[t]] - w.center[t]) * scale + 0.5 * n;
-            tt -= n * std::floor(tt / n);
-            const double cf = std::floor(tt);
-            int cell = (int)cf;
-            const double f = tt - cf;
-            if (cell >= n) cell -= n;
-            if (cell < 0) cell += n;
-            frac[(size_t)i * 3 + t] = static_cast<T>(f);
-            cellc[(size_t)i * 3 + t] = cell;
-            lin += (size_t)cell * mul;
-            mul *= (size_t)n;
+    std::vector<int32_t> hist;
+    std::vector<int32_t> cellc;
+    std::vector<T> frac;
+    DeviceBins db;
+    if (X.dev) {
+        device_bin<T>(X.dev, N, ldx, w, db, hist, X.s);
+    } else {
+        cellc.assign((size_t)N * 3, 0);
+        frac.assign((size_t)N * 3, T(0));
+        hist.assign(ncells, 0);
+        const double scale = (double)n / w.h;
+        for (int64_t i = 0; i < N; ++i) {
+            size_t lin = 0, mul = 1;
+            for (int t = 0; t < dA; ++t) {
+                double tt = (Xh[(size_t)i * ldx + w.feat[t]] - w.center[t]) * scale + 0.5 * n;
+                tt -= n * std::floor(tt / n);
+                const double cf = std::floor(tt);
+                int cell = (int)cf;
+                const double f = tt - cf;
+                if (cell >= n) cell -= n;
+                if (cell < 0) cell += n;
+                frac[(size_t)i * 3 + t] = static_cast<T>(f);
+                cellc[(size_t)i * 3 + t] = cell;
+                lin += (size_t)cell * mul;
+                mul *= (size_t)n;
+            }
+            ++hist[lin];
         }
-        occupied[lin] = 1;
     }
     size_t nocc = 0;
-    for (char o : occupied) nocc += o;
-    // dense regime: float32, small support and several points per occupied
-    // cell -> per-cell register accumulation with a fixed small tile
+    for (int32_t c : hist) nocc += c > 0 ? 1 : 0;
+    // dense regime: small support (float32; float64 in 3-D up to W = 6) and
+    // several points per occupied cell -> per-cell register accumulation
+    // with a fixed small tile
     const int W = 2 * m;
     const int dense_tile = dA == 3 ? 4 : (dA == 2 ? 16 : 64);
-    const bool dense_ok = prec == ANOVA_FP32_NFFT && n >= dense_tile && cell_width_supported(dA, W);
+    const bool dense_ok = n >= dense_tile && cell_width_supported(dA, W, prec);
     w.dense = dense_ok && (double)N >= 3.0 * (double)std::max<size_t>(nocc, 1);
     // tile edge: power of two dividing n whose region (tile + 2m - 1)^dA of
     // 64-bit spreading accumulators fits in 64 KB of LDS
@@ -702,6 +716,7 @@ void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int p
         return std::pow(L, dA) * 8.0;
     };
     while (tile > 2 && region(tile) > 65536.0) tile /= 2;
+    while (w.tile_cap > 0 && tile > 2 && tile > w.tile_cap) tile /= 2;
     if (w.dense) tile = dense_tile;
     w.tile = tile;
     w.tiles_per_dim = n / tile;
@@ -710,40 +725,56 @@ void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int p
     w.n_tiles = ntiles;
     int64_t cells_per_tile = 1;
     for (int t = 0; t < dA; ++t) cells_per_tile *= tile;
-    // sort key: tile, then cell inside the tile (x fastest)
-    std::vector<uint32_t> cellw(N);
-    std::vector<int32_t> key(N);
-    for (int64_t i = 0; i < N; ++i) {
-        uint32_t packed = 0;
+    // sort key: tile, then cell inside the tile (x fastest); per-point
+    // kernels keep the caller's order inside a tile (points of one cell in
+    // one wave collide on the same LDS addresses)
+    auto key_of = [&](const int *cell) {
         int64_t tk = 0, lk = 0, mul = 1, lmul = 1;
         for (int t = 0; t < dA; ++t) {
-            const int cell = cellc[(size_t)i * 3 + t];
-            packed |= (uint32_t)cell << (10 * t);
-            tk += (int64_t)(cell / tile) * mul;
-            lk += (int64_t)(cell % tile) * lmul;
+            tk += (int64_t)(cell[t] / tile) * mul;
+            lk += (int64_t)(cell[t] % tile) * lmul;
             mul *= w.tiles_per_dim;
             lmul *= tile;
         }
-        cellw[i] = packed;
-        // per-point kernels keep the caller's order inside a tile (points of
-        // one cell in one wave collide on the same LDS addresses)
-        key[i] = (int32_t)(w.dense ? tk * cells_per_tile + lk : tk * cells_per_tile);
-    }
-    // stable counting sort by key
+        return w.dense ? tk * cells_per_tile + lk : tk * cells_per_tile;
+    };
+    // first sorted position of each key, from the points per cell
     const int64_t nkeys = ntiles * cells_per_tile;
     std::vector<int64_t> kstart(nkeys + 1, 0);
-    for (int64_t i = 0; i < N; ++i) kstart[key[i] + 1]++;
+    for (size_t lin = 0; lin < ncells; ++lin) {
+        if (hist[lin] == 0) continue;
+        int cell[3] = {0, 0, 0};
+        size_t r = lin;
+        for (int t = 0; t < dA; ++t) {
+            cell[t] = (int)(r % (size_t)n);
+            r /= (size_t)n;
+        }
+        kstart[key_of(cell) + 1] += hist[lin];
+    }
     for (int64_t k = 0; k < nkeys; ++k) kstart[k + 1] += kstart[k];
-    std::vector<int64_t> fill(kstart.begin(), kstart.end() - 1);
-    std::vector<int32_t> perm(N);
-    for (int64_t i = 0; i < N; ++i) perm[fill[key[i]]++] = (int32_t)i;
-    std::vector<Node> nodes(N);
-    for (int64_t j = 0; j < N; ++j) {
-        const int32_t i = perm[j];
-        Node nd{};
-        for (int t = 0; t < 3; ++t) nd.f[t] = frac[(size_t)i * 3 + t];
-        nd.cell = cellw[i];
-        nodes[j] = nd;
+    // stable sort by key (ties by the caller's index)
+    if (X.dev) {
+        device_sort_nodes<T, Node>(w, N, cells_per_tile, w.dense, db, X.s);
+        w.nodes = std::move(db.nodes);
+        w.perm = std::move(db.perm);
+    } else {
+        std::vector<int64_t> fill(kstart.begin(), kstart.end() - 1);
+        std::vector<int32_t> perm(N);
+        for (int64_t i = 0; i < N; ++i) perm[fill[key_of(&cellc[(size_t)i * 3])]++] = (int32_t)i;
+        std::vector<Node> nodes(N);
+        for (int64_t j = 0; j < N; ++j) {
+            const int32_t i = perm[j];
+            Node nd{};
+            uint32_t packed = 0;
+            for (int t = 0; t < 3; ++t) {
+                nd.f[t] = frac[(size_t)i * 3 + t];
+                if (t < dA) packed |= (uint32_t)cellc[(size_t)i * 3 + t] << (10 * t);
+            }
+            nd.cell = packed;
+            nodes[j] = nd;
+        }
+        upload(w.nodes, nodes);
+        upload(w.perm, perm);
     }
     std::vector<int64_t> start(ntiles + 1);
     for (int64_t t = 0; t <= ntiles; ++t) start[t] = kstart[t * cells_per_tile];
@@ -780,7 +811,8 @@ void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int p
         for (int64_t k = 0; k < nkeys; ++k) maxcnt = std::max(maxcnt, kstart[k + 1] - kstart[k]);
         double model_time = 0.0;
         const int K = best_chunks((int64_t)ne.size() * std::max(1, w.launch_windows), maxcnt,
-                                  cell_point_splits(dA, 2 * m), cell_resident_blocks(dA, 2 * m),
+                                  cell_point_splits(dA, 2 * m, prec),
+                                  cell_resident_blocks(dA, 2 * m, prec),
                                   model_time);
         std::vector<int32_t> cstart(ne.size() + 1);
         for (size_t k = 0; k <= ne.size(); ++k) cstart[k] = (int32_t)(k * K);
@@ -801,8 +833,6 @@ void build_window(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int p
     w.n_nonempty = nonempty;
     w.n_sub = (int64_t)subs.size();
     w.n_regions = w.dense ? (int64_t)w.chunk_start.back() : w.n_sub;
-    upload(w.nodes, nodes);
-    upload(w.perm, perm);
     upload(w.subs, subs);
     // per non-empty tile: its sub-problems, and the fold lists over tiles
     {
@@ -1032,11 +1062,11 @@ static void apply_choice(WindowPlan &w, const Choice &c, const anova_params &prm
     w.reg_q = prm.reg_q;
 }
 
-static void build_for(WindowPlan &w, const double *Xh, int64_t N, int64_t ldx, int prec) {
+static void build_for(WindowPlan &w, const Points &X, int prec) {
     if (prec == ANOVA_FP64)
-        build_window<double, NodeF64>(w, Xh, N, ldx, prec);
+        build_window<double, NodeF64>(w, X, prec);
     else
-        build_window<float, NodeF32>(w, Xh, N, ldx, prec);
+        build_window<float, NodeF32>(w, X, prec);
 }
 
 // Device time of one product of a one-window plan (the best of 3 after a
@@ -1087,25 +1117,45 @@ static double time_window(anova_plan_s &one, const double *alpha, double *out, i
     return best;
 }
 
-// Plan from validated arguments and host points Xh (rows ldx apart); with
-// targets Zh (Nz rows ldz apart) also a prediction plan, whose periods and
-// centres are chosen for both point sets together.
-static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, int32_t d,
-                              int64_t ldx, const anova_window *win, int32_t P,
-                              const anova_params *prm, const double *Zh = nullptr,
-                              int64_t Nz = 0, int64_t ldz = 0) {
+// Minimum and maximum of each of the d features of the points, which must
+// all be finite (`what` names them in the error).
+static void feature_bounds(const Points &X, int d, std::vector<double> &lo,
+                           std::vector<double> &hi, const char *what) {
+    lo.assign(d, 0.0);
+    hi.assign(d, 0.0);
+    if (X.dev) {
+        bool finite = true;
+        device_bounds(X.dev, X.N, X.ld, d, lo.data(), hi.data(), finite, X.s);
+        ANOVA_REQUIRE(finite, std::string(what) + " holds a non-finite value");
+        return;
+    }
+    for (int t = 0; t < d; ++t) lo[t] = hi[t] = X.host[t];
+    for (size_t i = 0; i < (size_t)X.N; ++i)
+        for (int t = 0; t < d; ++t) {
+            const double v = X.host[i * X.ld + t];
+            ANOVA_REQUIRE(std::isfinite(v), std::string(what) + " holds a non-finite value");
+            lo[t] = std::min(lo[t], v);
+            hi[t] = std::max(hi[t], v);
+        }
+}
+
+// Plan from validated arguments and the points X (host or device); with
+// targets Z (Z.N > 0) also a prediction plan, whose periods and centres are
+// chosen for both point sets together.
+static anova_status make_plan(anova_plan_t *out, const Points &X, int32_t d,
+                              const anova_window *win, int32_t P, const anova_params *prm,
+                              const Points &Z = Points{}) {
     anova_plan_s *p = nullptr;
+    const int64_t N = X.N;
+    const bool targets = Z.N > 0;
     anova_status st = guarded([&] {
-        for (size_t i = 0; i < (size_t)N; ++i)
-            for (int t = 0; t < d; ++t)
-                ANOVA_REQUIRE(std::isfinite(Xh[i * ldx + t]), "X holds a non-finite value");
-        for (size_t i = 0; i < (size_t)Nz; ++i)
-            for (int t = 0; t < d; ++t)
-                ANOVA_REQUIRE(std::isfinite(Zh[i * ldz + t]), "Z holds a non-finite value");
+        std::vector<double> xlo, xhi, zlo, zhi;
+        feature_bounds(X, d, xlo, xhi, "X");
+        if (targets) feature_bounds(Z, d, zlo, zhi, "Z");
         p = new anova_plan_s();
         ANOVA_HIP_CHECK(hipGetDevice(&p->device));
         p->N = N; p->d = d; p->P = P; p->precision = prm->precision; p->ell = prm->ell;
-        p->Nz = Zh ? Nz : 0;
+        p->Nz = targets ? Z.N : 0;
         p->win.resize(P);
         double eta_abs = 0.0;
         for (int l = 0; l < P; ++l) eta_abs += std::fabs(win[l].eta);
@@ -1121,19 +1171,14 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
             double D = 0.0, lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
             for (int t = 0; t < w.dA; ++t) {
                 w.feat[t] = win[l].feat[t];
-                lo[t] = hi[t] = Xh[w.feat[t]];
-                for (int64_t i = 1; i < N; ++i) {
-                    const double v = Xh[(size_t)i * ldx + w.feat[t]];
-                    lo[t] = std::min(lo[t], v);
-                    hi[t] = std::max(hi[t], v);
-                }
+                lo[t] = xlo[w.feat[t]];
+                hi[t] = xhi[w.feat[t]];
                 // targets: every difference z - x enters the periodised
                 // kernel, so the box holds both sets (Sec. 4.2 scales both
                 // into the same torus)
-                for (int64_t i = 0; Zh && i < Nz; ++i) {
-                    const double v = Zh[(size_t)i * ldz + w.feat[t]];
-                    lo[t] = std::min(lo[t], v);
-                    hi[t] = std::max(hi[t], v);
+                if (targets) {
+                    lo[t] = std::min(lo[t], zlo[w.feat[t]]);
+                    hi[t] = std::max(hi[t], zhi[w.feat[t]]);
                 }
                 D = std::max(D, hi[t] - lo[t]);
             }
@@ -1149,7 +1194,7 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
             if (prm->tune == 0 || cands.size() == 1) {
                 set_centers(w, cands.front(), lo, hi, *prm);
                 apply_choice(w, cands.front(), *prm);
-                build_for(w, Xh, N, ldx, prm->precision);
+                build_for(w, X, prm->precision);
                 continue;
             }
             // measured choice: build the cheapest candidates (model cost
@@ -1160,25 +1205,35 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
                 upload(tune_alpha, std::vector<double>((size_t)N, 1.0));
                 tune_out.alloc((size_t)N * (size_t)P * sizeof(double));
             }
+            // (per-point windows: also with tiles of half the edge, whose
+            // regions hold fewer halo points per point but add fold work)
             double best_t = std::numeric_limits<double>::infinity();
             for (size_t k = 0; k < cands.size() && k < 4; ++k) {
                 if (cands[k].cost > 8.0 * cands.front().cost) break;
-                anova_plan_s one;
-                one.N = N; one.d = d; one.P = 1; one.precision = prm->precision;
-                one.ell = prm->ell; one.device = p->device;
-                one.win.resize(1);
-                WindowPlan &v = one.win[0];
-                v.dA = w.dA; v.eta = w.eta; v.extent = w.extent;
-                v.launch_windows = w.launch_windows;  // chunks as in the full plan
-                for (int t = 0; t < 3; ++t) v.feat[t] = w.feat[t];
-                set_centers(v, cands[k], lo, hi, *prm);
-                apply_choice(v, cands[k], *prm);
-                build_for(v, Xh, N, ldx, prm->precision);
-                const double t =
-                    time_window(one, tune_alpha.as<double>(), tune_out.as<double>(), P);
-                if (t < best_t) {
-                    best_t = t;
-                    w = std::move(v);
+                int cap = 0;
+                for (int variant = 0; variant < 2; ++variant) {
+                    anova_plan_s one;
+                    one.N = N; one.d = d; one.P = 1; one.precision = prm->precision;
+                    one.ell = prm->ell; one.device = p->device;
+                    one.win.resize(1);
+                    WindowPlan &v = one.win[0];
+                    v.dA = w.dA; v.eta = w.eta; v.extent = w.extent;
+                    v.launch_windows = w.launch_windows;  // chunks as in the full plan
+                    v.tile_cap = cap;
+                    for (int t = 0; t < 3; ++t) v.feat[t] = w.feat[t];
+                    set_centers(v, cands[k], lo, hi, *prm);
+                    apply_choice(v, cands[k], *prm);
+                    build_for(v, X, prm->precision);
+                    const double t =
+                        time_window(one, tune_alpha.as<double>(), tune_out.as<double>(), P);
+                    const bool halve = !v.dense && v.tile > 2;
+                    const int tile = v.tile;
+                    if (t < best_t) {
+                        best_t = t;
+                        w = std::move(v);
+                    }
+                    if (!halve) break;
+                    cap = tile / 2;
                 }
             }
         }
@@ -1191,10 +1246,10 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
                 v.dA = w.dA; v.eta = w.eta; v.ell = w.ell; v.h = w.h; v.extent = w.extent;
                 v.M = w.M; v.n = w.n; v.m = w.m; v.kb_b = w.kb_b; v.reg_q = w.reg_q;
                 for (int t = 0; t < 3; ++t) { v.feat[t] = w.feat[t]; v.center[t] = w.center[t]; }
-                build_window<double, NodeF64>(v, Xh, N, ldx, ANOVA_FP64);
+                build_window<double, NodeF64>(v, X, ANOVA_FP64);
             }
         }
-        if (Zh) {
+        if (targets) {
             // the targets binned on the same grids, in the plan's precision
             p->tgt.resize(P);
             for (int l = 0; l < P; ++l) {
@@ -1207,7 +1262,7 @@ static anova_status make_plan(anova_plan_t *out, const double *Xh, int64_t N, in
                 v.err_window = w.err_window; v.err_round = w.err_round;
                 v.err_total = w.err_total;
                 for (int t = 0; t < 3; ++t) { v.feat[t] = w.feat[t]; v.center[t] = w.center[t]; }
-                build_for(v, Zh, Nz, ldz, prm->precision);
+                build_for(v, Z, prm->precision);
             }
         }
         if (prm->target_err > 0) {
@@ -1236,19 +1291,15 @@ extern "C" anova_status anova_fastsum_plan(anova_plan_t *out, const double *X, i
         return ANOVA_E_INVALID;
     }
     *out = nullptr;
-    std::vector<double> Xh;
-    const anova_status st = guarded([&] {
-        validate(X, N, d, ldx, win, P, prm);
-        hipStream_t s = (hipStream_t)stream;
-        ANOVA_HIP_CHECK(hipStreamSynchronize(s));
-        // rows are ldx apart; the last row ends after its d entries
-        const size_t cnt = (size_t)(N - 1) * ldx + d;
-        Xh.resize(cnt);
-        std::lock_guard<std::recursive_mutex> lock(device_mutex());
-        ANOVA_HIP_CHECK(hipMemcpy(Xh.data(), X, cnt * sizeof(double), hipMemcpyDeviceToHost));
-    });
+    const anova_status st = guarded([&] { validate(X, N, d, ldx, win, P, prm); });
     if (st != ANOVA_OK) return st;
-    return make_plan(out, Xh.data(), N, d, ldx, win, P, prm);
+    // the points stay on the device: bounds, binning and sorting run there
+    Points pts;
+    pts.dev = X;
+    pts.N = N;
+    pts.ld = ldx;
+    pts.s = (hipStream_t)stream;
+    return make_plan(out, pts, d, win, P, prm);
 }
 
 extern "C" anova_status anova_fastsum_plan_host(anova_plan_t *out, const double *X, int64_t N,
@@ -1261,7 +1312,11 @@ extern "C" anova_status anova_fastsum_plan_host(anova_plan_t *out, const double 
     *out = nullptr;
     const anova_status st = guarded([&] { validate(X, N, d, ldx, win, P, prm); });
     if (st != ANOVA_OK) return st;
-    return make_plan(out, X, N, d, ldx, win, P, prm);
+    Points pts;
+    pts.host = X;
+    pts.N = N;
+    pts.ld = ldx;
+    return make_plan(out, pts, d, win, P, prm);
 }
 
 static void validate_targets(const double *Z, int64_t Nz, int32_t d, int64_t ldz) {
@@ -1279,21 +1334,15 @@ extern "C" anova_status anova_predict_plan(anova_plan_t *out, const double *X, i
         return ANOVA_E_INVALID;
     }
     *out = nullptr;
-    std::vector<double> Xh, Zh;
     const anova_status st = guarded([&] {
         validate(X, N, d, ldx, win, P, prm);
         validate_targets(Z, Nz, d, ldz);
-        hipStream_t s = (hipStream_t)stream;
-        ANOVA_HIP_CHECK(hipStreamSynchronize(s));
-        const size_t cx = (size_t)(N - 1) * ldx + d, cz = (size_t)(Nz - 1) * ldz + d;
-        Xh.resize(cx);
-        Zh.resize(cz);
-        std::lock_guard<std::recursive_mutex> lock(device_mutex());
-        ANOVA_HIP_CHECK(hipMemcpy(Xh.data(), X, cx * sizeof(double), hipMemcpyDeviceToHost));
-        ANOVA_HIP_CHECK(hipMemcpy(Zh.data(), Z, cz * sizeof(double), hipMemcpyDeviceToHost));
     });
     if (st != ANOVA_OK) return st;
-    return make_plan(out, Xh.data(), N, d, ldx, win, P, prm, Zh.data(), Nz, ldz);
+    Points px, pz;
+    px.dev = X; px.N = N; px.ld = ldx; px.s = (hipStream_t)stream;
+    pz.dev = Z; pz.N = Nz; pz.ld = ldz; pz.s = (hipStream_t)stream;
+    return make_plan(out, px, d, win, P, prm, pz);
 }
 
 extern "C" anova_status anova_predict_plan_host(anova_plan_t *out, const double *X, int64_t N,
@@ -1310,7 +1359,10 @@ extern "C" anova_status anova_predict_plan_host(anova_plan_t *out, const double 
         validate_targets(Z, Nz, d, ldz);
     });
     if (st != ANOVA_OK) return st;
-    return make_plan(out, X, N, d, ldx, win, P, prm, Z, Nz, ldz);
+    Points px, pz;
+    px.host = X; px.N = N; px.ld = ldx;
+    pz.host = Z; pz.N = Nz; pz.ld = ldz;
+    return make_plan(out, px, d, win, P, prm, pz);
 }
 
 extern "C" anova_status anova_predict(anova_plan_t p, const double *alpha, double *out,

@@ -29,6 +29,7 @@ from __future__ import annotations
 
 import collections
 import math
+import threading
 import time
 from dataclasses import dataclass
 from typing import Any, Callable, Deque, Dict, List, Optional, Sequence
@@ -379,9 +380,9 @@ class Server:
 
 class HipExecutor:
     """Device work of the server through the C ABI: plan, CG state, batched
-    iterations.  Iterations run on one stream; plans are built from the host
-    points (possibly on planner threads, overlapping the iterations already
-    launched)."""
+    iterations.  Iterations run on one stream; plans are built on the device
+    from an upload of the request's points, each planner thread on a stream
+    of its own (overlapping the iterations already launched)."""
 
     def __init__(self, precision: Optional[int] = None, target_err: float = 1e-4,
                  params: Optional[Dict[str, Any]] = None):
@@ -394,6 +395,7 @@ class HipExecutor:
         self.target_err = target_err
         self.params = dict(params or {})
         self.stream = torch.cuda.Stream()
+        self._planner = threading.local()  # per planner thread: its stream
 
     def estimate(self, req: Request) -> int:
         return estimate_bytes(req.N, len(req.windows), req.nrhs,
@@ -406,11 +408,17 @@ class HipExecutor:
                               4 if self.precision == self.A.ANOVA_FP32_NFFT else 8)
 
     def plan(self, req: Request):
-        """Build the plan from the host points (any thread); returns
-        (state, exact device bytes)."""
-        A = self.A
+        """Build the plan (any thread): the points go to the device and are
+        binned and sorted there; returns (state, exact device bytes)."""
+        torch, A = self.torch, self.A
         prm = A.make_params(req.ell, self.precision, target_err=self.target_err, **self.params)
-        plan = A.anova_fastsum_plan_host(req.X, req.windows, prm)
+        s = getattr(self._planner, "stream", None)
+        if s is None:
+            s = self._planner.stream = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            X = torch.from_numpy(np.ascontiguousarray(req.X, dtype=np.float64)).to("cuda")
+        plan = A.anova_fastsum_plan(X, req.windows, prm, stream=s)  # synchronises s
+        del X
         pb, sb = plan.footprint(req.nrhs)
         io = 2 * req.N * req.nrhs * 8  # y and alpha
         return {"plan": plan, "req": req, "solve": None}, pb + sb + io

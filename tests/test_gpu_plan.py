@@ -1,0 +1,85 @@
+"""The plan built on the device (bounds, binning and the stable sort of the
+points by grid tile and cell run in HIP kernels, Sec. 4.2's scaled nodes)
+against the plan built from host memory: the same parameters, tiles and
+work items, and products and CG solves equal bit for bit.  Also the
+device path's refusal of non-finite points.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from tests.gpu_util import dev_cols, dev_rows, empty_cols, to_np
+
+pytestmark = pytest.mark.gpu
+
+F32, F64 = 1, 0
+
+
+@pytest.fixture(scope="module")
+def A():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2111_10140_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def _matvec(A, plan, a, beta):
+    import torch
+    out = empty_cols(a.shape[0])
+    A.anova_matvec(plan, dev_cols(a), out, beta)
+    torch.cuda.synchronize()
+    return to_np(out)
+
+
+def _same_plans(dev, host):
+    assert dev.P == host.P
+    for l in range(dev.P):
+        a, b = dev.info(l), host.info(l)
+        assert (a.M, a.n, a.m, a.h, a.center, a.per_cell, a.tile, a.n_tiles, a.n_subproblems) == \
+               (b.M, b.n, b.m, b.h, b.center, b.per_cell, b.tile, b.n_tiles, b.n_subproblems), l
+
+
+@pytest.mark.parametrize("case", [
+    ("mixed windows, per-point and per-cell", F32,
+     lambda: workloads.random_problem(7001, 6, [(0, 1, 2), (3, 4), (5,)], 0.2, seed=41), {}),
+    ("3-D per-cell, tile-aligned", F32, lambda: workloads.feature_grouped(200_003, seed=42), {}),
+    ("float64 per-point", F64, lambda: workloads.feature_grouped(20_001, seed=43), {}),
+    ("wide per-cell (m = 6)", F32, lambda: workloads.feature_grouped(100_000, seed=44),
+     dict(M=64, m=6, n=128)),
+    ("one point", F32, lambda: workloads.random_problem(1, 3, [(0, 1, 2)], 0.2, seed=45), {}),
+], ids=lambda c: c[0] if isinstance(c, tuple) else str(c))
+def test_device_plan_equals_host_plan(A, case):
+    import torch
+    name, precision, make, kw = case
+    p = make()
+    print(f"plan case {name}: N={p.N} precision={precision}", flush=True)
+    prm = A.make_params(p.ell, precision, **kw)
+    dev = A.anova_fastsum_plan(dev_rows(p.X), p.windows, prm)
+    host = A.anova_fastsum_plan_host(p.X, p.windows, prm)
+    _same_plans(dev, host)
+    a = p.alpha[:, 0]
+    assert np.array_equal(_matvec(A, dev, a, p.beta), _matvec(A, host, a, p.beta))
+    if p.N > 1:
+        # the solve also uses a float32 plan's float64 residual windows
+        y = dev_cols(p.y[:, 0])
+        xs = []
+        for plan in (dev, host):
+            x = empty_cols(p.N)
+            A.krr_cg_solve(plan, y, x, p.beta, 1e-6, 3000, allow_not_converged=True)
+            torch.cuda.synchronize()
+            xs.append(to_np(x))
+        assert np.array_equal(xs[0], xs[1])
+    dev.destroy()
+    host.destroy()
+
+
+def test_device_plan_rejects_non_finite_points(A):
+    p = workloads.random_problem(5000, 3, [(0, 1, 2)], 0.2, seed=46)
+    for bad in (np.nan, np.inf, -np.inf):
+        X = p.X.copy()
+        X[4321, 1] = bad
+        with pytest.raises(A.AnovaError) as ei:
+            A.anova_fastsum_plan(dev_rows(X), p.windows, A.make_params(p.ell, F32))
+        assert ei.value.status == A.ANOVA_E_INVALID
+        assert "non-finite" in str(ei.value)

@@ -109,3 +109,28 @@ def test_footprint_matches_device_memory(A):
     assert 0.8 * (pb + sb) - (4 << 20) <= used <= 1.25 * (pb + sb) + (16 << 20)
     sv.destroy()
     plan.destroy()
+
+
+def test_full_size_served_request_against_oracle(A):
+    # one request at the serving stream's largest size (N = 5e5, nine
+    # features in three windows, two columns) through the server; its
+    # residual y - (K + beta I) alpha with the oracle's exact operator on 256
+    # sampled rows.  K~ differs from K by at most the per-entry target
+    # (1e-4) per unit of ||alpha||_1, and CG leaves ||r|| <= tol ||y||.
+    from paper_2111_10140_amd.serve import HipExecutor, Server
+    p = workloads.random_problem(500_000, 9, [(0, 1, 2), (3, 4, 5), (6, 7, 8)], 0.25, nrhs=2,
+                                 seed=74)
+    ex = HipExecutor(F32, target_err=1e-4)
+    srv = Server(ex, budget=8 << 30)
+    h = srv.submit(p.X, p.windows, p.ell, p.beta, p.y, tol=1e-6, maxit=4000)
+    srv.run_until_idle()
+    res = srv.result(h)
+    assert res.status == "OK", (res.status, res.error)
+    a = res.alpha.reshape(p.N, p.nrhs)
+    rows = np.random.default_rng(3).choice(p.N, 256, replace=False)
+    Ka = oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a, rows=rows)
+    r = np.abs(p.y[rows] - Ka).max(axis=0)
+    bound = 1e-4 * np.abs(a).sum(axis=0) + 1e-6 * np.linalg.norm(p.y, axis=0)
+    print(f"served N=5e5: sampled residual {r}, bound {bound}")
+    assert np.all(r <= bound)
+    srv.close()

@@ -163,3 +163,61 @@ def test_stage_gather_matches_ndft(A, precision, N, d, M, n, m, h, per_cell):
     tol = kb_bound(m, n / M) + (3e-6 if precision == F32 else 1e-13)
     print(f"gather d={d} M={M} n={n} m={m} prec={precision}: err {err:.3e} (gate {tol:.2e})")
     assert err <= tol
+
+
+def direct_window_weights(X, h, n, m):
+    """Per point and axis the grid indices u = floor(t) - m + 1 + a (mod n)
+    and the window weights phi0(t - u) / phi0(0), a = 0 .. 2m-1, with
+    t = n (x / h) + n / 2 (grid point u sits at torus position u/n - 1/2):
+    the window sums of the spread and gather steps written out (Sec. 4.1)."""
+    b = oracle.fastsum.kb_beta(m, 2.0)
+    w0 = oracle.fastsum.kb_window(np.array([0.0]), m, b)[0]
+    t = n * (X / h) + n / 2.0
+    base = np.floor(t).astype(np.int64) - m + 1
+    offs = np.arange(2 * m)
+    u = base[:, :, None] + offs[None, None, :]            # (N, d, 2m)
+    w = oracle.fastsum.kb_window(t[:, :, None] - u, m, b) / w0
+    return u % n, w
+
+
+@pytest.mark.parametrize("m", [2, 3])
+def test_fp64_per_cell_stages_match_direct_window_sums(A, m):
+    # float64 per-cell kernels (3-D, W = 2m <= 6, many points per cell):
+    # the spread grid and the interpolated values against the window sums
+    # evaluated point by point in float64
+    import torch
+    N, M, n, h = 20000, 16, 32, 1.0
+    p = workloads.random_problem(N, 3, [(0, 1, 2)], 0.2, seed=60 + m, eta=[1.0])
+    plan = A.anova_fastsum_plan(dev_rows(p.X), p.windows,
+                                A.make_params(p.ell, F64, M=M, n=n, m=m, h=h, center=1))
+    assert plan.info(0).per_cell == 1
+    u, w = direct_window_weights(p.X, h, n, m)
+    a = p.alpha[:, 0]
+    # spread: grid[u3, u2, u1] = sum_j a_j w1 w2 w3
+    g = A.grid_tensor(plan, 0)
+    A.anova_stage_spread(plan, 0, dev_cols(a), g)
+    torch.cuda.synchronize()
+    got = to_np(g)
+    ref = np.zeros((n, n, n))
+    for i1 in range(2 * m):
+        for i2 in range(2 * m):
+            for i3 in range(2 * m):
+                np.add.at(ref, (u[:, 2, i3], u[:, 1, i2], u[:, 0, i1]),
+                          a * w[:, 0, i1] * w[:, 1, i2] * w[:, 2, i3])
+    err_s = np.max(np.abs(got - ref)) / np.abs(ref).max()
+    # gather: out_i = sum_u grid[u] w1 w2 w3 on an arbitrary grid
+    G = np.random.default_rng(70 + m).standard_normal((n, n, n))
+    g.copy_(torch.from_numpy(G))
+    out = dev_cols(np.zeros(N))
+    A.anova_stage_gather(plan, 0, g, out)
+    torch.cuda.synchronize()
+    got_g = to_np(out)
+    ref_g = np.zeros(N)
+    for i1 in range(2 * m):
+        for i2 in range(2 * m):
+            for i3 in range(2 * m):
+                ref_g += G[u[:, 2, i3], u[:, 1, i2], u[:, 0, i1]] * \
+                    w[:, 0, i1] * w[:, 1, i2] * w[:, 2, i3]
+    err_g = np.max(np.abs(got_g - ref_g)) / np.abs(G).max()
+    print(f"float64 per-cell m={m}: spread {err_s:.2e}, gather {err_g:.2e}")
+    assert err_s <= 1e-12 and err_g <= 1e-12
