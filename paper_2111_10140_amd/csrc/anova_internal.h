@@ -127,6 +127,11 @@ struct CombineWin {
 template <typename T> struct PolyDeg;
 template <> struct PolyDeg<float> { static constexpr int value = 8; };
 template <> struct PolyDeg<double> { static constexpr int value = 15; };
+// Degree of the float64 per-cell kernels' polynomials (3-D, W <= 6): those
+// windows' own aliasing error is above 1e-8, and degree 11 fits to below
+// 2e-10 of the maximum for m = 2, 3 and oversampling 1.25..4, with fewer
+// scalar registers than degree 15 (the coefficients stay uniform).
+constexpr int kPolyDegCell64 = 11;
 
 // ---------------------------------------------------------------- window plan
 struct WindowPlan {

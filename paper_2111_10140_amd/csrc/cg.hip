@@ -338,8 +338,9 @@ struct StepGraph {
     Batch pq, xq;  // q = A p, q = A x over every solve in the list
     hipStream_t cap = nullptr;
     // one iteration, one with residual recomputation, kGraphIters
-    // iterations without
+    // iterations without; each captured when first needed
     hipGraphExec_t g_plain = nullptr, g_replace = nullptr, g_block = nullptr;
+    int64_t uses = 0;  // krr_cg_iterate calls on this list
     ~StepGraph() {
         if (g_plain) (void)hipGraphExecDestroy(g_plain);
         if (g_replace) (void)hipGraphExecDestroy(g_replace);
@@ -393,6 +394,18 @@ static hipGraphExec_t capture(StepGraph &G, bool replace, int iters = 1) {
     return ex;
 }
 
+// The graph of one iteration (replace: with residual recomputation) or of
+// kGraphIters iterations (block), captured on first use.
+static hipGraphExec_t graph_for(StepGraph &G, bool replace, bool block) {
+    hipGraphExec_t &g = block ? G.g_block : (replace ? G.g_replace : G.g_plain);
+    if (!g) {
+        // capturing must not overlap other threads' allocations
+        std::lock_guard<std::recursive_mutex> dev_lock(device_mutex());
+        g = capture(G, replace, block ? kGraphIters : 1);
+    }
+    return g;
+}
+
 static BatchProblem product(anova_cg_s *sv, const double *in, bool residual) {
     BatchProblem bp;
     bp.residual = residual;
@@ -440,9 +453,6 @@ static StepGraph &step_graph(anova_cg_s *const *solves, int count) {
     G->pq.build(pq_probs);
     G->xq.build(xq_probs);
     ANOVA_HIP_CHECK(hipStreamCreateWithFlags(&G->cap, hipStreamNonBlocking));
-    G->g_plain = capture(*G, false);
-    G->g_replace = capture(*G, true);
-    G->g_block = capture(*G, false, kGraphIters);
     if (g_steps.size() >= kStepCache) g_steps.erase(g_steps.begin());
     g_steps.push_back(std::move(G));
     return *g_steps.back();
@@ -576,6 +586,10 @@ extern "C" anova_status krr_cg_iterate(anova_cg_t *solves, int32_t count, int32_
         std::lock_guard<std::mutex> lock(g_step_mu);
         StepGraph &G = step_graph(solves, count);
         hipStream_t s = (hipStream_t)stream;
+        // a list's first call launches its iterations directly: the lists
+        // of a serving loop change as requests join and leave, and one
+        // used once would not repay the captures
+        const bool direct = G.uses++ == 0;
         for (int k = 0; k < iters;) {
             // the next kGraphIters iterations in one launch when no solve
             // recomputes its residual in them
@@ -584,7 +598,10 @@ extern "C" anova_status krr_cg_iterate(anova_cg_t *solves, int32_t count, int32_
                 for (int j = 1; j <= kGraphIters; ++j)
                     block = block && (solves[i]->it + j) % solves[i]->period != 0;
             if (block) {
-                ANOVA_HIP_CHECK(hipGraphLaunch(G.g_block, s));
+                if (direct)
+                    for (int j = 0; j < kGraphIters; ++j) record_iteration(G, false, s);
+                else
+                    ANOVA_HIP_CHECK(hipGraphLaunch(graph_for(G, false, true), s));
                 for (int i = 0; i < count; ++i) solves[i]->it += kGraphIters;
                 k += kGraphIters;
                 continue;
@@ -592,7 +609,10 @@ extern "C" anova_status krr_cg_iterate(anova_cg_t *solves, int32_t count, int32_
             bool rep = false;
             for (int i = 0; i < count; ++i)
                 rep = rep || (solves[i]->it + 1) % solves[i]->period == 0;
-            ANOVA_HIP_CHECK(hipGraphLaunch(rep ? G.g_replace : G.g_plain, s));
+            if (direct)
+                record_iteration(G, rep, s);
+            else
+                ANOVA_HIP_CHECK(hipGraphLaunch(graph_for(G, rep, false), s));
             for (int i = 0; i < count; ++i) ++solves[i]->it;
             ++k;
         }

@@ -102,9 +102,9 @@ __device__ __forceinline__ void window_weights(const T *__restrict__ poly, T f, 
 // only the lower half is held, and split into its even and odd parts in z,
 // p(z) = E(z^2) + z O(z^2), it gives both weights of the pair (a, W-1-a),
 // E + zO and E - zO, for about half the multiply-adds of two evaluations.
-template <typename T, int W>
+template <typename T, int W, int DEG = PolyDeg<T>::value>
 struct WinPoly {
-    static constexpr int D = PolyDeg<T>::value, H = W / 2;
+    static constexpr int D = DEG, H = W / 2;
     static_assert(W % 2 == 0, "supports of 2m points");
     T c[H][D + 1];
     __device__ __forceinline__ void load(const T *__restrict__ poly) {
@@ -641,7 +641,7 @@ __global__ __launch_bounds__(kBlock, 2) void spread_cell64_kernel(const WinInst 
     const NodeF64 *__restrict__ nodes = static_cast<const NodeF64 *>(wi.nodes);
     const int32_t *__restrict__ perm = wi.perm;
     const double *__restrict__ alpha = wi.alpha;
-    WinPoly<double, W> wp;
+    WinPoly<double, W, kPolyDegCell64> wp;
     wp.load(static_cast<const double *>(wi.poly));
     int tk, chunk, K;
     locate_chunk(wi.src_sub, wi.n_nonempty, loc.lb, tk, chunk, K);
@@ -764,7 +764,7 @@ __global__ __launch_bounds__(kBlock, 2) void gather_cell64_kernel(const WinInst 
     const NodeF64 *__restrict__ nodes = static_cast<const NodeF64 *>(wi.nodes);
     const double *__restrict__ grid = static_cast<const double *>(wi.grid);
     double *__restrict__ tmp = static_cast<double *>(wi.tmp);
-    WinPoly<double, W> wp;
+    WinPoly<double, W, kPolyDegCell64> wp;
     wp.load(static_cast<const double *>(wi.poly));
     const int n = wi.n, tpd = wi.tpd;
     int tk, chunk, K;
@@ -803,9 +803,13 @@ __global__ __launch_bounds__(kBlock, 2) void gather_cell64_kernel(const WinInst 
     for (int j = pb; j < pe; ++j) {
         const NodeF64 nd = nx;
         if (j + 1 < pe) nx = nodes[j + 1];
-        double wx[W];
+        double wx[W], wy[H], wz[H];
         wp.eval(nd.f[0], wx);
         const double zy = 2.0 * nd.f[1] - 1.0, zz = 2.0 * nd.f[2] - 1.0;
+#pragma unroll
+        for (int b = 0; b < H; ++b) wy[b] = wp.at(sy ? -zy : zy, b);
+#pragma unroll
+        for (int c = 0; c < H; ++c) wz[c] = wp.at(sz ? -zz : zz, c);
         double part = 0.0;
 #pragma unroll
         for (int c = 0; c < H; ++c) {
@@ -815,9 +819,9 @@ __global__ __launch_bounds__(kBlock, 2) void gather_cell64_kernel(const WinInst 
                 double sr = 0.0;
 #pragma unroll
                 for (int i = 0; i < W; ++i) sr = fma(g[c][b][i], wx[i], sr);
-                sc = fma(sr, wp.at(sy ? -zy : zy, b), sc);
+                sc = fma(sr, wy[b], sc);
             }
-            part = fma(sc, wp.at(sz ? -zz : zz, c), part);
+            part = fma(sc, wz[c], part);
         }
         const double v = quad_sum_f64(part);
         if (sub == 0) tmp[perm[j]] = v;  // caller order

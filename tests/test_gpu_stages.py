@@ -184,7 +184,10 @@ def direct_window_weights(X, h, n, m):
 def test_fp64_per_cell_stages_match_direct_window_sums(A, m):
     # float64 per-cell kernels (3-D, W = 2m <= 6, many points per cell):
     # the spread grid and the interpolated values against the window sums
-    # evaluated point by point in float64
+    # evaluated point by point in float64.  The kernels' window polynomials
+    # (degree 11) fit the window to about 2e-10 of its maximum, three
+    # factors per weight: 1e-9 relative leaves room for that and nothing
+    # else (a wrong offset, plane or lane sum is an O(1) error)
     import torch
     N, M, n, h = 20000, 16, 32, 1.0
     p = workloads.random_problem(N, 3, [(0, 1, 2)], 0.2, seed=60 + m, eta=[1.0])
@@ -220,4 +223,4 @@ def test_fp64_per_cell_stages_match_direct_window_sums(A, m):
                     w[:, 0, i1] * w[:, 1, i2] * w[:, 2, i3]
     err_g = np.max(np.abs(got_g - ref_g)) / np.abs(G).max()
     print(f"float64 per-cell m={m}: spread {err_s:.2e}, gather {err_g:.2e}")
-    assert err_s <= 1e-12 and err_g <= 1e-12
+    assert err_s <= 1e-9 and err_g <= 1e-9

@@ -148,11 +148,13 @@ def test_shift_is_exact():
 
 
 def test_golden_figure_gaussian_value():
-    # The fast-summation figure marks the Gaussian at r = -L and r = L with
-    # value 0.2821 (4 digits).  With L = 0.75 and sigma = 2/3 the oracle's
-    # exp(-r^2/sigma^2) reproduces that printed value; the period implied by
-    # the ticks is h = 2 * (h/2) = 2.5 and the other marked points are the
-    # images -L + h and L + h.
+    # Consistency of the periodisation figure's printed ticks, not an
+    # independent pin of the oracle: the figure marks the Gaussian at r = -L
+    # and r = L with value 0.2821 (4 digits) but does not print its width;
+    # sigma = 2/3 is the width that gives 0.2821 at L = 0.75, so the value
+    # check only confirms the kernel convention exp(-r^2/sigma^2) (no factor
+    # 1/2, which would give 0.5311).  The ticks fix the period h = 2 (h/2) =
+    # 2.5, and the other marked points are the images -L + h and L + h.
     import json
     import os
     fx = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fastsum_figure.json")))
@@ -166,6 +168,8 @@ def test_golden_figure_gaussian_value():
         rr = (r + h / 2) % h - h / 2
         assert abs(abs(rr) - L) < 1e-12
         assert round(K[0, 1], 4) == val and round(K[0, 2], 4) == val
+    # the convention with a factor 1/2 does not reproduce the printed value
+    assert round(float(np.exp(-L ** 2 / (2 * (2.0 / 3.0) ** 2))), 4) != fx["marked_points"][0][1]
 
 
 # ---------------------------------------------------------------- prediction
