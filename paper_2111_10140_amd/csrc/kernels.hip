@@ -853,7 +853,7 @@ __global__ __launch_bounds__(kBlock, 2) void gather_cell64_kernel(const WinInst 
 template <int W> struct WideSplit;
 // NPS / NPG: z passes of the spreading / gathering kernel
 template <> struct WideSplit<8> { static constexpr int SX = 2, SY = 2, SZ = 1, NPS = 1, NPG = 1; };
-template <> struct WideSplit<12> { static constexpr int SX = 2, SY = 2, SZ = 2, NPS = 1, NPG = 2; };
+template <> struct WideSplit<12> { static constexpr int SX = 2, SY = 2, SZ = 2, NPS = 2, NPG = 2; };
 constexpr int kWideTile = 4, kWideCells = 64, kWideThreads = 128;
 
 template <int W>
@@ -926,6 +926,46 @@ __device__ __forceinline__ void wide_cells(const WinInst &wi, int key0, int chun
     __syncthreads();
 }
 
+// Window weights of one point staged in LDS for the lanes of its cell
+// (gathering): per axis the lower-half polynomials at z (lo, offsets
+// a < W/2) and at -z (hi, offset W-1-a), from one even/odd evaluation each,
+// then the point's caller index.  Each lane evaluates the weights of the
+// point it loaded, so a point's polynomials are evaluated once instead of
+// once per lane of the cell; a lane then reads the halves of each axis it
+// owns.  (The spreading kernel keeps evaluating its own: there the staged
+// weights' LDS and registers cost more occupancy than they save.)
+template <int W>
+struct WideStage {
+    static constexpr int H = W / 2;
+    static constexpr int STRIDE = 6 * H + 2;  // floats per point (even: float2 access)
+    __device__ __forceinline__ static void put(const WinPoly<float, W> &hp, float4 p, float *st) {
+        const float zs[3] = {2.0f * p.x - 1.0f, 2.0f * p.y - 1.0f, 2.0f * p.z - 1.0f};
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const float z = zs[t], z2 = z * z;
+            float lo[H], hi[H];
+#pragma unroll
+            for (int a = 0; a < H; ++a) hp.pair(z, z2, a, lo[a], hi[a]);
+#pragma unroll
+            for (int a = 0; a < H; a += 2) {
+                *reinterpret_cast<float2 *>(st + 2 * H * t + a) = make_float2(lo[a], lo[a + 1]);
+                *reinterpret_cast<float2 *>(st + 2 * H * t + H + a) = make_float2(hi[a], hi[a + 1]);
+            }
+        }
+        *reinterpret_cast<float2 *>(st + 6 * H) = make_float2(p.w, 0.0f);
+    }
+    // H weights of axis t, half s (0: lo, 1: hi)
+    __device__ __forceinline__ static void half(const float *st, int t, int s, float (&w)[H]) {
+        const float *src = st + 2 * H * t + (s ? H : 0);
+#pragma unroll
+        for (int a = 0; a < H; a += 2) {
+            const float2 v = *reinterpret_cast<const float2 *>(src + a);
+            w[a] = v.x;
+            w[a + 1] = v.y;
+        }
+    }
+};
+
 // A lane's block of the support (sx, sy, sz) and, for group g, its cell.
 template <int W>
 struct WideLane {
@@ -946,7 +986,7 @@ struct WideLane {
 };
 
 template <int W>
-__global__ __launch_bounds__(kWideThreads, 2) void spread_wide_kernel(
+__global__ __launch_bounds__(kWideThreads, WideSplit<W>::NPS == 2 ? 3 : 2) void spread_wide_kernel(
     const WinInst *__restrict__ insts, const int32_t *__restrict__ members,
     const int32_t *__restrict__ prefix, int cnt) {
     using SP = WideSplit<W>;
@@ -1121,8 +1161,10 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
     constexpr int WX = AX::NA, WY = AY::NA, PZ = AZ::NA / SP::NPG;
     constexpr int T = kWideTile, L = T + W - 1, L2 = L * L, VOL = L2 * L;
     constexpr int m = W / 2;
+    using ST = WideStage<W>;
+    constexpr int H = ST::H;
     __shared__ float g_lds[VOL];
-    __shared__ float4 stage[NT];
+    __shared__ __align__(16) float wst[NT * ST::STRIDE];
     __shared__ WideCells cs;
     const Located loc = locate(insts, members, prefix, cnt);
     const WinInst &wi = *loc.w;
@@ -1148,7 +1190,8 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
     wide_cells(wi, tile_id * kWideCells, chunk, K, cs);  // its barriers also order the fill
     const WideLane<W> ln;
     const bool lead = ln.sub == 0;
-    float4 *stg = stage + (threadIdx.x - ln.sub);
+    const float *cst = wst + (threadIdx.x - ln.sub) * ST::STRIDE;  // the cell's points
+    float *myst = wst + threadIdx.x * ST::STRIDE;
 #pragma unroll 1
     for (int g = 0; g < NG; ++g) {
         const int cell = cs.order[ln.slot(g)];
@@ -1177,7 +1220,7 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
                 nx = make_float4(r.x, r.y, r.z, __int_as_float(perm[jl]));
             }
             for (int q0 = pb; q0 < pe; q0 += TPC) {
-                stg[ln.sub] = nx;
+                ST::put(hp, nx, myst);
                 jl += TPC;
                 if (jl < pe) {
                     const float3 r = node_offsets(nodes + jl);
@@ -1185,14 +1228,14 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
                 }
                 const int kn = min(TPC, pe - q0);
                 for (int k = 0; k < kn; ++k) {
-                    const float4 p = stg[k];
-                    float *dst = tmp + __float_as_int(p.w);
+                    const float *ps = cst + k * ST::STRIDE;
+                    float *dst = tmp + __float_as_int(ps[6 * H]);
                     // a later pass adds to what the same lane wrote in the pass before
                     const float prev = pass > 0 && lead ? *dst : 0.0f;
+                    static_assert(SP::SX == 2 && SP::SY == 2, "x and y split in halves");
                     float wx[WX], wy[WY];
-                    AX::weights(hp, 2.0f * p.x - 1.0f, ln.sx, wx);
-                    AY::weights(hp, 2.0f * p.y - 1.0f, ln.sy, wy);
-                    const float zz = 2.0f * p.z - 1.0f;
+                    ST::half(ps, 0, ln.sx, wx);
+                    ST::half(ps, 1, ln.sy, wy);
                     float part = 0.0f;
                     auto plane = [&](int c) {
                         float sc = 0.0f;
@@ -1207,18 +1250,20 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
                     };
                     if constexpr (SP::SZ == 1 && SP::NPG == 1) {
                         // the whole z axis: planes in mirror pairs
-                        const float zz2 = zz * zz;
+                        float zlo[H], zhi[H];
+                        ST::half(ps, 2, 0, zlo);
+                        ST::half(ps, 2, 1, zhi);
 #pragma unroll
                         for (int c2 = 0; c2 < W / 2; ++c2) {
-                            float wlo, whi;
-                            hp.pair(zz, zz2, c2, wlo, whi);
-                            part = fmaf(plane(c2), wlo, part);
-                            part = fmaf(plane(W - 1 - c2), whi, part);
+                            part = fmaf(plane(c2), zlo[c2], part);
+                            part = fmaf(plane(W - 1 - c2), zhi[c2], part);
                         }
                     } else {
+                        static_assert(SP::SZ == 2, "z split in halves");
+                        float zh[H];
+                        ST::half(ps, 2, ln.sz, zh);
 #pragma unroll
-                        for (int c = 0; c < PZ; ++c)
-                            part = fmaf(plane(c), AZ::weight(hp, zz, ln.sz, pass * PZ + c), part);
+                        for (int c = 0; c < PZ; ++c) part = fmaf(plane(c), zh[pass * PZ + c], part);
                     }
                     const float v = cell_lanes_sum<TPC>(part);
                     if (lead) *dst = prev + v;  // caller order
