@@ -242,7 +242,6 @@ struct WinInst {
     const void *twiddle;
     const double *alpha;        // input column, caller's order
     void *priv;                 // spread regions
-    void *treg;                 // per-tile region sums
     void *grid;                 // n^dA grid
     void *tmp;                  // sorted coefficients (per-point spread), then
                                 // interpolated values in the caller's order
@@ -285,16 +284,15 @@ struct CombInst {
     CgHook hook;  // partial == nullptr: a plain product
 };
 
-// Stage identifiers; the first five are the reported timing kinds.
+// Stage identifiers, also the reported timing kinds.
 enum StageKind {
     kStagePermute = 0,
     kStageSpread = 1,
-    kStageTileSum = 2,
-    kStageFold = 3,
-    kStageConvolve = 4,
-    kStageGather = 5,
-    kStageCombine = 6,
-    kStageKinds = 7
+    kStageFold = 2,
+    kStageConvolve = 3,
+    kStageGather = 4,
+    kStageCombine = 5,
+    kStageKinds = 6
 };
 
 // A launch: all instances of one stage sharing a kernel signature.

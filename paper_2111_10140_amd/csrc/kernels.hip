@@ -488,31 +488,32 @@ __global__ __launch_bounds__(kBlock) void spread_cell_kernel(const WinInst *__re
     }
     __syncthreads();
     // region point (X, Y, Z) gets cell (dx, dy, dz)'s value at offset
-    // (X - dx, Y - dy, Z - dz) when that offset lies in [0, W)
+    // (X - dx, Y - dy, Z - dz), for the cells with every offset in [0, W):
+    // per dimension a run dx = max(0, X-W+1) .. min(TILE-1, X), added in
+    // increasing dz, dy, dx; along a run the staged index moves by a fixed
+    // stride (next cell, offset one lower)
     float *out = static_cast<float *>(wi.priv) + (size_t)loc.lb * VOL;
-    constexpr int KX = TILE < W ? TILE : W;  // loop over the shorter range
+    constexpr int KX = TILE < W ? TILE : W;  // longest run
     for (int e = threadIdx.x; e < VOL; e += kBlock) {
         const int X = e % L;
         const int Y = DA >= 2 ? (e / L) % L : 0;
         const int Z = DA == 3 ? e / L2 : 0;
+        const int x0 = max(0, X - (W - 1)), nx = min(TILE - 1, X) - x0 + 1;
+        const int y0 = DA >= 2 ? max(0, Y - (W - 1)) : 0;
+        const int y1 = DA >= 2 ? min(TILE - 1, Y) : 0;
+        const int z0 = DA == 3 ? max(0, Z - (W - 1)) : 0;
+        const int z1 = DA == 3 ? min(TILE - 1, Z) : 0;
         float sum = 0.0f;
 #pragma unroll 1
-        for (int kz = 0; kz < (DA == 3 ? KX : 1); ++kz) {
-            const int dz = DA == 3 ? (TILE <= W ? kz : Z - kz) : 0;
-            const int oz = Z - dz;
-            if (DA == 3 && (dz < 0 || dz >= TILE || oz < 0 || oz >= W)) continue;
-            for (int ky = 0; ky < (DA >= 2 ? KX : 1); ++ky) {
-                const int dy = DA >= 2 ? (TILE <= W ? ky : Y - ky) : 0;
-                const int oy = Y - dy;
-                if (DA >= 2 && (dy < 0 || dy >= TILE || oy < 0 || oy >= W)) continue;
+        for (int dz = z0; dz <= z1; ++dz) {
+#pragma unroll 1
+            for (int dy = y0; dy <= y1; ++dy) {
+                const float *src = stage +
+                                   ((dz * (DA >= 2 ? TILE : 1) + dy) * TILE + x0) * VW +
+                                   ((Z - dz) * WY + (Y - dy)) * W + (X - x0);
 #pragma unroll
-                for (int kx = 0; kx < KX; ++kx) {
-                    const int dx = TILE <= W ? kx : X - kx;
-                    const int ox = X - dx;
-                    if (dx < 0 || dx >= TILE || ox < 0 || ox >= W) continue;
-                    const int cidx = (dz * (DA >= 2 ? TILE : 1) + dy) * TILE + dx;
-                    sum += stage[cidx * VW + (oz * WY + oy) * W + ox];
-                }
+                for (int k = 0; k < KX; ++k)
+                    if (k < nx) sum += src[k * (VW - 1)];
             }
         }
         out[e] = sum;
@@ -985,20 +986,64 @@ struct WideLane {
     }
 };
 
+// x and y window weights of one point staged in LDS for the lanes of its
+// cell (spreading): per axis the lower-half polynomials at z and at -z
+// (offsets a and W-1-a), from one even/odd evaluation each, the x weights
+// already multiplied by the point's (scaled) coefficient.  A lane reads the
+// halves it owns; z weights, of which a lane needs only its z pass's
+// planes, stay with each lane.  Float offsets: x lo, x hi, y lo, y hi.
 template <int W>
-__global__ __launch_bounds__(kWideThreads, WideSplit<W>::NPS == 2 ? 3 : 2) void spread_wide_kernel(
+struct WideSpreadStage {
+    static constexpr int H = W / 2;
+    static constexpr int STRIDE = 4 * H;  // floats per point
+    __device__ __forceinline__ static void put(const WinPoly<float, W> &hp, float4 p, float *st) {
+        const float zs[2] = {2.0f * p.x - 1.0f, 2.0f * p.y - 1.0f};
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const float z = zs[t], z2 = z * z;
+            float lo[H], hi[H];
+#pragma unroll
+            for (int a = 0; a < H; ++a) {
+                hp.pair(z, z2, a, lo[a], hi[a]);
+                if (t == 0) {
+                    lo[a] *= p.w;
+                    hi[a] *= p.w;
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < H; a += 2) {
+                *reinterpret_cast<float2 *>(st + 2 * H * t + a) = make_float2(lo[a], lo[a + 1]);
+                *reinterpret_cast<float2 *>(st + 2 * H * t + H + a) = make_float2(hi[a], hi[a + 1]);
+            }
+        }
+    }
+    // H weights of axis t (0: x, 1: y), half s (0: lo, 1: hi)
+    __device__ __forceinline__ static void half(const float *st, int t, int s, float (&w)[H]) {
+        const float *src = st + 2 * H * t + (s ? H : 0);
+#pragma unroll
+        for (int a = 0; a < H; a += 2) {
+            const float2 v = *reinterpret_cast<const float2 *>(src + a);
+            w[a] = v.x;
+            w[a + 1] = v.y;
+        }
+    }
+};
+
+template <int W>
+__global__ __launch_bounds__(kWideThreads, 2) void spread_wide_kernel(
     const WinInst *__restrict__ insts, const int32_t *__restrict__ members,
     const int32_t *__restrict__ prefix, int cnt) {
     using SP = WideSplit<W>;
-    using AX = WideAxis<W, SP::SX>;
-    using AY = WideAxis<W, SP::SY>;
     using AZ = WideAxis<W, SP::SZ>;
+    using ST = WideSpreadStage<W>;
+    static_assert(SP::SX == 2 && SP::SY == 2, "x and y split in halves");
     constexpr int NT = kWideThreads, TPC = wide_lanes<W>();
     constexpr int NG = kWideCells / wide_group_cells<W>();
-    constexpr int WX = AX::NA, WY = AY::NA, PZ = AZ::NA / SP::NPS;
+    constexpr int H = W / 2, PZ = AZ::NA / SP::NPS;
     constexpr int T = kWideTile, L = T + W - 1, VOL = L * L * L;
     __shared__ unsigned long long acc_lds[VOL];
-    __shared__ float4 stage[NT];
+    __shared__ __align__(16) float stage_xy[NT * ST::STRIDE];
+    __shared__ float stage_z[NT];
     __shared__ WideCells cs;
     __shared__ float red[NT / 64];
     const Located loc = locate(insts, members, prefix, cnt);
@@ -1015,7 +1060,7 @@ __global__ __launch_bounds__(kWideThreads, WideSplit<W>::NPS == 2 ? 3 : 2) void 
     wide_cells(wi, key0, chunk, K, cs);  // its barriers also order the zero fill
     // the scale, from the largest |coefficient| over the tile's points (a
     // superset of the chunk's) and the largest count of one cell: every
-    // register sum of a cell then rounds below 2^30 (weights are at most 1),
+    // register sum of a cell then stays below 2^30 (weights are at most 1),
     // and an int64 region value adds at most one such sum per lane
     float amax = 0.0f;
     {
@@ -1041,7 +1086,9 @@ __global__ __launch_bounds__(kWideThreads, WideSplit<W>::NPS == 2 ? 3 : 2) void 
     (void)frexpf(fmaxf((float)cs.cnt[cs.order[0]], 1.0f), &ct);
     const int Sx = 30 - ex2 - ct;
     const WideLane<W> ln;
-    float4 *stg = stage + (threadIdx.x - ln.sub);
+    // this cell's staging slots: lane s of the cell stages point s of a round
+    float *sxy = stage_xy + (threadIdx.x - ln.sub) * ST::STRIDE;
+    float *sz = stage_z + (threadIdx.x - ln.sub);
 #pragma unroll 1
     for (int g = 0; g < NG; ++g) {
         const int cell = cs.order[ln.slot(g)];
@@ -1050,37 +1097,42 @@ __global__ __launch_bounds__(kWideThreads, WideSplit<W>::NPS == 2 ? 3 : 2) void 
         const int lx = cell % T, ly = (cell / T) % T, lz = cell / (T * T);
 #pragma unroll  // constant pass: the polynomial index stays static
         for (int pass = 0; pass < SP::NPS; ++pass) {
-            float acc[PZ][WY][WX];
+            float acc[PZ][H][H];
 #pragma unroll
             for (int c = 0; c < PZ; ++c)
 #pragma unroll
-                for (int b = 0; b < WY; ++b)
+                for (int b = 0; b < H; ++b)
 #pragma unroll
-                    for (int i = 0; i < WX; ++i) acc[c][b][i] = 0.0f;
-            // the cell's points go through LDS in rounds of TPC, lane s of
-            // the cell loading point s of the next round while the cell works
-            // through the current one; the lanes of a cell share a wave,
-            // whose LDS accesses complete in order
+                    for (int i = 0; i < H; ++i) acc[c][b][i] = 0.0f;
+            // the cell's points go through LDS in rounds of TPC: lane s of
+            // the cell stages the weights of point s of the round while the
+            // next round's point loads, then every lane of the cell works
+            // through the round's points; the lanes of a cell share a wave,
+            // whose LDS accesses complete in order.  Coefficients carry the
+            // fixed-point scale 2^Sx, so the sums are the region's integers
+            // before truncation.
             float4 nx = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
             int jl = pb + ln.sub;
             if (jl < pe) {
                 const float3 r = node_offsets(nodes + jl);
-                nx = make_float4(r.x, r.y, r.z, (float)alpha[perm[jl]]);
+                nx = make_float4(r.x, r.y, r.z, ldexpf((float)alpha[perm[jl]], Sx));
             }
             for (int q0 = pb; q0 < pe; q0 += TPC) {
-                stg[ln.sub] = nx;
+                if (jl < pe) {
+                    ST::put(hp, nx, sxy + ln.sub * ST::STRIDE);
+                    sz[ln.sub] = 2.0f * nx.z - 1.0f;
+                }
                 jl += TPC;
                 if (jl < pe) {
                     const float3 r = node_offsets(nodes + jl);
-                    nx = make_float4(r.x, r.y, r.z, (float)alpha[perm[jl]]);
+                    nx = make_float4(r.x, r.y, r.z, ldexpf((float)alpha[perm[jl]], Sx));
                 }
                 const int kn = min(TPC, pe - q0);
                 for (int k = 0; k < kn; ++k) {
-                    const float4 p = stg[k];
-                    float wx[WX], wy[WY];
-                    AX::weights(hp, 2.0f * p.x - 1.0f, ln.sx, wx);
-                    AY::weights(hp, 2.0f * p.y - 1.0f, ln.sy, wy);
-                    const float zz = 2.0f * p.z - 1.0f;
+                    float wx[H], wy[H];
+                    ST::half(sxy + k * ST::STRIDE, 0, ln.sx, wx);
+                    ST::half(sxy + k * ST::STRIDE, 1, ln.sy, wy);
+                    const float zz = sz[k];
                     if constexpr (SP::SZ == 1 && SP::NPS == 1) {
                         // the whole z axis: planes in mirror pairs
                         const float zz2 = zz * zz;
@@ -1091,12 +1143,12 @@ __global__ __launch_bounds__(kWideThreads, WideSplit<W>::NPS == 2 ? 3 : 2) void 
 #pragma unroll
                             for (int h = 0; h < 2; ++h) {
                                 const int c = h == 0 ? c2 : W - 1 - c2;
-                                const float wc = p.w * (h == 0 ? wlo : whi);
+                                const float wc = h == 0 ? wlo : whi;
 #pragma unroll
-                                for (int b = 0; b < WY; ++b) {
+                                for (int b = 0; b < H; ++b) {
                                     const float wbc = wc * wy[b];
 #pragma unroll
-                                    for (int i = 0; i < WX; ++i)
+                                    for (int i = 0; i < H; ++i)
                                         acc[c][b][i] = fmaf(wbc, wx[i], acc[c][b][i]);
                                 }
                             }
@@ -1104,31 +1156,31 @@ __global__ __launch_bounds__(kWideThreads, WideSplit<W>::NPS == 2 ? 3 : 2) void 
                     } else {
 #pragma unroll
                         for (int c = 0; c < PZ; ++c) {
-                            const float wc = p.w * AZ::weight(hp, zz, ln.sz, pass * PZ + c);
+                            const float wc = AZ::weight(hp, zz, ln.sz, pass * PZ + c);
 #pragma unroll
-                            for (int b = 0; b < WY; ++b) {
+                            for (int b = 0; b < H; ++b) {
                                 const float wbc = wc * wy[b];
 #pragma unroll
-                                for (int i = 0; i < WX; ++i)
+                                for (int i = 0; i < H; ++i)
                                     acc[c][b][i] = fmaf(wbc, wx[i], acc[c][b][i]);
                             }
                         }
                     }
                 }
             }
+            // register sums into the region: |sum| < 2^30, truncated to an
+            // integer (the x and y halves of a lane are mirrored for s = 1)
 #pragma unroll
             for (int c = 0; c < PZ; ++c) {
                 const int z = lz + AZ::offset(ln.sz, pass * PZ + c);
 #pragma unroll
-                for (int b = 0; b < WY; ++b) {
-                    unsigned long long *row = acc_lds + (z * L + ly + AY::offset(ln.sy, b)) * L + lx;
+                for (int b = 0; b < H; ++b) {
+                    const int y = ly + (ln.sy ? W - 1 - b : b);
+                    unsigned long long *row = acc_lds + (z * L + y) * L + lx;
 #pragma unroll
-                    for (int i = 0; i < WX; ++i) {
-                        const float v = acc[c][b][i];
-                        if (v != 0.0f)
-                            atomicAdd(&row[AX::offset(ln.sx, i)],
-                                      (unsigned long long)round_to_ll(ldexpf(v, Sx)));
-                    }
+                    for (int i = 0; i < H; ++i)
+                        atomicAdd(&row[ln.sx ? W - 1 - i : i],
+                                  (unsigned long long)(long long)(int)acc[c][b][i]);
                 }
             }
         }
@@ -1388,44 +1440,25 @@ __global__ __launch_bounds__(kBlock) void permute_kernel(const WinInst *__restri
     }
 }
 
-// ------------------------------------------------------------------ tile sum
-// Regions of the same tile (several sub-problems or chunks) are added
-// elementwise, in region order, into one region per non-empty tile:
-// src_sub[k] .. src_sub[k+1]-1 are the regions of the k-th non-empty tile.
-// Blocks: non-empty tiles x ceil(vol / kBlock).
-template <typename T>
-__global__ __launch_bounds__(kBlock) void tile_sum_kernel(const WinInst *__restrict__ insts,
-                                                          const int32_t *__restrict__ members,
-                                                          const int32_t *__restrict__ prefix,
-                                                          int cnt) {
-    const Located loc = locate(insts, members, prefix, cnt);
-    const WinInst &wi = *loc.w;
-    const int vol = wi.vol;
-    const int per = (vol + kBlock - 1) / kBlock;
-    const int k = loc.lb / per;
-    const int e = (loc.lb % per) * kBlock + threadIdx.x;
-    if (e >= vol) return;
-    const T *__restrict__ priv = static_cast<const T *>(wi.priv);
-    const int s0 = wi.src_sub[k], s1 = wi.src_sub[k + 1];
-    double s = 0.0;
-    for (int q = s0; q < s1; ++q) s += (double)priv[(size_t)q * vol + e];
-    static_cast<T *>(wi.treg)[(size_t)k * vol + e] = static_cast<T>(s);
-}
-
 // ------------------------------------------------------------------ fold
 // One workgroup per destination tile: every grid point of the tile is the
-// sum, in the fixed order of the plan's pair list, of the region values of
-// the non-empty tiles whose region covers it (regions wrap periodically: per
-// dimension the region indices of grid point o + c are the values in [0, L)
-// congruent to b + c mod n, b the tile origin's offset in the region).
-// Writes every grid point, so no zero fill is needed.
-constexpr int kFoldBatch = 8;  // region reads in flight per thread
+// sum, in the fixed order of the plan's pair list and, within a pair, of
+// the source tile's regions (its sub-problems or chunks), of the region
+// values that cover it (regions wrap periodically: per dimension the region
+// indices of grid point o + c are the values in [0, L) congruent to b + c
+// mod n, b the tile origin's offset in the region).  Writes every grid
+// point, so no zero fill is needed.
+constexpr int kFoldBatch = 16;  // region reads in flight per thread
 constexpr int kFoldZeroPasses = 4;  // zeroing workgroups: passes of the threads over tiles
+constexpr int kFoldPairsLds = 512;  // a tile's pair list staged in LDS up to this length
 
 // One workgroup per tile that receives regions, in the plan's order
 // (entries -1 are padding).  A small tile's cells get S threads each:
-// thread s of a cell adds regions s, s + S, s + 2S, ... of the tile's list,
-// and the S partial sums are then added in order of s.  The remaining
+// thread s of a cell adds pairs s, s + S, s + 2S, ... of the tile's list,
+// and the S partial sums are then added in order of s.  The tile's pair
+// list goes to LDS first (when it fits), each pair with its source tile's
+// first region and region count, so that a thread's region reads depend on
+// no other global load and go out kFoldBatch at a time.  The remaining
 // workgroups zero the tiles that receive no region, kFoldZeroPasses passes
 // of the threads over tiles each.
 template <typename T, int DA>
@@ -1434,10 +1467,10 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
                                                       const int32_t *__restrict__ prefix,
                                                       int cnt) {
     __shared__ double part[kBlock];
+    __shared__ int4 pairs_lds[kFoldPairsLds];  // {packed offsets, first region, regions, 0}
     const Located loc = locate(insts, members, prefix, cnt);
     const WinInst &wi = *loc.w;
-    const T *__restrict__ src =
-        static_cast<const T *>(wi.n_regions != wi.n_nonempty ? wi.treg : wi.priv);
+    const T *__restrict__ src = static_cast<const T *>(wi.priv);
     T *__restrict__ grid = static_cast<T *>(wi.grid);
     const int n = wi.n, tile = wi.tile, tpd = wi.tpd, vol = wi.vol;
     const int L = tile + wi.width - 1;
@@ -1467,7 +1500,22 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
     const int d = wi.fold_tiles[loc.lb];
     if (d < 0) return;  // padding (the whole workgroup)
     const int p0 = wi.fold_start[d], p1 = wi.fold_start[d + 1];
-    // sum over regions first, first + stride, ... of cell c
+    const bool staged = p1 - p0 <= kFoldPairsLds;
+    if (staged) {
+        for (int e = (int)threadIdx.x; e < p1 - p0; e += kBlock) {
+            const int2 pr = wi.fold_pairs[p0 + e];
+            const int q0 = wi.src_sub[pr.x], q1 = wi.src_sub[pr.x + 1];
+            pairs_lds[e] = make_int4(pr.y, q0, q1 - q0, 0);
+        }
+        __syncthreads();
+    }
+    auto pair_at = [&](int p) {
+        if (staged) return pairs_lds[p - p0];
+        const int2 pr = wi.fold_pairs[p];
+        const int q0 = wi.src_sub[pr.x];
+        return make_int4(pr.y, q0, wi.src_sub[pr.x + 1] - q0, 0);
+    };
+    // sum over the regions of pairs first, first + stride, ... of cell c
     auto cell_sum = [&](int c, int first, int stride) {
         const int cx = c % tile;
         const int cy = DA >= 2 ? (c / tile) % tile : 0;
@@ -1475,20 +1523,28 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
         double s = 0.0;
         if (L <= n) {
             // each region element lands on one grid point: at most one read
-            // per region; kFoldBatch regions' reads in flight, added in order
-            for (int p = first; p < p1; p += kFoldBatch * stride) {
+            // per region.  The thread walks its (pair, region) items in
+            // order, kFoldBatch reads in flight, added in order.
+            int p = first, q = 0;
+            int4 pr = p < p1 ? pair_at(p) : make_int4(0, 0, 0, 0);
+            while (p < p1) {
                 T v[kFoldBatch];
 #pragma unroll
                 for (int u = 0; u < kFoldBatch; ++u) {
                     v[u] = T(0);
-                    const int q = p + u * stride;
-                    if (q < p1) {
-                        const int2 pr = wi.fold_pairs[q];
-                        const int ex = (((pr.y & 1023) + cx) & (n - 1));
-                        const int ey = DA >= 2 ? ((((pr.y >> 10) & 1023) + cy) & (n - 1)) : 0;
-                        const int ez = DA == 3 ? ((((pr.y >> 20) & 1023) + cz) & (n - 1)) : 0;
-                        if (ex < L && ey < L && ez < L)
-                            v[u] = src[(size_t)pr.x * vol + ez * L2 + ey * L + ex];
+                    if (p < p1) {
+                        const int ex = (((pr.x & 1023) + cx) & (n - 1));
+                        const int ey = DA >= 2 ? ((((pr.x >> 10) & 1023) + cy) & (n - 1)) : 0;
+                        const int ez = DA == 3 ? ((((pr.x >> 20) & 1023) + cz) & (n - 1)) : 0;
+                        if (ex < L && ey < L && ez < L && q < pr.z)
+                            v[u] = src[(size_t)(pr.y + q) * vol + ez * L2 + ey * L + ex];
+                        // next item: the pair's next region, else the next pair
+                        // (a pair that misses this cell counts as one item)
+                        if (++q >= pr.z || !(ex < L && ey < L && ez < L)) {
+                            q = 0;
+                            p += stride;
+                            if (p < p1) pr = pair_at(p);
+                        }
                     }
                 }
 #pragma unroll
@@ -1496,15 +1552,17 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
             }
         } else {
             for (int p = first; p < p1; p += stride) {
-                const int2 pr = wi.fold_pairs[p];
-                const T *reg = src + (size_t)pr.x * vol;
-                const int bx = pr.y & 1023, by = (pr.y >> 10) & 1023, bz = (pr.y >> 20) & 1023;
+                const int4 pr = pair_at(p);
+                const int bx = pr.x & 1023, by = (pr.x >> 10) & 1023, bz = (pr.x >> 20) & 1023;
                 const int ex0 = (bx + cx) & (n - 1);
                 const int ey0 = DA >= 2 ? (by + cy) & (n - 1) : 0;
                 const int ez0 = DA == 3 ? (bz + cz) & (n - 1) : 0;
-                for (int ez = ez0; ez < (DA == 3 ? L : 1); ez += n)
-                    for (int ey = ey0; ey < (DA >= 2 ? L : 1); ey += n)
-                        for (int ex = ex0; ex < L; ex += n) s += (double)reg[ez * L2 + ey * L + ex];
+                for (int q = 0; q < pr.z; ++q) {
+                    const T *reg = src + (size_t)(pr.y + q) * vol;
+                    for (int ez = ez0; ez < (DA == 3 ? L : 1); ez += n)
+                        for (int ey = ey0; ey < (DA >= 2 ? L : 1); ey += n)
+                            for (int ex = ex0; ex < L; ex += n) s += (double)reg[ez * L2 + ey * L + ex];
+                }
             }
         }
         return s;
@@ -1538,14 +1596,29 @@ __device__ __forceinline__ typename Cplx<T>::type *filter_lines(typename Cplx<T>
                                                                 const typename Cplx<T>::type *__restrict__ tw) {
     using C = typename Cplx<T>::type;
     constexpr int n = 1 << LOGN;
-    // forward transform, X_k = sum_u x_u exp(-2 pi i k u / n)
-    for (int Ns = 1; Ns < n; Ns <<= 1) {
-        for (int e = threadIdx.x; e < NP * (n / 2); e += blockDim.x) {
+    // with n/2 dividing the workgroup size a thread keeps one butterfly
+    // column j = threadIdx.x mod n/2 in every stage: its LOGN twiddles and
+    // its multiplier values are loaded once, into registers
+    constexpr bool kFixedColumn = (n / 2) <= kBlock;
+    C twr[kFixedColumn ? LOGN : 1];
+    if constexpr (kFixedColumn) {
+        const int j = (int)threadIdx.x & (n / 2 - 1);
+#pragma unroll
+        for (int st = 0; st < LOGN; ++st) twr[st] = tw[(j & ((1 << st) - 1)) << (LOGN - 1 - st)];
+    }
+    // butterflies of stage st (sub-transform length Ns = 2^st); inverse:
+    // conjugate twiddles
+    auto stage = [&](int st, bool inverse) {
+        const int Ns = 1 << st;
+        for (int e = threadIdx.x; e < NP * (n / 2); e += kBlock) {
             const int ql = e >> (LOGN - 1), j = e & (n / 2 - 1);
             const int k = j & (Ns - 1);
             const C a = src[ql * n + j];
             const C b0 = src[ql * n + j + n / 2];
-            const C w = tw[k * (n / (2 * Ns))];
+            C w;
+            if constexpr (kFixedColumn) w = twr[st];
+            else w = tw[k * (n / (2 * Ns))];
+            if (inverse) w.y = -w.y;
             C b;
             b.x = b0.x * w.x - b0.y * w.y;
             b.y = b0.x * w.y + b0.y * w.x;
@@ -1555,32 +1628,20 @@ __device__ __forceinline__ typename Cplx<T>::type *filter_lines(typename Cplx<T>
         }
         __syncthreads();
         C *t = src; src = dst; dst = t;
-    }
-    for (int e = threadIdx.x; e < NP * n; e += blockDim.x) {
+    };
+    // forward transform, X_k = sum_u x_u exp(-2 pi i k u / n)
+#pragma unroll
+    for (int st = 0; st < LOGN; ++st) stage(st, false);
+    for (int e = threadIdx.x; e < NP * n; e += kBlock) {
         const T f = bconv[e & (n - 1)];
         C v = src[e];
         v.x *= f; v.y *= f;
         src[e] = v;
     }
     __syncthreads();
-    // inverse transform (conjugate twiddles, no 1/n: folded into the multiplier)
-    for (int Ns = 1; Ns < n; Ns <<= 1) {
-        for (int e = threadIdx.x; e < NP * (n / 2); e += blockDim.x) {
-            const int ql = e >> (LOGN - 1), j = e & (n / 2 - 1);
-            const int k = j & (Ns - 1);
-            const C a = src[ql * n + j];
-            const C b0 = src[ql * n + j + n / 2];
-            const C w = tw[k * (n / (2 * Ns))];
-            C b;
-            b.x = b0.x * w.x + b0.y * w.y;
-            b.y = b0.y * w.x - b0.x * w.y;
-            const int idx = ((j - k) << 1) + k;
-            dst[ql * n + idx] = C{a.x + b.x, a.y + b.y};
-            dst[ql * n + idx + Ns] = C{a.x - b.x, a.y - b.y};
-        }
-        __syncthreads();
-        C *t = src; src = dst; dst = t;
-    }
+    // inverse transform (no 1/n: folded into the multiplier)
+#pragma unroll
+    for (int st = 0; st < LOGN; ++st) stage(st, true);
     return src;
 }
 
@@ -1996,10 +2057,6 @@ void run_group(const BatchGroup &g, int precision, const WinInst *insts, hipStre
             break;
         case kStageSpread:
             if (f64) spread_group<double>(g, insts, s); else spread_group<float>(g, insts, s);
-            break;
-        case kStageTileSum:
-            if (f64) launch_k(tile_sum_kernel<double>, g, 0, insts, s);
-            else launch_k(tile_sum_kernel<float>, g, 0, insts, s);
             break;
         case kStageFold:
             if (f64) fold_group<double>(g, insts, s); else fold_group<float>(g, insts, s);
