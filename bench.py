@@ -88,8 +88,8 @@ def alg_bytes(stage: str, N: int, G: int, elem: int, P: int = 3, per_cell: bool 
               permutation index 4 B and float64 coefficient 8 B; per-point:
               node record (16 B f32 / 32 B f64) + sorted coefficient; one
               write of each grid value;
-    fold    : one write of each grid value (the tile regions it reads are
-              traffic of this implementation, not of the method);
+    tile_sum, fold : one write of each grid value (the tile regions they read
+              are traffic of this implementation, not of the method);
     convolve (one axis pass): one read and one write of the grid;
     gather  : the offsets (12 B per-cell, the node record per-point), the
               permutation index 4 B and one value written (in the caller's
@@ -107,7 +107,7 @@ def alg_bytes(stage: str, N: int, G: int, elem: int, P: int = 3, per_cell: bool 
         return N * (16 + P * elem)
     if stage == "convolve":
         return 2.0 * G * elem
-    return float(G * elem)  # fold
+    return float(G * elem)  # tile_sum, fold
 
 
 def alg_flops(N: int, dA: int, W: int) -> float:

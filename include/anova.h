@@ -417,16 +417,17 @@ anova_status anova_stage_gather(anova_plan_t plan, int32_t l, const void *grid, 
 /*
  * Per-stage device-time accounting, for benchmarks.  While enabled, every
  * anova_matvec and krr_cg_solve matvec records HIP events on the caller's
- * stream around each launch group of the six stage kinds, in execution
+ * stream around each launch group of the seven stage kinds, in execution
  * order: 0 permute (coefficients into each window's sorted point order),
- * 1 spread (window-weighted sums into per-tile grid regions, one or more
- * per tile), 2 fold (the regions added into the grid with periodic wrap),
- * 3 convolve (FFT, multiply, inverse FFT, one launch per axis; for n <= 32
- * in 2-D and 3-D the same filter as a circular convolution, x and y in one
- * launch, z in another), 4 gather (interpolation at the points, written in
- * the caller's order), 5 combine (weighted sum over windows plus the
- * shift).  anova_plan_stage_times synchronises, writes the
- * accumulated milliseconds and launch counts per kind (host arrays of 6) and
+ * 1 spread (window-weighted sums into per-tile grid regions), 2 tile sum
+ * (regions of one tile added, where a tile holds several), 3 fold (tile
+ * regions added into the grid with periodic wrap), 4 convolve (FFT, multiply,
+ * inverse FFT, one launch per axis; for n <= 32 in 2-D and 3-D the same filter
+ * as a circular convolution, x and y in one launch, z in another), 5 gather
+ * (interpolation at the points,
+ * written in the caller's order), 6 combine (weighted sum over windows plus
+ * the shift).  anova_plan_stage_times synchronises, writes the
+ * accumulated milliseconds and launch counts per kind (host arrays of 7) and
  * resets the counters.  Enabling adds a few microseconds of
  * event overhead per launch; disabled by default.
  */

@@ -210,7 +210,7 @@ class WindowInfo:
     tile: int
 
 
-STAGE_KINDS = ("permute", "spread", "fold", "convolve", "gather", "combine")
+STAGE_KINDS = ("permute", "spread", "tile_sum", "fold", "convolve", "gather", "combine")
 
 
 class Plan:

@@ -242,6 +242,7 @@ struct WinInst {
     const void *twiddle;
     const double *alpha;        // input column, caller's order
     void *priv;                 // spread regions
+    void *treg;                 // per-tile region sums
     void *grid;                 // n^dA grid
     void *tmp;                  // sorted coefficients (per-point spread), then
                                 // interpolated values in the caller's order
@@ -284,15 +285,16 @@ struct CombInst {
     CgHook hook;  // partial == nullptr: a plain product
 };
 
-// Stage identifiers, also the reported timing kinds.
+// Stage identifiers; the first five are the reported timing kinds.
 enum StageKind {
     kStagePermute = 0,
     kStageSpread = 1,
-    kStageFold = 2,
-    kStageConvolve = 3,
-    kStageGather = 4,
-    kStageCombine = 5,
-    kStageKinds = 6
+    kStageTileSum = 2,
+    kStageFold = 3,
+    kStageConvolve = 4,
+    kStageGather = 5,
+    kStageCombine = 6,
+    kStageKinds = 7
 };
 
 // A launch: all instances of one stage sharing a kernel signature.

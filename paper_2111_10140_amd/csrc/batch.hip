@@ -24,13 +24,14 @@ namespace {
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 struct Sizes {
-    size_t grid, priv, tmp;
+    size_t grid, priv, treg, tmp;
 };
 
 Sizes instance_sizes(const WindowPlan &w, size_t es, bool own_grid) {
     Sizes z{};
     z.grid = own_grid ? align256(w.grid_elems() * es) : 0;
     z.priv = align256((size_t)w.n_regions * w.region_elems() * es);
+    z.treg = w.n_regions != w.n_nonempty ? align256((size_t)w.n_nonempty * w.region_elems() * es) : 0;
     z.tmp = align256((size_t)w.n_points * es);
     return z;
 }
@@ -77,7 +78,7 @@ size_t problem_work_bytes(const BatchProblem &bp) {
         for (int l = 0; l < bp.plan->P; ++l) {
             if (bp.only_window >= 0 && l != bp.only_window) continue;
             const Sizes z = instance_sizes(wins[l], es, bp.grid_override == nullptr);
-            total += z.grid + z.priv + z.tmp;
+            total += z.grid + z.priv + z.treg + z.tmp;
             if (bp.predict) total += align256((size_t)bp.plan->tgt[l].n_points * es);
         }
     return total;
@@ -119,7 +120,7 @@ void Batch::build(const std::vector<BatchProblem> &problems, const ExternalSpace
     groups.clear();
     // ---- instances and work-space layout
     struct Slot {
-        size_t grid, priv, tmp;
+        size_t grid, priv, treg, tmp;
     };
     std::vector<Slot> slots;
     std::vector<char *> slot_base;  // nullptr: the batch's own work space
@@ -146,8 +147,8 @@ void Batch::build(const std::vector<BatchProblem> &problems, const ExternalSpace
                 if (bp.only_window >= 0 && l != bp.only_window) continue;
                 const WindowPlan &w = problem_windows(bp)[l];
                 const Sizes z = instance_sizes(w, es, bp.grid_override == nullptr);
-                Slot sl{off, off + z.grid, off + z.grid + z.priv};
-                off += z.grid + z.priv + z.tmp;
+                Slot sl{off, off + z.grid, off + z.grid + z.priv, off + z.grid + z.priv + z.treg};
+                off += z.grid + z.priv + z.treg + z.tmp;
                 slots.push_back(sl);
                 slot_base.push_back(static_cast<char *>(bp.work));
                 WinInst wi{};
@@ -160,7 +161,7 @@ void Batch::build(const std::vector<BatchProblem> &problems, const ExternalSpace
                     // the targets: no grid, regions or sums of their own
                     const WindowPlan &v = p->tgt[l];
                     const size_t tz = align256((size_t)v.n_points * es);
-                    slots.push_back(Slot{off, off, off});
+                    slots.push_back(Slot{off, off, off, off});
                     off += tz;
                     slot_base.push_back(static_cast<char *>(bp.work));
                     WinInst wt{};
@@ -197,6 +198,7 @@ void Batch::build(const std::vector<BatchProblem> &problems, const ExternalSpace
         else if (!insts[i].grid)
             insts[i].grid = base + slots[i].grid;
         insts[i].priv = base + slots[i].priv;
+        insts[i].treg = base + slots[i].treg;
         insts[i].tmp = base + slots[i].tmp;
     }
     for (size_t k = 0; k < cwins.size(); ++k) cwins[k].tmp = insts[(size_t)cwin_inst[k]].tmp;
@@ -253,6 +255,15 @@ void Batch::build(const std::vector<BatchProblem> &problems, const ExternalSpace
             g.W = w.width;
             g.tile = w.tile;
         });
+    // tile sum (instances whose tiles hold several regions)
+    add_stage(
+        kStageTileSum, [](const WinInst &) { return std::make_tuple(0, 0, 0, 0, 0, 0); },
+        [](const WinInst &w, int &b) {
+            if (w.n_regions == w.n_nonempty) return false;
+            b = w.n_nonempty * ((w.vol + 255) / 256);
+            return true;
+        },
+        [](BatchGroup &, const WinInst &) {});
     // fold
     add_stage(
         kStageFold, [](const WinInst &w) { return std::make_tuple(w.dA, 0, 0, 0, 0, 0); },

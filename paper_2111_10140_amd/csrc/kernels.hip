@@ -488,32 +488,31 @@ __global__ __launch_bounds__(kBlock) void spread_cell_kernel(const WinInst *__re
     }
     __syncthreads();
     // region point (X, Y, Z) gets cell (dx, dy, dz)'s value at offset
-    // (X - dx, Y - dy, Z - dz), for the cells with every offset in [0, W):
-    // per dimension a run dx = max(0, X-W+1) .. min(TILE-1, X), added in
-    // increasing dz, dy, dx; along a run the staged index moves by a fixed
-    // stride (next cell, offset one lower)
+    // (X - dx, Y - dy, Z - dz) when that offset lies in [0, W)
     float *out = static_cast<float *>(wi.priv) + (size_t)loc.lb * VOL;
-    constexpr int KX = TILE < W ? TILE : W;  // longest run
+    constexpr int KX = TILE < W ? TILE : W;  // loop over the shorter range
     for (int e = threadIdx.x; e < VOL; e += kBlock) {
         const int X = e % L;
         const int Y = DA >= 2 ? (e / L) % L : 0;
         const int Z = DA == 3 ? e / L2 : 0;
-        const int x0 = max(0, X - (W - 1)), nx = min(TILE - 1, X) - x0 + 1;
-        const int y0 = DA >= 2 ? max(0, Y - (W - 1)) : 0;
-        const int y1 = DA >= 2 ? min(TILE - 1, Y) : 0;
-        const int z0 = DA == 3 ? max(0, Z - (W - 1)) : 0;
-        const int z1 = DA == 3 ? min(TILE - 1, Z) : 0;
         float sum = 0.0f;
 #pragma unroll 1
-        for (int dz = z0; dz <= z1; ++dz) {
-#pragma unroll 1
-            for (int dy = y0; dy <= y1; ++dy) {
-                const float *src = stage +
-                                   ((dz * (DA >= 2 ? TILE : 1) + dy) * TILE + x0) * VW +
-                                   ((Z - dz) * WY + (Y - dy)) * W + (X - x0);
+        for (int kz = 0; kz < (DA == 3 ? KX : 1); ++kz) {
+            const int dz = DA == 3 ? (TILE <= W ? kz : Z - kz) : 0;
+            const int oz = Z - dz;
+            if (DA == 3 && (dz < 0 || dz >= TILE || oz < 0 || oz >= W)) continue;
+            for (int ky = 0; ky < (DA >= 2 ? KX : 1); ++ky) {
+                const int dy = DA >= 2 ? (TILE <= W ? ky : Y - ky) : 0;
+                const int oy = Y - dy;
+                if (DA >= 2 && (dy < 0 || dy >= TILE || oy < 0 || oy >= W)) continue;
 #pragma unroll
-                for (int k = 0; k < KX; ++k)
-                    if (k < nx) sum += src[k * (VW - 1)];
+                for (int kx = 0; kx < KX; ++kx) {
+                    const int dx = TILE <= W ? kx : X - kx;
+                    const int ox = X - dx;
+                    if (dx < 0 || dx >= TILE || ox < 0 || ox >= W) continue;
+                    const int cidx = (dz * (DA >= 2 ? TILE : 1) + dy) * TILE + dx;
+                    sum += stage[cidx * VW + (oz * WY + oy) * W + ox];
+                }
             }
         }
         out[e] = sum;
@@ -930,7 +929,8 @@ __device__ __forceinline__ void wide_cells(const WinInst &wi, int key0, int chun
 // Window weights of one point staged in LDS for the lanes of its cell
 // (gathering): per axis the lower-half polynomials at z (lo, offsets
 // a < W/2) and at -z (hi, offset W-1-a), from one even/odd evaluation each,
-// then the point's caller index.  Each lane evaluates the weights of the
+// stored by offset (the hi half reversed, so that half s holds offsets
+// s W/2 .. s W/2 + W/2 - 1 in order), then the point's caller index.  Each lane evaluates the weights of the
 // point it loaded, so a point's polynomials are evaluated once instead of
 // once per lane of the cell; a lane then reads the halves of each axis it
 // owns.  (The spreading kernel keeps evaluating its own: there the staged
@@ -950,12 +950,13 @@ struct WideStage {
 #pragma unroll
             for (int a = 0; a < H; a += 2) {
                 *reinterpret_cast<float2 *>(st + 2 * H * t + a) = make_float2(lo[a], lo[a + 1]);
-                *reinterpret_cast<float2 *>(st + 2 * H * t + H + a) = make_float2(hi[a], hi[a + 1]);
+                *reinterpret_cast<float2 *>(st + 2 * H * t + H + a) =
+                    make_float2(hi[H - 1 - a], hi[H - 2 - a]);
             }
         }
         *reinterpret_cast<float2 *>(st + 6 * H) = make_float2(p.w, 0.0f);
     }
-    // H weights of axis t, half s (0: lo, 1: hi)
+    // H weights of axis t, half s: offsets s H .. s H + H - 1
     __device__ __forceinline__ static void half(const float *st, int t, int s, float (&w)[H]) {
         const float *src = st + 2 * H * t + (s ? H : 0);
 #pragma unroll
@@ -988,10 +989,11 @@ struct WideLane {
 
 // x and y window weights of one point staged in LDS for the lanes of its
 // cell (spreading): per axis the lower-half polynomials at z and at -z
-// (offsets a and W-1-a), from one even/odd evaluation each, the x weights
-// already multiplied by the point's (scaled) coefficient.  A lane reads the
-// halves it owns; z weights, of which a lane needs only its z pass's
-// planes, stay with each lane.  Float offsets: x lo, x hi, y lo, y hi.
+// (offsets a and W-1-a), from one even/odd evaluation each, stored by
+// offset (x then y, W each), the x weights already multiplied by the
+// point's (scaled) coefficient.  A lane reads the half of each axis it
+// owns; z weights, of which a lane needs only its z pass's planes, stay
+// with each lane.
 template <int W>
 struct WideSpreadStage {
     static constexpr int H = W / 2;
@@ -1013,11 +1015,12 @@ struct WideSpreadStage {
 #pragma unroll
             for (int a = 0; a < H; a += 2) {
                 *reinterpret_cast<float2 *>(st + 2 * H * t + a) = make_float2(lo[a], lo[a + 1]);
-                *reinterpret_cast<float2 *>(st + 2 * H * t + H + a) = make_float2(hi[a], hi[a + 1]);
+                *reinterpret_cast<float2 *>(st + 2 * H * t + H + a) =
+                    make_float2(hi[H - 1 - a], hi[H - 2 - a]);
             }
         }
     }
-    // H weights of axis t (0: x, 1: y), half s (0: lo, 1: hi)
+    // H weights of axis t (0: x, 1: y), half s: offsets s H .. s H + H - 1
     __device__ __forceinline__ static void half(const float *st, int t, int s, float (&w)[H]) {
         const float *src = st + 2 * H * t + (s ? H : 0);
 #pragma unroll
@@ -1169,18 +1172,18 @@ __global__ __launch_bounds__(kWideThreads, 2) void spread_wide_kernel(
                 }
             }
             // register sums into the region: |sum| < 2^30, truncated to an
-            // integer (the x and y halves of a lane are mirrored for s = 1)
+            // integer (x and y offsets in order from the lane's half, z
+            // mirrored for the upper half)
 #pragma unroll
             for (int c = 0; c < PZ; ++c) {
                 const int z = lz + AZ::offset(ln.sz, pass * PZ + c);
 #pragma unroll
                 for (int b = 0; b < H; ++b) {
-                    const int y = ly + (ln.sy ? W - 1 - b : b);
-                    unsigned long long *row = acc_lds + (z * L + y) * L + lx;
+                    unsigned long long *row =
+                        acc_lds + (z * L + ly + ln.sy * H + b) * L + lx + ln.sx * H;
 #pragma unroll
                     for (int i = 0; i < H; ++i)
-                        atomicAdd(&row[ln.sx ? W - 1 - i : i],
-                                  (unsigned long long)(long long)(int)acc[c][b][i]);
+                        atomicAdd(&row[i], (unsigned long long)(long long)(int)acc[c][b][i]);
                 }
             }
         }
@@ -1200,6 +1203,18 @@ __device__ __forceinline__ float cell_lanes_sum(float v) {
     return v;
 }
 
+// Row and plane strides of the grid tile in the gathering kernel's LDS:
+// the lanes of a cell read their blocks at offsets W/2 (sx + RY sy + RZ sz)
+// floats apart, padded at W = 12 so that these eight offsets fall in eight
+// different LDS banks.
+template <int W>
+struct WideGridPad {
+    static constexpr int L = kWideTile + W - 1;
+    static constexpr int RY = W == 12 ? L + 3 : L;
+    static constexpr int RZ = W == 12 ? 276 : L * L;
+    static_assert(RY >= L && RZ >= RY * L, "strides cover the tile");
+};
+
 template <int W>
 __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
     const WinInst *__restrict__ insts, const int32_t *__restrict__ members,
@@ -1212,10 +1227,11 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
     constexpr int NG = kWideCells / wide_group_cells<W>();
     constexpr int WX = AX::NA, WY = AY::NA, PZ = AZ::NA / SP::NPG;
     constexpr int T = kWideTile, L = T + W - 1, L2 = L * L, VOL = L2 * L;
+    constexpr int RY = WideGridPad<W>::RY, RZ = WideGridPad<W>::RZ;
     constexpr int m = W / 2;
     using ST = WideStage<W>;
     constexpr int H = ST::H;
-    __shared__ float g_lds[VOL];
+    __shared__ float g_lds[RZ * L];
     __shared__ __align__(16) float wst[NT * ST::STRIDE];
     __shared__ WideCells cs;
     const Located loc = locate(insts, members, prefix, cnt);
@@ -1237,7 +1253,7 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
         size_t gi = (size_t)wrap_index(ox - m + 1 + e % L, n);
         gi += (size_t)n * (size_t)wrap_index(oy - m + 1 + (e / L) % L, n);
         gi += (size_t)n * (size_t)n * (size_t)wrap_index(oz - m + 1 + e / L2, n);
-        g_lds[e] = grid[gi];
+        g_lds[(e / L2) * RZ + ((e / L) % L) * RY + e % L] = grid[gi];
     }
     wide_cells(wi, tile_id * kWideCells, chunk, K, cs);  // its barriers also order the fill
     const WideLane<W> ln;
@@ -1252,15 +1268,17 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
         const int lx = cell % T, ly = (cell / T) % T, lz = cell / (T * T);
 #pragma unroll  // constant pass: the polynomial index stays static
         for (int pass = 0; pass < SP::NPG; ++pass) {
+            // the lane's block, every axis in offset order from its half
+            // (the staged weights are stored by offset)
             float gv[PZ][WY][WX];
 #pragma unroll
             for (int c = 0; c < PZ; ++c) {
-                const int z = lz + AZ::offset(ln.sz, pass * PZ + c);
+                const int z = lz + ln.sz * (W / SP::SZ) + pass * PZ + c;
 #pragma unroll
                 for (int b = 0; b < WY; ++b) {
-                    const float *row = g_lds + (z * L + ly + AY::offset(ln.sy, b)) * L + lx;
+                    const float *row = g_lds + z * RZ + (ly + ln.sy * H + b) * RY + lx + ln.sx * H;
 #pragma unroll
-                    for (int i = 0; i < WX; ++i) gv[c][b][i] = row[AX::offset(ln.sx, i)];
+                    for (int i = 0; i < WX; ++i) gv[c][b][i] = row[i];
                 }
             }
             // points through LDS in rounds of TPC, as in the spreading kernel
@@ -1301,15 +1319,14 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
                         return sc;
                     };
                     if constexpr (SP::SZ == 1 && SP::NPG == 1) {
-                        // the whole z axis: planes in mirror pairs
+                        // the whole z axis
                         float zlo[H], zhi[H];
                         ST::half(ps, 2, 0, zlo);
                         ST::half(ps, 2, 1, zhi);
 #pragma unroll
-                        for (int c2 = 0; c2 < W / 2; ++c2) {
-                            part = fmaf(plane(c2), zlo[c2], part);
-                            part = fmaf(plane(W - 1 - c2), zhi[c2], part);
-                        }
+                        for (int c = 0; c < H; ++c) part = fmaf(plane(c), zlo[c], part);
+#pragma unroll
+                        for (int c = 0; c < H; ++c) part = fmaf(plane(H + c), zhi[c], part);
                     } else {
                         static_assert(SP::SZ == 2, "z split in halves");
                         float zh[H];
@@ -1440,37 +1457,60 @@ __global__ __launch_bounds__(kBlock) void permute_kernel(const WinInst *__restri
     }
 }
 
+// ------------------------------------------------------------------ tile sum
+// Regions of the same tile (several sub-problems or chunks) are added
+// elementwise, in region order, into one region per non-empty tile:
+// src_sub[k] .. src_sub[k+1]-1 are the regions of the k-th non-empty tile.
+// Blocks: non-empty tiles x ceil(vol / kBlock).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void tile_sum_kernel(const WinInst *__restrict__ insts,
+                                                          const int32_t *__restrict__ members,
+                                                          const int32_t *__restrict__ prefix,
+                                                          int cnt) {
+    const Located loc = locate(insts, members, prefix, cnt);
+    const WinInst &wi = *loc.w;
+    const int vol = wi.vol;
+    const int per = (vol + kBlock - 1) / kBlock;
+    const int k = loc.lb / per;
+    const int e = (loc.lb % per) * kBlock + threadIdx.x;
+    if (e >= vol) return;
+    const T *__restrict__ priv = static_cast<const T *>(wi.priv);
+    const int s0 = wi.src_sub[k], s1 = wi.src_sub[k + 1];
+    double s = 0.0;
+    for (int q = s0; q < s1; ++q) s += (double)priv[(size_t)q * vol + e];
+    static_cast<T *>(wi.treg)[(size_t)k * vol + e] = static_cast<T>(s);
+}
+
 // ------------------------------------------------------------------ fold
 // One workgroup per destination tile: every grid point of the tile is the
-// sum, in the fixed order of the plan's pair list and, within a pair, of
-// the source tile's regions (its sub-problems or chunks), of the region
-// values that cover it (regions wrap periodically: per dimension the region
-// indices of grid point o + c are the values in [0, L) congruent to b + c
-// mod n, b the tile origin's offset in the region).  Writes every grid
-// point, so no zero fill is needed.
+// sum, in the fixed order of the plan's pair list, of the region values of
+// the non-empty tiles whose region covers it (regions wrap periodically: per
+// dimension the region indices of grid point o + c are the values in [0, L)
+// congruent to b + c mod n, b the tile origin's offset in the region).
+// Writes every grid point, so no zero fill is needed.
 constexpr int kFoldBatch = 16;  // region reads in flight per thread
 constexpr int kFoldZeroPasses = 4;  // zeroing workgroups: passes of the threads over tiles
 constexpr int kFoldPairsLds = 512;  // a tile's pair list staged in LDS up to this length
 
 // One workgroup per tile that receives regions, in the plan's order
 // (entries -1 are padding).  A small tile's cells get S threads each:
-// thread s of a cell adds pairs s, s + S, s + 2S, ... of the tile's list,
+// thread s of a cell adds regions s, s + S, s + 2S, ... of the tile's list,
 // and the S partial sums are then added in order of s.  The tile's pair
-// list goes to LDS first (when it fits), each pair with its source tile's
-// first region and region count, so that a thread's region reads depend on
-// no other global load and go out kFoldBatch at a time.  The remaining
-// workgroups zero the tiles that receive no region, kFoldZeroPasses passes
-// of the threads over tiles each.
+// list goes to LDS first (when it fits), so that the region reads of a
+// thread depend on no other global load and go out kFoldBatch at a time.
+// The remaining workgroups zero the tiles that receive no region,
+// kFoldZeroPasses passes of the threads over tiles each.
 template <typename T, int DA>
 __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict__ insts,
                                                       const int32_t *__restrict__ members,
                                                       const int32_t *__restrict__ prefix,
                                                       int cnt) {
     __shared__ double part[kBlock];
-    __shared__ int4 pairs_lds[kFoldPairsLds];  // {packed offsets, first region, regions, 0}
+    __shared__ int2 pairs_lds[kFoldPairsLds];
     const Located loc = locate(insts, members, prefix, cnt);
     const WinInst &wi = *loc.w;
-    const T *__restrict__ src = static_cast<const T *>(wi.priv);
+    const T *__restrict__ src =
+        static_cast<const T *>(wi.n_regions != wi.n_nonempty ? wi.treg : wi.priv);
     T *__restrict__ grid = static_cast<T *>(wi.grid);
     const int n = wi.n, tile = wi.tile, tpd = wi.tpd, vol = wi.vol;
     const int L = tile + wi.width - 1;
@@ -1502,20 +1542,11 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
     const int p0 = wi.fold_start[d], p1 = wi.fold_start[d + 1];
     const bool staged = p1 - p0 <= kFoldPairsLds;
     if (staged) {
-        for (int e = (int)threadIdx.x; e < p1 - p0; e += kBlock) {
-            const int2 pr = wi.fold_pairs[p0 + e];
-            const int q0 = wi.src_sub[pr.x], q1 = wi.src_sub[pr.x + 1];
-            pairs_lds[e] = make_int4(pr.y, q0, q1 - q0, 0);
-        }
+        for (int e = (int)threadIdx.x; e < p1 - p0; e += kBlock) pairs_lds[e] = wi.fold_pairs[p0 + e];
         __syncthreads();
     }
-    auto pair_at = [&](int p) {
-        if (staged) return pairs_lds[p - p0];
-        const int2 pr = wi.fold_pairs[p];
-        const int q0 = wi.src_sub[pr.x];
-        return make_int4(pr.y, q0, wi.src_sub[pr.x + 1] - q0, 0);
-    };
-    // sum over the regions of pairs first, first + stride, ... of cell c
+    auto pair_at = [&](int q) { return staged ? pairs_lds[q - p0] : wi.fold_pairs[q]; };
+    // sum over regions first, first + stride, ... of cell c
     auto cell_sum = [&](int c, int first, int stride) {
         const int cx = c % tile;
         const int cy = DA >= 2 ? (c / tile) % tile : 0;
@@ -1523,28 +1554,20 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
         double s = 0.0;
         if (L <= n) {
             // each region element lands on one grid point: at most one read
-            // per region.  The thread walks its (pair, region) items in
-            // order, kFoldBatch reads in flight, added in order.
-            int p = first, q = 0;
-            int4 pr = p < p1 ? pair_at(p) : make_int4(0, 0, 0, 0);
-            while (p < p1) {
+            // per region; kFoldBatch regions' reads in flight, added in order
+            for (int p = first; p < p1; p += kFoldBatch * stride) {
                 T v[kFoldBatch];
 #pragma unroll
                 for (int u = 0; u < kFoldBatch; ++u) {
                     v[u] = T(0);
-                    if (p < p1) {
-                        const int ex = (((pr.x & 1023) + cx) & (n - 1));
-                        const int ey = DA >= 2 ? ((((pr.x >> 10) & 1023) + cy) & (n - 1)) : 0;
-                        const int ez = DA == 3 ? ((((pr.x >> 20) & 1023) + cz) & (n - 1)) : 0;
-                        if (ex < L && ey < L && ez < L && q < pr.z)
-                            v[u] = src[(size_t)(pr.y + q) * vol + ez * L2 + ey * L + ex];
-                        // next item: the pair's next region, else the next pair
-                        // (a pair that misses this cell counts as one item)
-                        if (++q >= pr.z || !(ex < L && ey < L && ez < L)) {
-                            q = 0;
-                            p += stride;
-                            if (p < p1) pr = pair_at(p);
-                        }
+                    const int q = p + u * stride;
+                    if (q < p1) {
+                        const int2 pr = pair_at(q);
+                        const int ex = (((pr.y & 1023) + cx) & (n - 1));
+                        const int ey = DA >= 2 ? ((((pr.y >> 10) & 1023) + cy) & (n - 1)) : 0;
+                        const int ez = DA == 3 ? ((((pr.y >> 20) & 1023) + cz) & (n - 1)) : 0;
+                        if (ex < L && ey < L && ez < L)
+                            v[u] = src[(size_t)pr.x * vol + ez * L2 + ey * L + ex];
                     }
                 }
 #pragma unroll
@@ -1552,17 +1575,15 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
             }
         } else {
             for (int p = first; p < p1; p += stride) {
-                const int4 pr = pair_at(p);
-                const int bx = pr.x & 1023, by = (pr.x >> 10) & 1023, bz = (pr.x >> 20) & 1023;
+                const int2 pr = pair_at(p);
+                const T *reg = src + (size_t)pr.x * vol;
+                const int bx = pr.y & 1023, by = (pr.y >> 10) & 1023, bz = (pr.y >> 20) & 1023;
                 const int ex0 = (bx + cx) & (n - 1);
                 const int ey0 = DA >= 2 ? (by + cy) & (n - 1) : 0;
                 const int ez0 = DA == 3 ? (bz + cz) & (n - 1) : 0;
-                for (int q = 0; q < pr.z; ++q) {
-                    const T *reg = src + (size_t)(pr.y + q) * vol;
-                    for (int ez = ez0; ez < (DA == 3 ? L : 1); ez += n)
-                        for (int ey = ey0; ey < (DA >= 2 ? L : 1); ey += n)
-                            for (int ex = ex0; ex < L; ex += n) s += (double)reg[ez * L2 + ey * L + ex];
-                }
+                for (int ez = ez0; ez < (DA == 3 ? L : 1); ez += n)
+                    for (int ey = ey0; ey < (DA >= 2 ? L : 1); ey += n)
+                        for (int ex = ex0; ex < L; ex += n) s += (double)reg[ez * L2 + ey * L + ex];
             }
         }
         return s;
@@ -2057,6 +2078,10 @@ void run_group(const BatchGroup &g, int precision, const WinInst *insts, hipStre
             break;
         case kStageSpread:
             if (f64) spread_group<double>(g, insts, s); else spread_group<float>(g, insts, s);
+            break;
+        case kStageTileSum:
+            if (f64) launch_k(tile_sum_kernel<double>, g, 0, insts, s);
+            else launch_k(tile_sum_kernel<float>, g, 0, insts, s);
             break;
         case kStageFold:
             if (f64) fold_group<double>(g, insts, s); else fold_group<float>(g, insts, s);

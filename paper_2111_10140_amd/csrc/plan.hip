@@ -1481,7 +1481,7 @@ extern "C" anova_status anova_stage_spread(anova_plan_t p, int32_t l, const doub
         ANOVA_REQUIRE(p != nullptr && alpha != nullptr && grid != nullptr, "NULL argument");
         ANOVA_REQUIRE(l >= 0 && l < p->P, "window index out of range");
         stage_run(p, l, alpha, nullptr, grid, (1u << kStagePermute) | (1u << kStageSpread) |
-                      (1u << kStageFold),
+                      (1u << kStageTileSum) | (1u << kStageFold),
                   (hipStream_t)stream);
     });
 }
