@@ -600,13 +600,13 @@ __global__ __launch_bounds__(kBlock) void gather_cell_kernel(const WinInst *__re
 // Float64 per-cell kernels (d_A = 3, W <= 6, tiles of 4^3 cells): a cell's
 // W^3 float64 support does not fit one thread's registers, so the four
 // lanes of a cell each own a quarter of it, (z half sz) x (y half sy) x all
-// of x, and every lane of the cell walks all of its points.  A lane owning
-// an upper half indexes it mirrored (register c holds offset W-1-c) and
-// evaluates the lower-half polynomials at -z, as the window is even.
-// Spreading stages the cells' lower z halves in LDS, adds them into the
-// region in a fixed order, then the upper halves; gathering adds the four
-// lanes' partial interpolations with DPP quad steps.  No atomics: the
-// results are the same bits for any scheduling.
+// of x, and every lane of the cell walks all of its points, whose window
+// weights the lane that loads each point evaluates once and stages in LDS
+// (the window is even: offsets a and W-1-a come from one even/odd
+// evaluation).  Spreading stages the cells' lower z halves in LDS, adds them
+// into the region in a fixed order, then the upper halves; gathering adds
+// the four lanes' partial interpolations with DPP quad steps.  No atomics:
+// the results are the same bits for any scheduling.
 __device__ __forceinline__ double dpp_f64(double v, int ctrl_is_xor1) {
     const long long b = __double_as_longlong(v);
     int lo, hi;
@@ -625,6 +625,33 @@ __device__ __forceinline__ double quad_sum_f64(double v) {
     return v + dpp_f64(v, 0);
 }
 
+// Window weights of one point staged in LDS for the four lanes of its cell
+// (float64 per-cell kernels): per axis all W weights by offset, from W/2
+// even/odd evaluations (offsets a and W-1-a), then the coefficient
+// (spreading) or the point's caller index (gathering).  The lane that loads
+// a point evaluates them once; each lane then reads all of x and the y and
+// z halves it owns.
+template <int W>
+struct Stage64 {
+    static constexpr int H = W / 2;
+    static constexpr int STRIDE = 3 * W + 2;  // doubles per point (even: 16-byte records)
+    __device__ __forceinline__ static void put(const WinPoly<double, W, kPolyDegCell64> &wp,
+                                               const double (&f)[3], double last, double *st) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const double z = 2.0 * f[t] - 1.0, z2 = z * z;
+#pragma unroll
+            for (int a = 0; a < H; ++a) {
+                double lo, hi;
+                wp.pair(z, z2, a, lo, hi);
+                st[t * W + a] = lo;
+                st[t * W + W - 1 - a] = hi;
+            }
+        }
+        st[3 * W] = last;
+    }
+};
+
 template <int W>
 __global__ __launch_bounds__(kBlock, 2) void spread_cell64_kernel(const WinInst *__restrict__ insts,
                                                                const int32_t *__restrict__ members,
@@ -634,8 +661,12 @@ __global__ __launch_bounds__(kBlock, 2) void spread_cell64_kernel(const WinInst 
     constexpr int L = TILE + W - 1, L2 = L * L, VOL = L2 * L;
     constexpr int VS = H * W * W;  // one z half of a cell's support
     constexpr int PER = (VOL + kBlock - 1) / kBlock;
+    using ST = Stage64<W>;
     static_assert(W % 2 == 0 && W <= 6, "supports of 4 or 6 points");
-    __shared__ __align__(16) double stage[CELLS * VS];
+    // the point loop stages weights here, the region formation the cells'
+    // z halves afterwards
+    constexpr int LDS_D = CELLS * VS > kBlock * ST::STRIDE ? CELLS * VS : kBlock * ST::STRIDE;
+    __shared__ __align__(16) double lds[LDS_D];
     const Located loc = locate(insts, members, prefix, cnt);
     const WinInst &wi = *loc.w;
     const NodeF64 *__restrict__ nodes = static_cast<const NodeF64 *>(wi.nodes);
@@ -650,6 +681,7 @@ __global__ __launch_bounds__(kBlock, 2) void spread_cell64_kernel(const WinInst 
     const int sz = sub >> 1, sy = sub & 1;
     int pb, pe;
     chunk_range(wi.cell_start[key0 + cell], wi.cell_start[key0 + cell + 1], chunk, K, pb, pe);
+    // register (c, b, i) holds offset (sz H + c, sy H + b, i)
     double acc[H][H][W];
 #pragma unroll
     for (int c = 0; c < H; ++c)
@@ -657,61 +689,66 @@ __global__ __launch_bounds__(kBlock, 2) void spread_cell64_kernel(const WinInst 
         for (int b = 0; b < H; ++b)
 #pragma unroll
             for (int i = 0; i < W; ++i) acc[c][b][i] = 0.0;
-    // the next point's record and coefficient load while the current one
-    // is accumulated (the permutation index one point earlier still)
-    double rx = 0, ry = 0, rz = 0, an = 0;
-    int pn = 0;
-    if (pb < pe) {
-        const NodeF64 nd = nodes[pb];
-        rx = nd.f[0]; ry = nd.f[1]; rz = nd.f[2];
-        an = alpha[perm[pb]];
+    // the cell's points go through LDS in rounds of four, lane s of the
+    // cell staging point s of a round (its record and coefficient loading a
+    // round ahead); the lanes of a cell share a wave, whose LDS accesses
+    // complete in order
+    double *cst = lds + (threadIdx.x - sub) * ST::STRIDE;
+    double nf[3] = {0.0, 0.0, 0.0}, na = 0.0;
+    int jl = pb + sub;
+    if (jl < pe) {
+        const NodeF64 nd = nodes[jl];
+        nf[0] = nd.f[0]; nf[1] = nd.f[1]; nf[2] = nd.f[2];
+        na = alpha[perm[jl]];
     }
-    if (pb + 1 < pe) pn = perm[pb + 1];
-    for (int j = pb; j < pe; ++j) {
-        const double x = rx, y = ry, z = rz, a = an;
-        if (j + 1 < pe) {
-            const NodeF64 nd = nodes[j + 1];
-            rx = nd.f[0]; ry = nd.f[1]; rz = nd.f[2];
-            an = alpha[pn];
+    for (int q0 = pb; q0 < pe; q0 += 4) {
+        if (jl < pe) ST::put(wp, nf, na, cst + sub * ST::STRIDE);
+        jl += 4;
+        if (jl < pe) {
+            const NodeF64 nd = nodes[jl];
+            nf[0] = nd.f[0]; nf[1] = nd.f[1]; nf[2] = nd.f[2];
+            na = alpha[perm[jl]];
         }
-        if (j + 2 < pe) pn = perm[j + 2];
-        double wx[W], wy[H], wz[H];
-        wp.eval(x, wx);
-        const double zy = 2.0 * y - 1.0, zz = 2.0 * z - 1.0;
+        const int kn = min(4, pe - q0);
+        for (int k = 0; k < kn; ++k) {
+            const double *ps = cst + k * ST::STRIDE;
+            double wx[W], wy[H], wz[H];
 #pragma unroll
-        for (int b = 0; b < H; ++b) wy[b] = wp.at(sy ? -zy : zy, b);
+            for (int i = 0; i < W; ++i) wx[i] = ps[i];
 #pragma unroll
-        for (int c = 0; c < H; ++c) wz[c] = wp.at(sz ? -zz : zz, c);
+            for (int b = 0; b < H; ++b) wy[b] = ps[W + sy * H + b];
 #pragma unroll
-        for (int c = 0; c < H; ++c) {
-            const double wc = a * wz[c];
+            for (int c = 0; c < H; ++c) wz[c] = ps[2 * W + sz * H + c];
+            const double a = ps[3 * W];
 #pragma unroll
-            for (int b = 0; b < H; ++b) {
-                const double wbc = wc * wy[b];
+            for (int c = 0; c < H; ++c) {
+                const double wc = a * wz[c];
 #pragma unroll
-                for (int i = 0; i < W; ++i) acc[c][b][i] = fma(wbc, wx[i], acc[c][b][i]);
+                for (int b = 0; b < H; ++b) {
+                    const double wbc = wc * wy[b];
+#pragma unroll
+                    for (int i = 0; i < W; ++i) acc[c][b][i] = fma(wbc, wx[i], acc[c][b][i]);
+                }
             }
         }
     }
+    __syncthreads();  // every cell is done with its staged weights
     // the region: element (X, Y, Z) adds cell (dx, dy, dz)'s value at offset
     // (X - dx, Y - dy, Z - dz); lower z halves (offsets 0 .. H-1) first
+    double *stage = lds;
     double sum[PER];
 #pragma unroll
     for (int k = 0; k < PER; ++k) sum[k] = 0.0;
-    const int lx = cell % TILE, ly = (cell / TILE) % TILE, lz = cell / (TILE * TILE);
-    (void)lx; (void)ly; (void)lz;
 #pragma unroll 1
     for (int half = 0; half < 2; ++half) {
         if (half) __syncthreads();  // the first half's reads are done
         if (sz == half) {
-            // stage[cell][c][oy][ox], c the plane inside the half (mirrored
-            // for the upper half: plane c holds offset W-1-c)
+            // stage[cell][c][oy][ox], c the plane inside the half
 #pragma unroll
             for (int c = 0; c < H; ++c)
 #pragma unroll
                 for (int b = 0; b < H; ++b) {
-                    const int oy = sy ? W - 1 - b : b;
-                    double *row = stage + ((size_t)(cell * H + c) * W + oy) * W;
+                    double *row = stage + ((size_t)(cell * H + c) * W + sy * H + b) * W;
 #pragma unroll
                     for (int i = 0; i < W; ++i) row[i] = acc[c][b][i];
                 }
@@ -727,7 +764,7 @@ __global__ __launch_bounds__(kBlock, 2) void spread_cell64_kernel(const WinInst 
                 const int oz = Z - dz;
                 if (oz < 0 || oz >= W) continue;
                 if ((oz >= H) != (half == 1)) continue;
-                const int c = half ? W - 1 - oz : oz;
+                const int c = oz - half * H;
                 for (int dy = 0; dy < TILE; ++dy) {
                     const int oy = Y - dy;
                     if (oy < 0 || oy >= W) continue;
@@ -758,7 +795,9 @@ __global__ __launch_bounds__(kBlock, 2) void gather_cell64_kernel(const WinInst 
                                                                int cnt) {
     constexpr int m = W / 2, H = W / 2, TILE = 4, CELLS = 64;
     constexpr int L = TILE + W - 1, L2 = L * L, VOL = L2 * L;
+    using ST = Stage64<W>;
     __shared__ double g_lds[VOL];
+    __shared__ __align__(16) double wst[kBlock * ST::STRIDE];
     const Located loc = locate(insts, members, prefix, cnt);
     const WinInst &wi = *loc.w;
     const NodeF64 *__restrict__ nodes = static_cast<const NodeF64 *>(wi.nodes);
@@ -788,43 +827,62 @@ __global__ __launch_bounds__(kBlock, 2) void gather_cell64_kernel(const WinInst 
     // the four lanes of a cell share its point count, so they leave together
     if (pb >= pe) return;
     const int lx = cell % TILE, ly = (cell / TILE) % TILE, lz = cell / (TILE * TILE);
+    // register (c, b, i) holds offset (sz H + c, sy H + b, i)
     double g[H][H][W];
 #pragma unroll
     for (int c = 0; c < H; ++c)
 #pragma unroll
         for (int b = 0; b < H; ++b) {
-            const int zc = sz ? W - 1 - c : c, yb = sy ? W - 1 - b : b;
-            const double *row = g_lds + ((lz + zc) * L + ly + yb) * L + lx;
+            const double *row = g_lds + ((lz + sz * H + c) * L + ly + sy * H + b) * L + lx;
 #pragma unroll
             for (int i = 0; i < W; ++i) g[c][b][i] = row[i];
         }
+    // points through LDS in rounds of four, as in the spreading kernel (the
+    // staged record ends with the point's caller index)
     const int32_t *__restrict__ perm = wi.perm;
-    NodeF64 nx = nodes[pb];
-    for (int j = pb; j < pe; ++j) {
-        const NodeF64 nd = nx;
-        if (j + 1 < pe) nx = nodes[j + 1];
-        double wx[W], wy[H], wz[H];
-        wp.eval(nd.f[0], wx);
-        const double zy = 2.0 * nd.f[1] - 1.0, zz = 2.0 * nd.f[2] - 1.0;
-#pragma unroll
-        for (int b = 0; b < H; ++b) wy[b] = wp.at(sy ? -zy : zy, b);
-#pragma unroll
-        for (int c = 0; c < H; ++c) wz[c] = wp.at(sz ? -zz : zz, c);
-        double part = 0.0;
-#pragma unroll
-        for (int c = 0; c < H; ++c) {
-            double sc = 0.0;
-#pragma unroll
-            for (int b = 0; b < H; ++b) {
-                double sr = 0.0;
-#pragma unroll
-                for (int i = 0; i < W; ++i) sr = fma(g[c][b][i], wx[i], sr);
-                sc = fma(sr, wy[b], sc);
-            }
-            part = fma(sc, wz[c], part);
+    double *cst = wst + (threadIdx.x - sub) * ST::STRIDE;
+    double nf[3] = {0.0, 0.0, 0.0};
+    int np = 0;
+    int jl = pb + sub;
+    if (jl < pe) {
+        const NodeF64 nd = nodes[jl];
+        nf[0] = nd.f[0]; nf[1] = nd.f[1]; nf[2] = nd.f[2];
+        np = perm[jl];
+    }
+    for (int q0 = pb; q0 < pe; q0 += 4) {
+        if (jl < pe) ST::put(wp, nf, __longlong_as_double((long long)np), cst + sub * ST::STRIDE);
+        jl += 4;
+        if (jl < pe) {
+            const NodeF64 nd = nodes[jl];
+            nf[0] = nd.f[0]; nf[1] = nd.f[1]; nf[2] = nd.f[2];
+            np = perm[jl];
         }
-        const double v = quad_sum_f64(part);
-        if (sub == 0) tmp[perm[j]] = v;  // caller order
+        const int kn = min(4, pe - q0);
+        for (int k = 0; k < kn; ++k) {
+            const double *ps = cst + k * ST::STRIDE;
+            double wx[W], wy[H], wz[H];
+#pragma unroll
+            for (int i = 0; i < W; ++i) wx[i] = ps[i];
+#pragma unroll
+            for (int b = 0; b < H; ++b) wy[b] = ps[W + sy * H + b];
+#pragma unroll
+            for (int c = 0; c < H; ++c) wz[c] = ps[2 * W + sz * H + c];
+            double part = 0.0;
+#pragma unroll
+            for (int c = 0; c < H; ++c) {
+                double sc = 0.0;
+#pragma unroll
+                for (int b = 0; b < H; ++b) {
+                    double sr = 0.0;
+#pragma unroll
+                    for (int i = 0; i < W; ++i) sr = fma(g[c][b][i], wx[i], sr);
+                    sc = fma(sr, wy[b], sc);
+                }
+                part = fma(sc, wz[c], part);
+            }
+            const double v = quad_sum_f64(part);
+            if (sub == 0) tmp[(int)__double_as_longlong(ps[3 * W])] = v;  // caller order
+        }
     }
 }
 
