@@ -88,8 +88,17 @@ __device__ __forceinline__ ColRange col_range(const CgCol *__restrict__ cols,
 }
 
 __device__ double sum_partials(const double *__restrict__ partial, int nblk, double *sh) {
+    // a thread adds partials tid, tid + kRedBlock, ... in that order (a
+    // missing one as +0), their loads issued eight at a time
+    constexpr int B = 8;
     double v = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += kRedBlock) v += partial[i];
+    for (int i = threadIdx.x; i < nblk; i += B * kRedBlock) {
+        double t[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) t[u] = i + u * kRedBlock < nblk ? partial[i + u * kRedBlock] : 0.0;
+#pragma unroll
+        for (int u = 0; u < B; ++u) v += t[u];
+    }
     return block_sum(v, sh);
 }
 

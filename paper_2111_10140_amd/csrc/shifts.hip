@@ -81,8 +81,17 @@ __device__ __forceinline__ double ms_block_sum(double v, double *sh) {
 
 // fixed-order sum of nblk partials (one workgroup)
 __device__ double ms_sum_partials(const double *__restrict__ partial, int nblk, double *sh) {
+    // partials tid, tid + kMsBlock, ... in that order (a missing one as +0),
+    // their loads issued eight at a time
+    constexpr int B = 8;
     double v = 0.0;
-    for (int i = threadIdx.x; i < nblk; i += kMsBlock) v += partial[i];
+    for (int i = threadIdx.x; i < nblk; i += B * kMsBlock) {
+        double t[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) t[u] = i + u * kMsBlock < nblk ? partial[i + u * kMsBlock] : 0.0;
+#pragma unroll
+        for (int u = 0; u < B; ++u) v += t[u];
+    }
     return ms_block_sum(v, sh);
 }
 
