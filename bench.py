@@ -38,7 +38,7 @@ VALU_FP32_PEAK_TFLOPS = 78.6
 # the chip's float32 vector peak counting packed instructions (which this
 # library does not emit), reported beside the fraction for reference
 VALU_FP32_PACKED_PEAK_TFLOPS = 157.3
-C_EVAL = 8  # flops charged per window evaluation (degree-8 polynomial)
+C_EVAL = 8  # flops charged per window evaluation (a fixed charge, not the kernels' own count)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "headline_pmc_traffic.txt")
 
 
@@ -113,9 +113,9 @@ def alg_bytes(stage: str, N: int, G: int, elem: int, P: int = 3, per_cell: bool 
 def alg_flops(N: int, dA: int, W: int) -> float:
     """Algorithmic flops of one window's spread or gather (an FMA counts 2):
     per point, 2 W^d_A for the tensor-product sum over the W^d_A support
-    points, plus d_A W window evaluations at C_EVAL flops each (degree-8
-    polynomials per support offset).  The kernels' own instruction counts
-    (mirror pairs, weight products) are not what is charged."""
+    points, plus d_A W window evaluations at C_EVAL flops each.  The
+    kernels' own instruction counts (degree-7 polynomials evaluated in
+    mirror pairs, weight products) are not what is charged."""
     return float(N) * (2 * W ** dA + dA * W * C_EVAL)
 
 

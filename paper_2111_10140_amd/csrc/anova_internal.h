@@ -122,10 +122,11 @@ struct CombineWin {
 };
 
 // Degree of the per-offset window polynomials: the fit error of the
-// Kaiser-Bessel window stays below 2e-7 (float32) and 1.2e-14 (float64) of
-// its maximum for m = 2..8 and oversampling 1.25..4.
+// Kaiser-Bessel window stays below 1.1e-6 (float32; below 2e-7 for m >= 3)
+// and 1.2e-14 (float64) of its maximum for m = 2..8 and oversampling
+// 1.25..4, and the plan counts it in the window error.
 template <typename T> struct PolyDeg;
-template <> struct PolyDeg<float> { static constexpr int value = 8; };
+template <> struct PolyDeg<float> { static constexpr int value = 7; };
 template <> struct PolyDeg<double> { static constexpr int value = 15; };
 // Degree of the float64 per-cell kernels' polynomials (3-D, W <= 6): those
 // windows' own aliasing error is above 1e-8, and degree 11 fits to below
