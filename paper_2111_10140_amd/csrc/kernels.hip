@@ -1534,8 +1534,16 @@ __global__ __launch_bounds__(kBlock) void tile_sum_kernel(const WinInst *__restr
     if (e >= vol) return;
     const T *__restrict__ priv = static_cast<const T *>(wi.priv);
     const int s0 = wi.src_sub[k], s1 = wi.src_sub[k + 1];
+    // regions in order, their loads issued eight at a time (a missing one as +0)
+    constexpr int B = 8;
     double s = 0.0;
-    for (int q = s0; q < s1; ++q) s += (double)priv[(size_t)q * vol + e];
+    for (int q = s0; q < s1; q += B) {
+        T v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) v[u] = q + u < s1 ? priv[(size_t)(q + u) * vol + e] : T(0);
+#pragma unroll
+        for (int u = 0; u < B; ++u) s += (double)v[u];
+    }
     static_cast<T *>(wi.treg)[(size_t)k * vol + e] = static_cast<T>(s);
 }
 
@@ -1724,6 +1732,163 @@ __device__ __forceinline__ typename Cplx<T>::type *filter_lines(typename Cplx<T>
     return src;
 }
 
+// ---- register-resident transforms of 64 to 256 points
+// DFT of R = 8 or 16 values held in registers (radix 2, decimation in
+// time, unrolled: every index is a compile-time constant).  Forward:
+// A_k = sum_u a_u exp(-2 pi i u k / R); INV: the conjugate exponent.  The
+// twiddles are exp(-+2 pi i j / 16), cos and sin of multiples of pi / 8.
+__host__ __device__ constexpr int bit_reverse(int i, int bits) {
+    int r = 0;
+    for (int b = 0; b < bits; ++b) r |= ((i >> b) & 1) << (bits - 1 - b);
+    return r;
+}
+template <typename T, int R, bool INV>
+__device__ __forceinline__ void dft_reg(typename Cplx<T>::type (&a)[R]) {
+    using C = typename Cplx<T>::type;
+    static_assert(R == 2 || R == 4 || R == 8 || R == 16, "2 to 16 points");
+    constexpr int LR = R == 2 ? 1 : (R == 4 ? 2 : (R == 8 ? 3 : 4));
+    constexpr double c16[8] = {1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508977,
+                               0.0, -0.38268343236508977, -0.70710678118654752, -0.92387953251128674};
+    constexpr double s16[8] = {0.0, 0.38268343236508977, 0.70710678118654752, 0.92387953251128674,
+                               1.0, 0.92387953251128674, 0.70710678118654752, 0.38268343236508977};
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+        const int j = bit_reverse(i, LR);
+        if (j > i) {
+            const C t = a[i];
+            a[i] = a[j];
+            a[j] = t;
+        }
+    }
+#pragma unroll
+    for (int len = 2; len <= R; len <<= 1) {
+#pragma unroll
+        for (int i = 0; i < R; i += len) {
+#pragma unroll
+            for (int k = 0; k < len / 2; ++k) {
+                const T wr = (T)c16[k * (16 / len)];
+                const T wi = INV ? (T)s16[k * (16 / len)] : -(T)s16[k * (16 / len)];
+                const C u = a[i + k], v0 = a[i + k + len / 2];
+                C v;
+                if (k == 0) {
+                    v = v0;
+                } else {
+                    v.x = v0.x * wr - v0.y * wi;
+                    v.y = v0.x * wi + v0.y * wr;
+                }
+                a[i + k] = C{u.x + v.x, u.y + v.y};
+                a[i + k + len / 2] = C{u.x - v.x, u.y - v.y};
+            }
+        }
+    }
+}
+
+// exp(-2 pi i p / n) from the plan's table of the first n/2 powers
+template <typename C>
+__device__ __forceinline__ C twiddle_pow(const C *__restrict__ tw, int p, int n) {
+    p &= n - 1;
+    if (p < n / 2) return tw[p];
+    const C w = tw[p - n / 2];
+    return C{-w.x, -w.y};
+}
+
+// Axis pass for n = R1 R2 = 64, 128 or 256 (R1 = 8 or 16, R2 = 8 or 16):
+// forward transform, multiplier, inverse transform of NP complex lines (two
+// real lines each) with one LDS exchange per direction.  Index u = u1 +
+// R1 u2 and k = k2 + R2 k1: thread t of a line first transforms its u1 = t
+// column over u2 (R2 points), multiplies by exp(-2 pi i u1 k2 / n) and
+// writes it to LDS; thread t < R2 then transforms the k2 = t row over u1
+// (R1 points), which gives X at k = t + R2 k1, applies the multiplier there,
+// and runs the inverse steps in the opposite order (inverse over k1,
+// conjugate twiddle, exchange, inverse over k2).  The lanes of a workgroup
+// map to (line, t) with consecutive lanes on neighbouring lines for the
+// strided axes (their reads are then contiguous across lanes) and on
+// neighbouring t for axis 0.
+template <typename T, int LOGN>
+__global__ __launch_bounds__(kBlock) void convolve4_kernel(const WinInst *__restrict__ insts,
+                                                           const int32_t *__restrict__ members,
+                                                           const int32_t *__restrict__ prefix,
+                                                           int cnt, int axis) {
+    using C = typename Cplx<T>::type;
+    constexpr int n = 1 << LOGN, R1 = 1 << ((LOGN + 1) / 2), R2 = 1 << (LOGN / 2);
+    constexpr int NP = kBlock / R1;  // complex lines per workgroup
+    // padded exchange rows (RS) and lines (LS odd: lanes on neighbouring
+    // lines, as on the strided axes, then meet different LDS banks)
+    constexpr int RS = R2 + 1, LS = R1 * RS + 1;
+    __shared__ C xl[NP * LS];
+    const Located loc = locate(insts, members, prefix, cnt);
+    const WinInst &wi = *loc.w;
+    T *__restrict__ grid = static_cast<T *>(wi.grid);
+    const T *__restrict__ bconv = static_cast<const T *>(wi.bconv);
+    const C *__restrict__ tw = static_cast<const C *>(wi.twiddle);
+    int nlines = 1;
+    for (int d = 1; d < wi.dA; ++d) nlines *= n;
+    const int ls = LOGN * axis;  // stride s = n^axis = 2^ls
+    const size_t s = (size_t)1 << ls;
+    const bool contiguous = axis == 0;
+    // strided axes: lane groups of NP take columns t in the order 0, R1/2,
+    // 1, R1/2 + 1, ..., so that every wave holds as many columns t < R2 (the
+    // ones that do the middle step) as the others
+    const int tq = (int)threadIdx.x / NP;
+    const int q = contiguous ? (int)threadIdx.x / R1 : (int)threadIdx.x % NP;
+    const int t = contiguous ? (int)threadIdx.x % R1 : (tq & 1) * (R1 / 2) + (tq >> 1);
+    const int r0 = 2 * (loc.lb * NP + q), r1 = r0 + 1;
+    auto base_of = [&](int r) -> size_t {
+        const size_t hi = (size_t)(r >> ls), lo = (size_t)(r & (int)(s - 1));
+        return hi * s * n + lo;
+    };
+    const size_t b0 = base_of(r0), b1 = base_of(r1);
+    const bool in0 = r0 < nlines, in1 = r1 < nlines;
+    C *xq = xl + q * LS;
+    // forward over u2 for u1 = t, twiddle, exchange
+    C a[R2];
+#pragma unroll
+    for (int u2 = 0; u2 < R2; ++u2) {
+        const size_t off = (size_t)(t + R1 * u2) * s;
+        a[u2] = C{in0 ? grid[b0 + off] : T(0), in1 ? grid[b1 + off] : T(0)};
+    }
+    dft_reg<T, R2, false>(a);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) {
+        const C w = twiddle_pow(tw, t * k2, n);
+        const C v = a[k2];
+        xq[t * RS + k2] = C{v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x};
+    }
+    __syncthreads();
+    if (t < R2) {
+        // forward over u1 for k2 = t: X at k = t + R2 k1; multiplier; inverse
+        C b[R1];
+#pragma unroll
+        for (int u1 = 0; u1 < R1; ++u1) b[u1] = xq[u1 * RS + t];
+        dft_reg<T, R1, false>(b);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            const T f = bconv[t + R2 * k1];
+            b[k1].x *= f;
+            b[k1].y *= f;
+        }
+        dft_reg<T, R1, true>(b);
+#pragma unroll
+        for (int u1 = 0; u1 < R1; ++u1) {
+            const C w = twiddle_pow(tw, u1 * t, n);  // conjugated below
+            const C v = b[u1];
+            xq[u1 * RS + t] = C{v.x * w.x + v.y * w.y, v.y * w.x - v.x * w.y};
+        }
+    }
+    __syncthreads();
+    // inverse over k2 for u1 = t: the line at u = t + R1 u2 (the multiplier
+    // carries the 1/n)
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) a[k2] = xq[t * RS + k2];
+    dft_reg<T, R2, true>(a);
+#pragma unroll
+    for (int u2 = 0; u2 < R2; ++u2) {
+        const size_t off = (size_t)(t + R1 * u2) * s;
+        if (in0) grid[b0 + off] = a[u2].x;
+        if (in1) grid[b1 + off] = a[u2].y;
+    }
+}
+
 // One pass along `axis` (element stride n^axis) of the n^d_A real grid of
 // each instance, NP complex lines (2 NP real lines) per workgroup.
 template <typename T, int LOGN>
@@ -1895,6 +2060,17 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(const CombInst *__restr
 // ================================================================== host side
 namespace {
 
+int ilog2(int n) {
+    int l = 0;
+    while ((1 << (l + 1)) <= n) ++l;
+    return l;
+}
+// n = 64 .. 256 (float64: up to 128, whose exchange fits 64 KB of LDS) go
+// through the register-resident transform kernel
+bool convolve_four_step(int n, int elem_bytes) {
+    return (n == 64 || n == 128 || n == 256) && (elem_bytes == 4 || n <= 128);
+}
+
 template <int DA>
 struct CellTileOf {
     static constexpr int value = DA == 3 ? 4 : (DA == 2 ? 16 : 64);
@@ -2053,6 +2229,21 @@ void convolve_group(const BatchGroup &g, const WinInst *insts, hipStream_t s) {
         ANOVA_HIP_CHECK(hipGetLastError());
         return;
     }
+    if (convolve_four_step(g.n, (int)sizeof(T))) {
+        if (g.np != kBlock / (1 << ((ilog2(g.n) + 1) / 2)))
+            throw Error{ANOVA_E_INVALID, "convolution lines per workgroup do not match the kernel"};
+#define ANOVA_CONV4(LOGN)                                                                     \
+    hipLaunchKernelGGL((convolve4_kernel<T, LOGN>), dim3((unsigned)g.blocks), dim3(kBlock), 0, s, \
+                       insts, g.members, g.prefix, g.cnt, g.axis)
+        switch (g.n) {
+            case 64: ANOVA_CONV4(6); break;
+            case 128: ANOVA_CONV4(7); break;
+            default: ANOVA_CONV4(8); break;
+        }
+#undef ANOVA_CONV4
+        ANOVA_HIP_CHECK(hipGetLastError());
+        return;
+    }
     const size_t shm = 2 * (size_t)g.np * g.n * sizeof(typename Cplx<T>::type);
 #define ANOVA_CONV(LOGN)                                                                  \
     hipLaunchKernelGGL((convolve_kernel<T, LOGN>), dim3((unsigned)g.blocks), dim3(kBlock), \
@@ -2074,6 +2265,8 @@ void convolve_group(const BatchGroup &g, const WinInst *insts, hipStream_t s) {
 
 bool convolve_direct(int n, int dA) { return dA >= 2 && n <= kConvolveDirectMax; }
 int convolve_lines_per_block(int n, int nq, int elem_bytes) {
+    // the register-resident kernel maps its threads to (line, column)
+    if (convolve_four_step(n, elem_bytes)) return kBlock / (1 << ((ilog2(n) + 1) / 2));
     // passes along y and z read, for each line position, the workgroup's
     // 2 NP neighbouring lines: 2 NP elements of 128 contiguous bytes keep
     // those reads whole cache lines (NP = 16 floats or 8 doubles); the LDS
