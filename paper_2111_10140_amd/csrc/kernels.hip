@@ -1291,6 +1291,7 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
     constexpr int H = ST::H;
     __shared__ float g_lds[RZ * L];
     __shared__ __align__(16) float wst[NT * ST::STRIDE];
+    __shared__ float vsum[NT];  // a round's values, slot s of a cell for its point s
     __shared__ WideCells cs;
     const Located loc = locate(insts, members, prefix, cnt);
     const WinInst &wi = *loc.w;
@@ -1318,49 +1319,50 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
     const bool lead = ln.sub == 0;
     const float *cst = wst + (threadIdx.x - ln.sub) * ST::STRIDE;  // the cell's points
     float *myst = wst + threadIdx.x * ST::STRIDE;
+    float *cval = vsum + (threadIdx.x - ln.sub);
+    static_assert(SP::SX == 2 && SP::SY == 2, "x and y split in halves");
 #pragma unroll 1
     for (int g = 0; g < NG; ++g) {
         const int cell = cs.order[ln.slot(g)];
         const int pb = cs.pb[cell], pe = pb + cs.cnt[cell];
         if (pb >= pe) continue;  // the lanes of a cell go on together
         const int lx = cell % T, ly = (cell / T) % T, lz = cell / (T * T);
-#pragma unroll  // constant pass: the polynomial index stays static
-        for (int pass = 0; pass < SP::NPG; ++pass) {
-            // the lane's block, every axis in offset order from its half
-            // (the staged weights are stored by offset)
-            float gv[PZ][WY][WX];
-#pragma unroll
-            for (int c = 0; c < PZ; ++c) {
-                const int z = lz + ln.sz * (W / SP::SZ) + pass * PZ + c;
-#pragma unroll
-                for (int b = 0; b < WY; ++b) {
-                    const float *row = g_lds + z * RZ + (ly + ln.sy * H + b) * RY + lx + ln.sx * H;
-#pragma unroll
-                    for (int i = 0; i < WX; ++i) gv[c][b][i] = row[i];
-                }
-            }
-            // points through LDS in rounds of TPC, as in the spreading kernel
-            // (offsets and the point's index in the caller's order)
-            float4 nx = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            int jl = pb + ln.sub;
+        // the cell's points go through LDS in rounds of TPC, lane s of the
+        // cell staging point s of a round (offsets and caller index loading a
+        // round ahead); within a round each pass loads its block of the
+        // support and adds its part of the round's values, so a value is
+        // written once, after the last pass
+        float4 nx = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        int jl = pb + ln.sub;
+        if (jl < pe) {
+            const float3 r = node_offsets(nodes + jl);
+            nx = make_float4(r.x, r.y, r.z, __int_as_float(perm[jl]));
+        }
+        for (int q0 = pb; q0 < pe; q0 += TPC) {
+            ST::put(hp, nx, myst);
+            jl += TPC;
             if (jl < pe) {
                 const float3 r = node_offsets(nodes + jl);
                 nx = make_float4(r.x, r.y, r.z, __int_as_float(perm[jl]));
             }
-            for (int q0 = pb; q0 < pe; q0 += TPC) {
-                ST::put(hp, nx, myst);
-                jl += TPC;
-                if (jl < pe) {
-                    const float3 r = node_offsets(nodes + jl);
-                    nx = make_float4(r.x, r.y, r.z, __int_as_float(perm[jl]));
+            const int kn = min(TPC, pe - q0);
+#pragma unroll  // constant pass: the polynomial index stays static
+            for (int pass = 0; pass < SP::NPG; ++pass) {
+                // the lane's block, every axis in offset order from its half
+                // (the staged weights are stored by offset)
+                float gv[PZ][WY][WX];
+#pragma unroll
+                for (int c = 0; c < PZ; ++c) {
+                    const int z = lz + ln.sz * (W / SP::SZ) + pass * PZ + c;
+#pragma unroll
+                    for (int b = 0; b < WY; ++b) {
+                        const float *row = g_lds + z * RZ + (ly + ln.sy * H + b) * RY + lx + ln.sx * H;
+#pragma unroll
+                        for (int i = 0; i < WX; ++i) gv[c][b][i] = row[i];
+                    }
                 }
-                const int kn = min(TPC, pe - q0);
                 for (int k = 0; k < kn; ++k) {
                     const float *ps = cst + k * ST::STRIDE;
-                    float *dst = tmp + __float_as_int(ps[6 * H]);
-                    // a later pass adds to what the same lane wrote in the pass before
-                    const float prev = pass > 0 && lead ? *dst : 0.0f;
-                    static_assert(SP::SX == 2 && SP::SY == 2, "x and y split in halves");
                     float wx[WX], wy[WY];
                     ST::half(ps, 0, ln.sx, wx);
                     ST::half(ps, 1, ln.sy, wy);
@@ -1393,9 +1395,11 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
                         for (int c = 0; c < PZ; ++c) part = fmaf(plane(c), zh[pass * PZ + c], part);
                     }
                     const float v = cell_lanes_sum<TPC>(part);
-                    if (lead) *dst = prev + v;  // caller order
+                    if (lead) cval[k] = pass == 0 ? v : cval[k] + v;
                 }
             }
+            // lane s of the cell writes the value of the point it staged
+            if (ln.sub < kn) tmp[__float_as_int(myst[6 * H])] = cval[ln.sub];  // caller order
         }
     }
 }
