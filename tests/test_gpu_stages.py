@@ -70,7 +70,10 @@ def axis_multiplier(ell, h, M, n, m):
     (F32, 3, 64, 128, 6),   # FFT per axis at the paper's parameters
     (F32, 2, 12, 16, 3),    # taps, one plane
     (F32, 1, 48, 64, 4),    # 1-D: FFT
+    (F32, 2, 128, 256, 4),  # 16 x 16 register transforms
+    (F32, 1, 96, 128, 5),
     (F64, 3, 32, 64, 4),
+    (F64, 2, 64, 128, 4),   # float64, 16 x 8 register transforms
     (F64, 3, 16, 32, 4),    # taps in float64
     (F64, 2, 24, 32, 4),
     (F64, 1, 12, 16, 3),    # 1-D, small n: FFT
