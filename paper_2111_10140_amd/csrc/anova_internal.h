@@ -121,13 +121,17 @@ struct CombineWin {
     double eta;
 };
 
-// Degree of the per-offset window polynomials: the fit error of the
-// Kaiser-Bessel window stays below 1.1e-6 (float32; below 2e-7 for m >= 3)
-// and 1.2e-14 (float64) of its maximum for m = 2..8 and oversampling
-// 1.25..4, and the plan counts it in the window error.
+// Degree of the per-offset window polynomials of a support of W points: the
+// fit error of the Kaiser-Bessel window stays below 2e-7 (float32: degree 8
+// for m <= 2, 7 beyond) and 1.2e-14 (float64) of its maximum for m = 2..8
+// and oversampling 1.25..4, and the plan counts it in the window error.
 template <typename T> struct PolyDeg;
-template <> struct PolyDeg<float> { static constexpr int value = 7; };
-template <> struct PolyDeg<double> { static constexpr int value = 15; };
+template <> struct PolyDeg<float> {
+    static constexpr int of(int W) { return W <= 4 ? 8 : 7; }
+};
+template <> struct PolyDeg<double> {
+    static constexpr int of(int) { return 15; }
+};
 // Degree of the float64 per-cell kernels' polynomials (3-D, W <= 6): those
 // windows' own aliasing error is above 1e-8, and degree 11 fits to below
 // 2e-10 of the maximum for m = 2, 3 and oversampling 1.25..4, with fewer

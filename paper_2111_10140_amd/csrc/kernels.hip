@@ -80,11 +80,11 @@ __device__ __forceinline__ double uniform(double v) {
 
 // Weights phi0(f + m - 1 - a), a = 0..W-1, of a point with fractional cell
 // offset f in [0,1): one polynomial per support offset, Horner in z = 2f-1.
-// The degree is fixed per precision, so the loops unroll and the
+// The degree is fixed per precision and width, so the loops unroll and the
 // coefficients, uniform across the wave, stay in scalar registers.
 template <typename T, int W>
 __device__ __forceinline__ void window_weights(const T *__restrict__ poly, T f, T (&w)[W]) {
-    constexpr int D = PolyDeg<T>::value;
+    constexpr int D = PolyDeg<T>::of(W);
     const T z = T(2) * f - T(1);
 #pragma unroll
     for (int a = 0; a < W; ++a) w[a] = poly[a * (D + 1) + D];
@@ -102,7 +102,7 @@ __device__ __forceinline__ void window_weights(const T *__restrict__ poly, T f, 
 // only the lower half is held, and split into its even and odd parts in z,
 // p(z) = E(z^2) + z O(z^2), it gives both weights of the pair (a, W-1-a),
 // E + zO and E - zO, for about half the multiply-adds of two evaluations.
-template <typename T, int W, int DEG = PolyDeg<T>::value>
+template <typename T, int W, int DEG = PolyDeg<T>::of(W)>
 struct WinPoly {
     static constexpr int D = DEG, H = W / 2;
     static_assert(W % 2 == 0, "supports of 2m points");

@@ -876,8 +876,8 @@ void build_window(WindowPlan &w, const Points &X, int prec) {
     // window polynomial table at the precision's fixed degree; its error
     // perturbs every weight, counted (per dimension, spread and gather) in
     // the window error relative to the window's integral
-    const int deg = prec == ANOVA_FP64 ? (w.dense ? kPolyDegCell64 : PolyDeg<double>::value)
-                                       : PolyDeg<float>::value;
+    const int deg = prec == ANOVA_FP64 ? (w.dense ? kPolyDegCell64 : PolyDeg<double>::of(2 * m))
+                                       : PolyDeg<float>::of(2 * m);
     double fit_err = 0.0;
     std::vector<double> coef = fit_window_polys(m, w.kb_b, deg, fit_err);
     w.poly_deg = deg;
