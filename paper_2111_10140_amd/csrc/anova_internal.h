@@ -62,32 +62,62 @@ anova_status guarded(F &&f) {
 // invalidate (plans may be built on several host threads).
 std::recursive_mutex &device_mutex();
 
+// Small device blocks (tables of plans, batches and solves: up to
+// kSmallBlockMax bytes, in power-of-two size classes) are kept per device
+// for reuse when released instead of being freed: hipFree waits for the
+// device, which stalls the work of other threads and streams (a serving
+// loop frees and allocates such tables whenever a request starts or ends).
+// At most kSmallCacheBytes per device are kept.  Called with device_mutex()
+// held; `dev` is the current device.
+constexpr size_t kSmallBlockMax = (size_t)1 << 20;
+constexpr size_t kSmallCacheBytes = (size_t)256 << 20;
+void *small_block_take(int dev, size_t cls);           // nullptr if none is cached
+bool small_block_give(int dev, void *p, size_t cls);  // false: the cache is full
+
 struct DevBuf {
     void *ptr = nullptr;
     size_t bytes = 0;
+    int dev = -1;  // device of a cached-class block
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
-    DevBuf(DevBuf &&o) noexcept : ptr(o.ptr), bytes(o.bytes) { o.ptr = nullptr; o.bytes = 0; }
+    DevBuf(DevBuf &&o) noexcept : ptr(o.ptr), bytes(o.bytes), dev(o.dev) {
+        o.ptr = nullptr; o.bytes = 0; o.dev = -1;
+    }
     DevBuf &operator=(DevBuf &&o) noexcept {
         release();
-        ptr = o.ptr; bytes = o.bytes; o.ptr = nullptr; o.bytes = 0;
+        ptr = o.ptr; bytes = o.bytes; dev = o.dev; o.ptr = nullptr; o.bytes = 0; o.dev = -1;
         return *this;
     }
     ~DevBuf() { release(); }
+    static size_t size_class(size_t b) {
+        size_t c = 256;
+        while (c < b) c <<= 1;
+        return c;
+    }
     void alloc(size_t b) {
         release();
         if (b == 0) b = 256;
         std::lock_guard<std::recursive_mutex> lock(device_mutex());
+        if (b <= kSmallBlockMax) {
+            const size_t cls = size_class(b);
+            int d = 0;
+            ANOVA_HIP_CHECK(hipGetDevice(&d));
+            ptr = small_block_take(d, cls);
+            if (!ptr) ANOVA_HIP_CHECK(hipMalloc(&ptr, cls));
+            bytes = cls;
+            dev = d;
+            return;
+        }
         ANOVA_HIP_CHECK(hipMalloc(&ptr, b));
         bytes = b;
     }
     void release() {
         if (ptr) {
             std::lock_guard<std::recursive_mutex> lock(device_mutex());
-            (void)hipFree(ptr);
+            if (dev < 0 || !small_block_give(dev, ptr, bytes)) (void)hipFree(ptr);
         }
-        ptr = nullptr; bytes = 0;
+        ptr = nullptr; bytes = 0; dev = -1;
     }
     template <typename T> T *as() const { return static_cast<T *>(ptr); }
 };

@@ -734,8 +734,12 @@ extern "C" anova_status anova_plan_footprint(anova_plan_t plan, int32_t nrhs,
             const int64_t N = plan->N;
             const int64_t nblk = (N + kSpan - 1) / kSpan;
             // r, p, q, partial sums, scalars, work space, column tables
-            // (each allocation rounded as DevBuf rounds an empty one)
-            auto dev = [](size_t b) { return (int64_t)std::max<size_t>(b, 256); };
+            // (each allocation rounded as DevBuf rounds it: small blocks to
+            // their size class)
+            auto dev = [](size_t b) {
+                if (b == 0) b = 256;
+                return (int64_t)(b <= kSmallBlockMax ? DevBuf::size_class(b) : b);
+            };
             int64_t b = 3 * dev((size_t)N * nrhs * sizeof(double));
             b += dev((size_t)2 * nblk * nrhs * sizeof(double)) + dev(sizeof(CgScal) * nrhs);
             const int64_t ncomb = (N + combine_span() - 1) / combine_span();

@@ -969,6 +969,35 @@ std::recursive_mutex &device_mutex() {
     return mu;
 }
 
+namespace {
+struct SmallCache {
+    std::map<size_t, std::vector<void *>> free;  // size class -> blocks
+    size_t bytes = 0;
+};
+std::map<int, SmallCache> &small_caches() {
+    static std::map<int, SmallCache> c;  // per device; guarded by device_mutex()
+    return c;
+}
+}  // namespace
+
+void *small_block_take(int dev, size_t cls) {
+    SmallCache &c = small_caches()[dev];
+    auto it = c.free.find(cls);
+    if (it == c.free.end() || it->second.empty()) return nullptr;
+    void *p = it->second.back();
+    it->second.pop_back();
+    c.bytes -= cls;
+    return p;
+}
+
+bool small_block_give(int dev, void *p, size_t cls) {
+    SmallCache &c = small_caches()[dev];
+    if (c.bytes + cls > kSmallCacheBytes) return false;
+    c.free[cls].push_back(p);
+    c.bytes += cls;
+    return true;
+}
+
 hipEvent_t pool_event(anova_plan_s *p) {
     if (!p->event_pool.empty()) {
         hipEvent_t e = p->event_pool.back();
