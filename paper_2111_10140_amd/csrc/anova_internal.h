@@ -67,8 +67,10 @@ std::recursive_mutex &device_mutex();
 // for reuse when released instead of being freed: hipFree waits for the
 // device, which stalls the work of other threads and streams (a serving
 // loop frees and allocates such tables whenever a request starts or ends).
-// At most kSmallCacheBytes per device are kept.  Called with device_mutex()
-// held; `dev` is the current device.
+// A released block becomes reusable only after a device synchronisation
+// that follows its release (one per many releases), as work queued before
+// the release may still read it.  At most kSmallCacheBytes per device are
+// kept.  Called with device_mutex() held; `dev` is the block's device.
 constexpr size_t kSmallBlockMax = (size_t)1 << 20;
 constexpr size_t kSmallCacheBytes = (size_t)256 << 20;
 void *small_block_take(int dev, size_t cls);           // nullptr if none is cached

@@ -970,13 +970,29 @@ std::recursive_mutex &device_mutex() {
 }
 
 namespace {
+// A released block may still be read by work queued before its release (on
+// any stream), so it waits in `pending` until a device synchronisation
+// after its release, one for every kPendingFlush releases, and only then
+// becomes reusable.
+constexpr size_t kPendingFlush = 512;
 struct SmallCache {
-    std::map<size_t, std::vector<void *>> free;  // size class -> blocks
-    size_t bytes = 0;
+    std::map<size_t, std::vector<void *>> free;  // size class -> reusable blocks
+    std::vector<std::pair<void *, size_t>> pending;
+    size_t bytes = 0;  // free and pending
 };
 std::map<int, SmallCache> &small_caches() {
     static std::map<int, SmallCache> c;  // per device; guarded by device_mutex()
     return c;
+}
+void flush_pending(int dev, SmallCache &c) {
+    int cur = 0;
+    ANOVA_HIP_CHECK(hipGetDevice(&cur));
+    if (cur != dev) ANOVA_HIP_CHECK(hipSetDevice(dev));
+    const hipError_t e = hipDeviceSynchronize();
+    if (cur != dev) (void)hipSetDevice(cur);
+    ANOVA_HIP_CHECK(e);
+    for (auto &b : c.pending) c.free[b.second].push_back(b.first);
+    c.pending.clear();
 }
 }  // namespace
 
@@ -993,8 +1009,9 @@ void *small_block_take(int dev, size_t cls) {
 bool small_block_give(int dev, void *p, size_t cls) {
     SmallCache &c = small_caches()[dev];
     if (c.bytes + cls > kSmallCacheBytes) return false;
-    c.free[cls].push_back(p);
+    c.pending.emplace_back(p, cls);
     c.bytes += cls;
+    if (c.pending.size() >= kPendingFlush) flush_pending(dev, c);
     return true;
 }
 
