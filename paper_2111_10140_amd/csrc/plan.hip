@@ -965,8 +965,10 @@ void validate(const double *X, int64_t N, int32_t d, int64_t ldx, const anova_wi
 }  // namespace
 
 std::recursive_mutex &device_mutex() {
-    static std::recursive_mutex mu;
-    return mu;
+    // never destroyed: buffers held by other static objects are released
+    // during exit, after function-local statics constructed later are gone
+    static std::recursive_mutex *mu = new std::recursive_mutex();
+    return *mu;
 }
 
 namespace {
@@ -981,8 +983,9 @@ struct SmallCache {
     size_t bytes = 0;  // free and pending
 };
 std::map<int, SmallCache> &small_caches() {
-    static std::map<int, SmallCache> c;  // per device; guarded by device_mutex()
-    return c;
+    // per device; guarded by device_mutex(); never destroyed (as the mutex)
+    static std::map<int, SmallCache> *c = new std::map<int, SmallCache>();
+    return *c;
 }
 void flush_pending(int dev, SmallCache &c) {
     int cur = 0;
