@@ -987,13 +987,15 @@ std::map<int, SmallCache> &small_caches() {
     static std::map<int, SmallCache> *c = new std::map<int, SmallCache>();
     return *c;
 }
+// (runs inside buffer releases, destructors included: a failed
+// synchronisation leaves the blocks pending instead of throwing)
 void flush_pending(int dev, SmallCache &c) {
     int cur = 0;
-    ANOVA_HIP_CHECK(hipGetDevice(&cur));
-    if (cur != dev) ANOVA_HIP_CHECK(hipSetDevice(dev));
+    if (hipGetDevice(&cur) != hipSuccess) return;
+    if (cur != dev && hipSetDevice(dev) != hipSuccess) return;
     const hipError_t e = hipDeviceSynchronize();
     if (cur != dev) (void)hipSetDevice(cur);
-    ANOVA_HIP_CHECK(e);
+    if (e != hipSuccess) return;
     for (auto &b : c.pending) c.free[b.second].push_back(b.first);
     c.pending.clear();
 }
