@@ -343,6 +343,33 @@ def test_rebuilt_tables_on_a_nonblocking_stream(A):
         assert np.array_equal(to_np(outs[c]), alone[c]), c
 
 
+def test_plans_released_while_products_run(A):
+    # plans built and destroyed on a non-blocking stream while products of
+    # earlier plans may still be queued there: the library keeps released
+    # device tables for reuse only after a device synchronisation that
+    # follows their release (hundreds of releases here, so that reuse
+    # happens), and every product must equal the same product run alone
+    import torch
+    p = workloads.random_problem(3000, 6, [(0, 1, 2), (3, 4), (5,)], 0.2, seed=23)
+    a = np.ascontiguousarray(p.alpha[:, 0])
+    alone = gpu_matvec(A, make_plan(A, p, F32), a, p.beta)
+    x = dev_cols(a)
+    st = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    outs = []
+    with torch.cuda.stream(st):
+        for _ in range(24):
+            plan = A.anova_fastsum_plan(dev_rows(p.X), p.windows, A.make_params(p.ell, F32),
+                                        stream=st)
+            o = torch.empty_like(x)
+            A.anova_matvec(plan, x, o, p.beta, stream=st)
+            outs.append(o)
+            plan.destroy()
+    st.synchronize()
+    for k, o in enumerate(outs):
+        assert np.array_equal(to_np(o), alone), k
+
+
 def test_host_plan_equals_device_plan(A):
     import torch
     p = workloads.random_problem(5000, 6, [(0, 1, 2), (3, 4), (5,)], 0.2, seed=33)
