@@ -1404,6 +1404,324 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
     }
 }
 
+// ------------------------------------------------------------------ per-tile, matrix cores
+// 12-point supports in 3-D.  A tile of 4^3 cells has a 15^3 region, which
+// pads to 15 planes of 16 x 16.  Spreading adds, for each plane z,
+//   R_z[y][x] += sum_j (a_j wz_j[z] wy_j[y]) wx_j[x]
+// over the tile's points j, each point's weights placed at its cell's offset
+// in zero-padded 16-vectors: a (16 x K) by (K x 16) product for K points,
+// four points per V_MFMA_F32_16X16X4_F32.  Gathering contracts the other
+// way: T_z[y][j] = sum_x G_z[y][x] wx_j[x] by the same instruction with x as
+// the inner dimension, then v_j = sum_z wz_j[z] sum_y wy_j[y] T_z[y][j] on
+// the vector units.  Instruction layout (one 16 x 16 block, inner dimension
+// 4): lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16], and its four
+// result registers hold D[4 (l / 16) + r][l % 16].
+//
+// One lane evaluates a point's weights and stages them in LDS for its wave
+// (x and y zero-padded to 16 at the cell's offset, z unpadded); each wave
+// takes a contiguous quarter of the workgroup's points.  A tile's points are
+// sorted by cell, z slowest, so a run of them mostly shares one z layer and
+// touches W of the 15 planes: each step computes the planes its points can
+// touch and skips the rest.  Compared with the per-cell kernels there are no
+// atomics: a wave's sums stay in its result registers until the end, where
+// the four waves' regions are added in a fixed order.
+constexpr int kMfmaThreads = 256, kMfmaRound = 64;
+constexpr int kMfmaStride = 44;  // floats per staged point: x 16, y 16, z 12
+typedef float mfma_f4 __attribute__((ext_vector_type(4)));
+
+template <int W>
+struct MfmaRegion {
+    static constexpr int L = kWideTile + W - 1;  // region edge
+    static_assert(L <= 16, "region rows and columns fit one 16-wide block");
+    static_assert(W <= 12, "z weights take 12 staged slots");
+    static_assert(L - W == 3, "four z layers of cells per tile");
+};
+
+// Stage one point: its x and y weights at offsets lx, ly of zero-padded
+// 16-vectors (y multiplied by ya), then its W z weights.
+template <int W>
+__device__ __forceinline__ void mfma_stage(const WinPoly<float, W> &hp, float3 r, int lx, int ly,
+                                           float ya, float *st) {
+    float4 *v = reinterpret_cast<float4 *>(st);
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    float w[W];
+    hp.eval(r.x, w);
+#pragma unroll
+    for (int a = 0; a < W; ++a) st[lx + a] = w[a];
+    hp.eval(r.y, w);
+#pragma unroll
+    for (int a = 0; a < W; ++a) st[16 + ly + a] = ya * w[a];
+    hp.eval(r.z, w);
+#pragma unroll
+    for (int a = 0; a < W; ++a) st[32 + a] = w[a];
+}
+
+__device__ __forceinline__ void mfma_stage_zero(float *st) {
+    float4 *v = reinterpret_cast<float4 *>(st);
+#pragma unroll
+    for (int q = 0; q < kMfmaStride / 4; ++q) v[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
+// LDS written by one lane of a wave and then read by others: LDS operations
+// of a wave complete in order; this keeps the compiler from moving them.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Planes [zlo, zhi) of a step: W planes from a constant first one when the
+// step's points share a z layer, else all of them.  f(Z0, NZ) runs planes
+// Z0 .. Z0 + NZ - 1 with both constant, so the per-plane registers stay
+// statically indexed.
+template <int W, typename F>
+__device__ __forceinline__ void mfma_planes(int zlo, int zhi, F &&f) {
+    constexpr int L = MfmaRegion<W>::L;
+    using std::integral_constant;
+    if (zhi - zlo == W) {
+        switch (zlo) {
+            case 0: f(integral_constant<int, 0>{}, integral_constant<int, W>{}); return;
+            case 1: f(integral_constant<int, 1>{}, integral_constant<int, W>{}); return;
+            case 2: f(integral_constant<int, 2>{}, integral_constant<int, W>{}); return;
+            case 3: f(integral_constant<int, 3>{}, integral_constant<int, W>{}); return;
+            default: break;
+        }
+    }
+    f(integral_constant<int, 0>{}, integral_constant<int, L>{});
+}
+
+// z weight of plane c for a point of layer lz staged at sp: constant slot
+// when the step's points all start at plane Z0, else looked up and zero
+// outside the support.
+template <int W, int Z0, int NZ>
+__device__ __forceinline__ float mfma_zweight(const float *sp, int c, int lz) {
+    if constexpr (NZ == W) {
+        return sp[32 + c - Z0];
+    } else {
+        const int d = c - lz;
+        const float v = sp[32 + min(max(d, 0), W - 1)];
+        return (unsigned)d < (unsigned)W ? v : 0.0f;
+    }
+}
+
+// The workgroup's tile (origin cell) and its points: a contiguous share of
+// the tile's sorted points, chunk `chunk` of K.
+struct MfmaTile {
+    int ox, oy, oz, c0, c1;
+    int key0, chunk, K;  // first (tile, cell) key; chunk `chunk` of K
+};
+__device__ __forceinline__ MfmaTile mfma_tile(const WinInst &wi, int lb) {
+    int tk, chunk, K;
+    locate_chunk(wi.src_sub, wi.n_nonempty, lb, tk, chunk, K);
+    const int tile_id = wi.tiles_ne[tk], tpd = wi.tpd;
+    MfmaTile t;
+    t.ox = (tile_id % tpd) * kWideTile;
+    t.oy = ((tile_id / tpd) % tpd) * kWideTile;
+    t.oz = (tile_id / (tpd * tpd)) * kWideTile;
+    t.key0 = tile_id * kWideCells;
+    t.chunk = chunk;
+    t.K = K;
+    chunk_range(wi.cell_start[t.key0], wi.cell_start[t.key0 + kWideCells], chunk, K, t.c0, t.c1);
+    return t;
+}
+
+// Wave wv's share of the workgroup's points: whole steps of S points, the
+// workgroup's steps split evenly over its waves (only its last step short).
+__device__ __forceinline__ void mfma_wave_share(const MfmaTile &t, int wv, int S, int &q0, int &q1) {
+    constexpr int NWV = kMfmaThreads / 64;
+    const int steps = (t.c1 - t.c0 + S - 1) / S;
+    q0 = min(t.c1, t.c0 + S * (steps * wv / NWV));
+    q1 = min(t.c1, t.c0 + S * (steps * (wv + 1) / NWV));
+}
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Spreading: wave wv takes the points of the tile's cell layer wv (cells
+// 16 wv .. 16 wv + 15, their chunk's share), whose z supports all start at
+// plane wv, so its steps touch W planes at constant indices.
+template <int W>
+__global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(
+    const WinInst *__restrict__ insts, const int32_t *__restrict__ members,
+    const int32_t *__restrict__ prefix, int cnt) {
+    constexpr int L = MfmaRegion<W>::L, VOL = L * L * L, NWV = kMfmaThreads / 64;
+    constexpr int LAYER = kWideTile * kWideTile;  // cells per z layer
+    constexpr int STAGE = NWV * kMfmaRound * kMfmaStride, PLANES = 2 * L * 256;
+    static_assert(NWV == kWideTile, "one wave per cell layer");
+    __shared__ __align__(16) float lds[STAGE > PLANES ? STAGE : PLANES];
+    const Located loc = locate(insts, members, prefix, cnt);
+    const WinInst &wi = *loc.w;
+    const NodeF32 *__restrict__ nodes = static_cast<const NodeF32 *>(wi.nodes);
+    const int32_t *__restrict__ perm = wi.perm;
+    const double *__restrict__ alpha = wi.alpha;
+    WinPoly<float, W> hp;
+    hp.load(static_cast<const float *>(wi.poly));
+    const MfmaTile tl = mfma_tile(wi, loc.lb);
+    const int lane = (int)threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int g = lane >> 4, col = lane & 15;
+    int q0, q1;
+    chunk_range(wi.cell_start[tl.key0 + LAYER * wv], wi.cell_start[tl.key0 + LAYER * (wv + 1)],
+                tl.chunk, tl.K, q0, q1);
+    float *wst = lds + wv * (kMfmaRound * kMfmaStride);
+    mfma_f4 acc[L];
+#pragma unroll
+    for (int c = 0; c < L; ++c) acc[c] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
+    auto run = [&](auto z0c) {
+        constexpr int Z0 = decltype(z0c)::value;
+        for (int base = q0; base < q1; base += kMfmaRound) {
+            const int kn = min(kMfmaRound, q1 - base);
+            float *st = wst + lane * kMfmaStride;
+            wave_lds_sync();  // the previous round's reads come first
+            if (lane < kn) {
+                const int j = base + lane;
+                const float4 nd = *reinterpret_cast<const float4 *>(nodes + j);
+                const uint32_t cb = __float_as_uint(nd.w);
+                const int lx = (int)(cb & 1023u) - tl.ox, ly = (int)((cb >> 10) & 1023u) - tl.oy;
+                mfma_stage(hp, make_float3(nd.x, nd.y, nd.z), lx, ly, (float)alpha[perm[j]], st);
+            } else {
+                mfma_stage_zero(st);  // a step's missing points add zero
+            }
+            wave_lds_sync();
+            for (int k0 = 0; k0 < kn; k0 += 4) {
+                // lanes of group g hold the step's point g: A column g, B row g
+                const float *sp = wst + (k0 + g) * kMfmaStride;
+                const float xb = sp[col], ya = sp[16 + col];
+#pragma unroll
+                for (int c = Z0; c < Z0 + W; ++c)
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya * sp[32 + c - Z0], xb, acc[c], 0, 0, 0);
+            }
+        }
+    };
+    switch (wv) {
+        case 0: run(std::integral_constant<int, 0>{}); break;
+        case 1: run(std::integral_constant<int, 1>{}); break;
+        case 2: run(std::integral_constant<int, 2>{}); break;
+        default: run(std::integral_constant<int, 3>{}); break;
+    }
+    // the four waves' regions: (0 + 2) + (1 + 3), in the padded layout
+    __syncthreads();
+    if (wv < 2) {
+        float *dst = lds + wv * (L * 256);
+#pragma unroll
+        for (int c = 0; c < L; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dst[c * 256 + (4 * g + r) * 16 + col] = acc[c][r];
+    }
+    __syncthreads();
+    if (wv >= 2) {
+        float *dst = lds + (wv - 2) * (L * 256);
+#pragma unroll
+        for (int c = 0; c < L; ++c)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) dst[c * 256 + (4 * g + r) * 16 + col] += acc[c][r];
+    }
+    __syncthreads();
+    float *out = static_cast<float *>(wi.priv) + (size_t)loc.lb * VOL;
+    for (int e = threadIdx.x; e < VOL; e += kMfmaThreads) {
+        const int i = (e / (L * L)) * 256 + ((e / L) % L) * 16 + e % L;
+        out[e] = lds[i] + lds[L * 256 + i];
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(kMfmaThreads) void gather_mfma_kernel(
+    const WinInst *__restrict__ insts, const int32_t *__restrict__ members,
+    const int32_t *__restrict__ prefix, int cnt) {
+    constexpr int L = MfmaRegion<W>::L, NWV = kMfmaThreads / 64, m = W / 2;
+    constexpr int STAGE = NWV * kMfmaRound * kMfmaStride, PLANES = L * 256;
+    __shared__ __align__(16) float lds[STAGE > PLANES ? STAGE : PLANES];
+    __shared__ int lzs[NWV * kMfmaRound], idx[NWV * kMfmaRound];
+    const Located loc = locate(insts, members, prefix, cnt);
+    const WinInst &wi = *loc.w;
+    const NodeF32 *__restrict__ nodes = static_cast<const NodeF32 *>(wi.nodes);
+    const float *__restrict__ grid = static_cast<const float *>(wi.grid);
+    float *__restrict__ tmp = static_cast<float *>(wi.tmp);
+    const int32_t *__restrict__ perm = wi.perm;
+    WinPoly<float, W> hp;
+    hp.load(static_cast<const float *>(wi.poly));
+    const MfmaTile tl = mfma_tile(wi, loc.lb);
+    const int n = wi.n;
+    const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    // the tile's region of the grid, padded to 16 x 16 planes with zeros
+    for (int e = threadIdx.x; e < L * 256; e += kMfmaThreads) {
+        const int x = e & 15, y = (e >> 4) & 15, z = e >> 8;
+        float v = 0.0f;
+        if (x < L && y < L) {
+            size_t gi = (size_t)wrap_index(tl.ox - m + 1 + x, n);
+            gi += (size_t)n * (size_t)wrap_index(tl.oy - m + 1 + y, n);
+            gi += (size_t)n * (size_t)n * (size_t)wrap_index(tl.oz - m + 1 + z, n);
+            v = grid[gi];
+        }
+        lds[e] = v;
+    }
+    __syncthreads();
+    // A operand of every plane, kept in registers: row col, x = 4 g .. 4 g + 3
+    // (step s of a plane's four takes x = 4 (l / 16) + s in lane l)
+    float4 gv[L];
+#pragma unroll
+    for (int c = 0; c < L; ++c) gv[c] = *reinterpret_cast<const float4 *>(lds + c * 256 + col * 16 + 4 * g);
+    __syncthreads();  // the region's LDS becomes staging space
+    int q0, q1;
+    mfma_wave_share(tl, wv, 16, q0, q1);
+    float *wst = lds + wv * (kMfmaRound * kMfmaStride);
+    int *wlz = lzs + wv * kMfmaRound;
+    int *widx = idx + wv * kMfmaRound;
+    for (int base = q0; base < q1; base += kMfmaRound) {
+        const int kn = min(kMfmaRound, q1 - base);
+        float *st = wst + lane * kMfmaStride;
+        wave_lds_sync();
+        if (lane < kn) {
+            const int j = base + lane;
+            const float4 nd = *reinterpret_cast<const float4 *>(nodes + j);
+            const uint32_t cb = __float_as_uint(nd.w);
+            const int lx = (int)(cb & 1023u) - tl.ox, ly = (int)((cb >> 10) & 1023u) - tl.oy;
+            wlz[lane] = (int)((cb >> 20) & 1023u) - tl.oz;
+            widx[lane] = perm[j];
+            mfma_stage(hp, make_float3(nd.x, nd.y, nd.z), lx, ly, 1.0f, st);
+        } else {
+            mfma_stage_zero(st);
+        }
+        wave_lds_sync();
+        for (int kb = 0; kb < kn; kb += 16) {
+            // lane l takes point kb + l % 16 (B column and result column)
+            const int p = kb + col;
+            const float *sp = wst + p * kMfmaStride;
+            const float4 xv = *reinterpret_cast<const float4 *>(sp + 4 * g);
+            const float4 yv = *reinterpret_cast<const float4 *>(sp + 16 + 4 * g);
+            const int lzp = wlz[min(p, kn - 1)];
+            const int zlo = __builtin_amdgcn_readfirstlane(wlz[kb]);
+            const int zhi = __builtin_amdgcn_readfirstlane(wlz[min(kb + 15, kn - 1)]) + W;
+            float part = 0.0f;
+            mfma_planes<W>(zlo, zhi, [&](auto z0c, auto nzc) {
+                constexpr int Z0 = decltype(z0c)::value, NZ = decltype(nzc)::value;
+#pragma unroll
+                for (int c = Z0; c < Z0 + NZ; ++c) {
+                    mfma_f4 t = {0.0f, 0.0f, 0.0f, 0.0f};
+                    t = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[c].x, xv.x, t, 0, 0, 0);
+                    t = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[c].y, xv.y, t, 0, 0, 0);
+                    t = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[c].z, xv.z, t, 0, 0, 0);
+                    t = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[c].w, xv.w, t, 0, 0, 0);
+                    // rows 4 g + r of the plane, weighted by y, then by z
+                    const float s = fmaf(yv.x, t[0], fmaf(yv.y, t[1], fmaf(yv.z, t[2], yv.w * t[3])));
+                    part = fmaf(mfma_zweight<W, Z0, NZ>(sp, c, lzp), s, part);
+                }
+            });
+            // the four row groups of the point, in the same order in every lane
+            part += __shfl_xor(part, 16, 64);
+            part += __shfl_xor(part, 32, 64);
+            if (g == 0 && p < kn) tmp[widx[p]] = part;  // caller order
+        }
+    }
+}
+
 // ------------------------------------------------------------------ gather, per point
 template <typename T, int DA, int W>
 __global__ __launch_bounds__(kBlock) void gather_pt_kernel(const WinInst *__restrict__ insts,
@@ -2120,7 +2438,8 @@ void spread_cell_launch(const BatchGroup &g, const WinInst *insts, hipStream_t s
     if constexpr (DA == 3 && (W == 8 || W == 12)) {
         if (g.tile != kWideTile)
             throw Error{ANOVA_E_INVALID, "wide per-cell kernels take 4^3-cell tiles"};
-        launch_nt(spread_wide_kernel<W>, kWideThreads, g, insts, s);
+        if constexpr (W == 12) launch_nt(spread_mfma_kernel<W>, kMfmaThreads, g, insts, s);
+        else launch_nt(spread_wide_kernel<W>, kWideThreads, g, insts, s);
     } else if constexpr (cell_supported<DA, W>()) {
         constexpr int TILE = CellTileOf<DA>::value;
         constexpr int S = kBlock / CellShape<DA, TILE>::cells;
@@ -2134,7 +2453,8 @@ void gather_cell_launch(const BatchGroup &g, const WinInst *insts, hipStream_t s
     if constexpr (DA == 3 && (W == 8 || W == 12)) {
         if (g.tile != kWideTile)
             throw Error{ANOVA_E_INVALID, "wide per-cell kernels take 4^3-cell tiles"};
-        launch_nt(gather_wide_kernel<W>, kWideThreads, g, insts, s);
+        if constexpr (W == 12) launch_nt(gather_mfma_kernel<W>, kMfmaThreads, g, insts, s);
+        else launch_nt(gather_wide_kernel<W>, kWideThreads, g, insts, s);
     } else if constexpr (cell_supported<DA, W>()) {
         constexpr int TILE = CellTileOf<DA>::value;
         constexpr int S = kBlock / CellShape<DA, TILE>::cells;
@@ -2167,8 +2487,12 @@ template <int DA, int W>
 int spread_cell_blocks_per_cu() {
     int nb = 0;
     if constexpr (DA == 3 && (W == 8 || W == 12)) {
-        ANOVA_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &nb, reinterpret_cast<const void *>(spread_wide_kernel<W>), kWideThreads, 0));
+        if constexpr (W == 12)
+            ANOVA_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, reinterpret_cast<const void *>(spread_mfma_kernel<W>), kMfmaThreads, 0));
+        else
+            ANOVA_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &nb, reinterpret_cast<const void *>(spread_wide_kernel<W>), kWideThreads, 0));
     } else if constexpr (cell_supported<DA, W>()) {
         constexpr int TILE = CellTileOf<DA>::value;
         constexpr int S = kBlock / CellShape<DA, TILE>::cells;
