@@ -144,6 +144,17 @@ __device__ __forceinline__ float3 node_offsets(const NodeF32 *__restrict__ p) {
     return *reinterpret_cast<const float3 *>(p);
 }
 
+// A device pointer read from an instance record is generic to the compiler,
+// so loads through it are flat loads, which also count against the LDS
+// wait counter: waiting for an LDS read then waits for them too.  Loads
+// through the global view are global loads, waited for on their own.
+template <typename T>
+using global_ptr = const __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ global_ptr<T> as_global(const T *p) {
+    return (global_ptr<T>)p;
+}
+
 // Periodic index on a grid of n points: n is a power of two (the plan
 // requires it), so the two's-complement mask also wraps negative g.
 __device__ __forceinline__ int wrap_index(int g, int n) { return g & (n - 1); }
@@ -346,12 +357,24 @@ __device__ __forceinline__ void chunk_range(int cs, int ce, int k, int K, int &b
 
 // Workgroup lb of a per-cell launch: its non-empty tile k (chunk_start =
 // src_sub, ascending), its chunk inside the tile and the tile's chunk count.
+// Plans give every tile of a window the same count, so k = lb / count is
+// tried first (checked against the starts, a search over them otherwise):
+// two dependent loads instead of one per halving of the tile list.
 __device__ __forceinline__ void locate_chunk(const int32_t *__restrict__ cstart, int n_ne, int lb,
                                              int &k, int &chunk, int &K) {
-    int lo = 0, hi = n_ne;  // cstart[lo] <= lb < cstart[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (cstart[mid] <= lb) lo = mid; else hi = mid;
+    int lo = -1;
+    const int k1 = __builtin_amdgcn_readfirstlane(cstart[1] - cstart[0]);
+    if (k1 > 0) {
+        const int kk = min(lb / k1, n_ne - 1);
+        if (cstart[kk] <= lb && lb < cstart[kk + 1]) lo = kk;
+    }
+    if (lo < 0) {
+        lo = 0;
+        int hi = n_ne;  // cstart[lo] <= lb < cstart[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (cstart[mid] <= lb) lo = mid; else hi = mid;
+        }
     }
     k = __builtin_amdgcn_readfirstlane(lo);
     const int c0 = __builtin_amdgcn_readfirstlane(cstart[k]);
@@ -1635,7 +1658,8 @@ __global__ __launch_bounds__(kMfmaThreads) void gather_mfma_kernel(
     const WinInst *__restrict__ insts, const int32_t *__restrict__ members,
     const int32_t *__restrict__ prefix, int cnt) {
     constexpr int L = MfmaRegion<W>::L, NWV = kMfmaThreads / 64, m = W / 2;
-    constexpr int STAGE = NWV * kMfmaRound * kMfmaStride, PLANES = L * 256;
+    constexpr int RS = 20, PS = 16 * RS;  // LDS row and plane strides of the region
+    constexpr int STAGE = NWV * kMfmaRound * kMfmaStride, PLANES = L * PS;
     __shared__ __align__(16) float lds[STAGE > PLANES ? STAGE : PLANES];
     __shared__ int lzs[NWV * kMfmaRound], idx[NWV * kMfmaRound];
     const Located loc = locate(insts, members, prefix, cnt);
@@ -1651,6 +1675,7 @@ __global__ __launch_bounds__(kMfmaThreads) void gather_mfma_kernel(
     const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
     const int g = lane >> 4, col = lane & 15;
     // the tile's region of the grid, padded to 16 x 16 planes with zeros
+    // (rows RS apart: the lanes' row reads below then meet fewer LDS banks)
     for (int e = threadIdx.x; e < L * 256; e += kMfmaThreads) {
         const int x = e & 15, y = (e >> 4) & 15, z = e >> 8;
         float v = 0.0f;
@@ -1660,14 +1685,14 @@ __global__ __launch_bounds__(kMfmaThreads) void gather_mfma_kernel(
             gi += (size_t)n * (size_t)n * (size_t)wrap_index(tl.oz - m + 1 + z, n);
             v = grid[gi];
         }
-        lds[e] = v;
+        lds[z * PS + y * RS + x] = v;
     }
     __syncthreads();
     // A operand of every plane, kept in registers: row col, x = 4 g .. 4 g + 3
     // (step s of a plane's four takes x = 4 (l / 16) + s in lane l)
     float4 gv[L];
 #pragma unroll
-    for (int c = 0; c < L; ++c) gv[c] = *reinterpret_cast<const float4 *>(lds + c * 256 + col * 16 + 4 * g);
+    for (int c = 0; c < L; ++c) gv[c] = *reinterpret_cast<const float4 *>(lds + c * PS + col * RS + 4 * g);
     __syncthreads();  // the region's LDS becomes staging space
     int q0, q1;
     mfma_wave_share(tl, wv, 16, q0, q1);
@@ -1877,6 +1902,8 @@ __global__ __launch_bounds__(kBlock) void tile_sum_kernel(const WinInst *__restr
 // congruent to b + c mod n, b the tile origin's offset in the region).
 // Writes every grid point, so no zero fill is needed.
 constexpr int kFoldBatch = 16;  // region reads in flight per thread
+template <typename T>
+__device__ const T kZeroValue = T(0);
 constexpr int kFoldZeroPasses = 4;  // zeroing workgroups: passes of the threads over tiles
 constexpr int kFoldPairsLds = 512;  // a tile's pair list staged in LDS up to this length
 
@@ -1897,8 +1924,8 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
     __shared__ int2 pairs_lds[kFoldPairsLds];
     const Located loc = locate(insts, members, prefix, cnt);
     const WinInst &wi = *loc.w;
-    const T *__restrict__ src =
-        static_cast<const T *>(wi.n_regions != wi.n_nonempty ? wi.treg : wi.priv);
+    const global_ptr<T> src =
+        as_global(static_cast<const T *>(wi.n_regions != wi.n_nonempty ? wi.treg : wi.priv));
     T *__restrict__ grid = static_cast<T *>(wi.grid);
     const int n = wi.n, tile = wi.tile, tpd = wi.tpd, vol = wi.vol;
     const int L = tile + wi.width - 1;
@@ -1934,6 +1961,7 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
         __syncthreads();
     }
     auto pair_at = [&](int q) { return staged ? pairs_lds[q - p0] : wi.fold_pairs[q]; };
+    const global_ptr<long long> fpairs = as_global(reinterpret_cast<const long long *>(wi.fold_pairs));
     // sum over regions first, first + stride, ... of cell c
     auto cell_sum = [&](int c, int first, int stride) {
         const int cx = c % tile;
@@ -1944,19 +1972,34 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
             // each region element lands on one grid point: at most one read
             // per region; kFoldBatch regions' reads in flight, added in order
             for (int p = first; p < p1; p += kFoldBatch * stride) {
+                // the batch's pairs first (from LDS, or from global memory
+                // when the list did not fit): waiting for them then waits
+                // for no region read, and the region reads go out together
+                int2 prs[kFoldBatch];
+                if (staged) {
+#pragma unroll
+                    for (int u = 0; u < kFoldBatch; ++u) prs[u] = pairs_lds[min(p + u * stride, p1 - 1) - p0];
+                } else {
+#pragma unroll
+                    for (int u = 0; u < kFoldBatch; ++u) {
+                        const long long w = fpairs[min(p + u * stride, p1 - 1)];  // {x, y}, x low
+                        prs[u] = make_int2((int)(unsigned)w, (int)(w >> 32));
+                    }
+                }
+                // a lane whose grid point the region misses reads a zero, so
+                // the loads carry no condition and nothing consumes one
+                // before the last is issued
                 T v[kFoldBatch];
 #pragma unroll
                 for (int u = 0; u < kFoldBatch; ++u) {
-                    v[u] = T(0);
                     const int q = p + u * stride;
-                    if (q < p1) {
-                        const int2 pr = pair_at(q);
-                        const int ex = (((pr.y & 1023) + cx) & (n - 1));
-                        const int ey = DA >= 2 ? ((((pr.y >> 10) & 1023) + cy) & (n - 1)) : 0;
-                        const int ez = DA == 3 ? ((((pr.y >> 20) & 1023) + cz) & (n - 1)) : 0;
-                        if (ex < L && ey < L && ez < L)
-                            v[u] = src[(size_t)pr.x * vol + ez * L2 + ey * L + ex];
-                    }
+                    const int2 pr = prs[u];
+                    const int ex = (((pr.y & 1023) + cx) & (n - 1));
+                    const int ey = DA >= 2 ? ((((pr.y >> 10) & 1023) + cy) & (n - 1)) : 0;
+                    const int ez = DA == 3 ? ((((pr.y >> 20) & 1023) + cz) & (n - 1)) : 0;
+                    const bool in = q < p1 && ex < L && ey < L && ez < L;
+                    const global_ptr<T> at = src + ((size_t)pr.x * vol + ez * L2 + ey * L + ex);
+                    v[u] = *(in ? at : as_global(&kZeroValue<T>));
                 }
 #pragma unroll
                 for (int u = 0; u < kFoldBatch; ++u) s += (double)v[u];
@@ -1964,7 +2007,7 @@ __global__ __launch_bounds__(kBlock) void fold_kernel(const WinInst *__restrict_
         } else {
             for (int p = first; p < p1; p += stride) {
                 const int2 pr = pair_at(p);
-                const T *reg = src + (size_t)pr.x * vol;
+                const global_ptr<T> reg = src + (size_t)pr.x * vol;
                 const int bx = pr.y & 1023, by = (pr.y >> 10) & 1023, bz = (pr.y >> 20) & 1023;
                 const int ex0 = (bx + cx) & (n - 1);
                 const int ey0 = DA >= 2 ? (by + cy) & (n - 1) : 0;
