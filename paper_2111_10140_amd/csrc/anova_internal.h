@@ -283,7 +283,7 @@ struct WinInst {
     void *grid;                 // n^dA grid
     void *tmp;                  // sorted coefficients (per-point spread), then
                                 // interpolated values in the caller's order
-    int32_t n, tile, tpd, pad0;
+    int32_t n, tile, tpd, chunks;  // chunks: per-cell mode's workgroups per tile (every tile alike)
     int32_t vol, n_sub, n_nonempty, n_tiles;
     int32_t n_regions, N, dA, width;
     int32_t fold_act, fold_len;  // entries of fold_tiles: tiles with regions, all

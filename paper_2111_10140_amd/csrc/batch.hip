@@ -66,6 +66,7 @@ void fill_inst(WinInst &wi, const WindowPlan &w, const double *alpha, void *grid
     wi.N = (int32_t)w.n_points;
     wi.dA = w.dA;
     wi.width = 2 * w.m;
+    wi.chunks = w.dense ? w.chunks : 0;
 }
 
 }  // namespace

@@ -357,24 +357,21 @@ __device__ __forceinline__ void chunk_range(int cs, int ce, int k, int K, int &b
 
 // Workgroup lb of a per-cell launch: its non-empty tile k (chunk_start =
 // src_sub, ascending), its chunk inside the tile and the tile's chunk count.
-// Plans give every tile of a window the same count, so k = lb / count is
-// tried first (checked against the starts, a search over them otherwise):
-// two dependent loads instead of one per halving of the tile list.
-__device__ __forceinline__ void locate_chunk(const int32_t *__restrict__ cstart, int n_ne, int lb,
-                                             int &k, int &chunk, int &K) {
-    int lo = -1;
-    const int k1 = __builtin_amdgcn_readfirstlane(cstart[1] - cstart[0]);
-    if (k1 > 0) {
-        const int kk = min(lb / k1, n_ne - 1);
-        if (cstart[kk] <= lb && lb < cstart[kk + 1]) lo = kk;
+// Plans give every tile of a window the same count (chunks > 0), so the
+// tile is lb / chunks with no load at all; a search over the starts
+// otherwise.
+__device__ __forceinline__ void locate_chunk(const int32_t *__restrict__ cstart, int n_ne, int chunks,
+                                             int lb, int &k, int &chunk, int &K) {
+    if (chunks > 0) {
+        k = __builtin_amdgcn_readfirstlane(lb / chunks);
+        K = chunks;
+        chunk = lb - k * chunks;
+        return;
     }
-    if (lo < 0) {
-        lo = 0;
-        int hi = n_ne;  // cstart[lo] <= lb < cstart[hi]
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (cstart[mid] <= lb) lo = mid; else hi = mid;
-        }
+    int lo = 0, hi = n_ne;  // cstart[lo] <= lb < cstart[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cstart[mid] <= lb) lo = mid; else hi = mid;
     }
     k = __builtin_amdgcn_readfirstlane(lo);
     const int c0 = __builtin_amdgcn_readfirstlane(cstart[k]);
@@ -423,7 +420,7 @@ __global__ __launch_bounds__(kBlock) void spread_cell_kernel(const WinInst *__re
     WinPoly<float, W> wp;
     wp.load(static_cast<const float *>(wi.poly));
     int tk, chunk, K;
-    locate_chunk(wi.src_sub, wi.n_nonempty, loc.lb, tk, chunk, K);
+    locate_chunk(wi.src_sub, wi.n_nonempty, wi.chunks, loc.lb, tk, chunk, K);
     const int key0 = wi.tiles_ne[tk] * CELLS;
     const int cell = threadIdx.x / S, split = (int)(threadIdx.x % S);
     int pb, pe;
@@ -564,7 +561,7 @@ __global__ __launch_bounds__(kBlock) void gather_cell_kernel(const WinInst *__re
     float *__restrict__ tmp = static_cast<float *>(wi.tmp);
     const int n = wi.n, tpd = wi.tpd;
     int tk, chunk, K;
-    locate_chunk(wi.src_sub, wi.n_nonempty, loc.lb, tk, chunk, K);
+    locate_chunk(wi.src_sub, wi.n_nonempty, wi.chunks, loc.lb, tk, chunk, K);
     const int tile_id = wi.tiles_ne[tk];
     const int key0 = tile_id * CELLS;
     const int ox = (tile_id % tpd) * TILE;
@@ -698,7 +695,7 @@ __global__ __launch_bounds__(kBlock, 2) void spread_cell64_kernel(const WinInst 
     WinPoly<double, W, kPolyDegCell64> wp;
     wp.load(static_cast<const double *>(wi.poly));
     int tk, chunk, K;
-    locate_chunk(wi.src_sub, wi.n_nonempty, loc.lb, tk, chunk, K);
+    locate_chunk(wi.src_sub, wi.n_nonempty, wi.chunks, loc.lb, tk, chunk, K);
     const int key0 = wi.tiles_ne[tk] * CELLS;
     const int cell = threadIdx.x / 4, sub = threadIdx.x % 4;
     const int sz = sub >> 1, sy = sub & 1;
@@ -830,7 +827,7 @@ __global__ __launch_bounds__(kBlock, 2) void gather_cell64_kernel(const WinInst 
     wp.load(static_cast<const double *>(wi.poly));
     const int n = wi.n, tpd = wi.tpd;
     int tk, chunk, K;
-    locate_chunk(wi.src_sub, wi.n_nonempty, loc.lb, tk, chunk, K);
+    locate_chunk(wi.src_sub, wi.n_nonempty, wi.chunks, loc.lb, tk, chunk, K);
     const int tile_id = wi.tiles_ne[tk];
     const int key0 = tile_id * CELLS;
     const int ox = (tile_id % tpd) * TILE;
@@ -1139,7 +1136,7 @@ __global__ __launch_bounds__(kWideThreads, 2) void spread_wide_kernel(
     hp.load(static_cast<const float *>(wi.poly));
     for (int e = threadIdx.x; e < VOL; e += NT) acc_lds[e] = 0ull;
     int tk, chunk, K;
-    locate_chunk(wi.src_sub, wi.n_nonempty, loc.lb, tk, chunk, K);
+    locate_chunk(wi.src_sub, wi.n_nonempty, wi.chunks, loc.lb, tk, chunk, K);
     const int key0 = wi.tiles_ne[tk] * kWideCells;
     wide_cells(wi, key0, chunk, K, cs);  // its barriers also order the zero fill
     // the scale, from the largest |coefficient| over the tile's points (a
@@ -1326,7 +1323,7 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
     hp.load(static_cast<const float *>(wi.poly));
     const int n = wi.n, tpd = wi.tpd;
     int tk, chunk, K;
-    locate_chunk(wi.src_sub, wi.n_nonempty, loc.lb, tk, chunk, K);
+    locate_chunk(wi.src_sub, wi.n_nonempty, wi.chunks, loc.lb, tk, chunk, K);
     const int tile_id = wi.tiles_ne[tk];
     const int ox = (tile_id % tpd) * T;
     const int oy = ((tile_id / tpd) % tpd) * T;
@@ -1480,6 +1477,28 @@ __device__ __forceinline__ void mfma_stage(const WinPoly<float, W> &hp, float3 r
     for (int a = 0; a < W; ++a) st[32 + a] = w[a];
 }
 
+// Compact staging (spreading): the W weights of each axis unpadded (z, then
+// x, then y multiplied by ya), then the cell offsets lx | ly << 8; a lane
+// applies the offsets when it reads.  An odd stride keeps the lanes'
+// staging writes in different LDS banks.
+constexpr int kSpreadStride = 37;
+template <int W>
+__device__ __forceinline__ void mfma_stage_compact(const WinPoly<float, W> &hp, float3 r, int lx, int ly,
+                                                   float ya, float *st) {
+    static_assert(3 * W + 1 <= kSpreadStride, "a point's weights fit its slot");
+    float w[W];
+    hp.eval(r.z, w);
+#pragma unroll
+    for (int a = 0; a < W; ++a) st[a] = w[a];
+    hp.eval(r.x, w);
+#pragma unroll
+    for (int a = 0; a < W; ++a) st[W + a] = w[a];
+    hp.eval(r.y, w);
+#pragma unroll
+    for (int a = 0; a < W; ++a) st[2 * W + a] = ya * w[a];
+    st[3 * W] = __int_as_float(lx | ly << 8);
+}
+
 __device__ __forceinline__ void mfma_stage_zero(float *st) {
     float4 *v = reinterpret_cast<float4 *>(st);
 #pragma unroll
@@ -1536,7 +1555,7 @@ struct MfmaTile {
 };
 __device__ __forceinline__ MfmaTile mfma_tile(const WinInst &wi, int lb) {
     int tk, chunk, K;
-    locate_chunk(wi.src_sub, wi.n_nonempty, lb, tk, chunk, K);
+    locate_chunk(wi.src_sub, wi.n_nonempty, wi.chunks, lb, tk, chunk, K);
     const int tile_id = wi.tiles_ne[tk], tpd = wi.tpd;
     MfmaTile t;
     t.ox = (tile_id % tpd) * kWideTile;
@@ -1575,7 +1594,7 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(
     const int32_t *__restrict__ prefix, int cnt) {
     constexpr int L = MfmaRegion<W>::L, VOL = L * L * L, NWV = kMfmaThreads / 64;
     constexpr int LAYER = kWideTile * kWideTile;  // cells per z layer
-    constexpr int STAGE = NWV * kMfmaRound * kMfmaStride, PLANES = 2 * L * 256;
+    constexpr int STAGE = NWV * kMfmaRound * kSpreadStride, PLANES = 2 * L * 256;
     static_assert(NWV == kWideTile, "one wave per cell layer");
     __shared__ __align__(16) float lds[STAGE > PLANES ? STAGE : PLANES];
     const Located loc = locate(insts, members, prefix, cnt);
@@ -1592,7 +1611,7 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(
     int q0, q1;
     chunk_range(wi.cell_start[tl.key0 + LAYER * wv], wi.cell_start[tl.key0 + LAYER * (wv + 1)],
                 tl.chunk, tl.K, q0, q1);
-    float *wst = lds + wv * (kMfmaRound * kMfmaStride);
+    float *wst = lds + wv * (kMfmaRound * kSpreadStride);
     mfma_f4 acc[L];
 #pragma unroll
     for (int c = 0; c < L; ++c) acc[c] = mfma_f4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -1600,25 +1619,33 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(
         constexpr int Z0 = decltype(z0c)::value;
         for (int base = q0; base < q1; base += kMfmaRound) {
             const int kn = min(kMfmaRound, q1 - base);
-            float *st = wst + lane * kMfmaStride;
+            float *st = wst + lane * kSpreadStride;
             wave_lds_sync();  // the previous round's reads come first
             if (lane < kn) {
                 const int j = base + lane;
                 const float4 nd = *reinterpret_cast<const float4 *>(nodes + j);
                 const uint32_t cb = __float_as_uint(nd.w);
                 const int lx = (int)(cb & 1023u) - tl.ox, ly = (int)((cb >> 10) & 1023u) - tl.oy;
-                mfma_stage(hp, make_float3(nd.x, nd.y, nd.z), lx, ly, (float)alpha[perm[j]], st);
+                mfma_stage_compact(hp, make_float3(nd.x, nd.y, nd.z), lx, ly, (float)alpha[perm[j]], st);
             } else {
-                mfma_stage_zero(st);  // a step's missing points add zero
+#pragma unroll
+                for (int q = 0; q < 3 * W + 1; ++q) st[q] = 0.0f;  // a step's missing points add zero
             }
             wave_lds_sync();
             for (int k0 = 0; k0 < kn; k0 += 4) {
-                // lanes of group g hold the step's point g: A column g, B row g
-                const float *sp = wst + (k0 + g) * kMfmaStride;
-                const float xb = sp[col], ya = sp[16 + col];
+                // lanes of group g hold the step's point g: A column g (row
+                // y = col), B row g (column x = col), each the point's weight
+                // at that offset from its cell, zero outside the support
+                const float *sp = wst + (k0 + g) * kSpreadStride;
+                const int lxy = __float_as_int(sp[3 * W]);
+                const int dx = col - (lxy & 255), dy = col - (lxy >> 8);
+                const float wxv = sp[W + min(max(dx, 0), W - 1)];
+                const float wyv = sp[2 * W + min(max(dy, 0), W - 1)];
+                const float xb = (unsigned)dx < (unsigned)W ? wxv : 0.0f;
+                const float ya = (unsigned)dy < (unsigned)W ? wyv : 0.0f;
 #pragma unroll
                 for (int c = Z0; c < Z0 + W; ++c)
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya * sp[32 + c - Z0], xb, acc[c], 0, 0, 0);
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(ya * sp[c - Z0], xb, acc[c], 0, 0, 0);
             }
         }
     };
