@@ -1438,15 +1438,14 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
 // result registers hold D[4 (l / 16) + r][l % 16].
 //
 // One lane evaluates a point's weights and stages them in LDS for its wave
-// (x and y zero-padded to 16 at the cell's offset, z unpadded); each wave
-// takes a contiguous quarter of the workgroup's points.  A tile's points are
-// sorted by cell, z slowest, so a run of them mostly shares one z layer and
-// touches W of the 15 planes: each step computes the planes its points can
-// touch and skips the rest.  Compared with the per-cell kernels there are no
-// atomics: a wave's sums stay in its result registers until the end, where
-// the four waves' regions are added in a fixed order.
-constexpr int kMfmaThreads = 256, kMfmaRound = 64;
-constexpr int kMfmaStride = 44;  // floats per staged point: x 16, y 16, z 12
+// (each axis's W weights and the point's cell offsets in the tile); a lane
+// of the instruction reads the weight at its own row or column, which is
+// zero outside the point's support.  A tile's points are sorted by cell, z
+// slowest, so a run of them mostly shares one z layer and touches W of the
+// 15 planes.  Compared with the per-cell kernels there are no atomics: a
+// wave's sums stay in its result registers until the end, where the four
+// waves' regions are added in a fixed order.
+constexpr int kMfmaThreads = 256, kMfmaRound = 64;  // points a wave stages at once
 typedef float mfma_f4 __attribute__((ext_vector_type(4)));
 
 template <int W>
@@ -1457,30 +1456,10 @@ struct MfmaRegion {
     static_assert(L - W == 3, "four z layers of cells per tile");
 };
 
-// Stage one point: its x and y weights at offsets lx, ly of zero-padded
-// 16-vectors (y multiplied by ya), then its W z weights.
-template <int W>
-__device__ __forceinline__ void mfma_stage(const WinPoly<float, W> &hp, float3 r, int lx, int ly,
-                                           float ya, float *st) {
-    float4 *v = reinterpret_cast<float4 *>(st);
-#pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    float w[W];
-    hp.eval(r.x, w);
-#pragma unroll
-    for (int a = 0; a < W; ++a) st[lx + a] = w[a];
-    hp.eval(r.y, w);
-#pragma unroll
-    for (int a = 0; a < W; ++a) st[16 + ly + a] = ya * w[a];
-    hp.eval(r.z, w);
-#pragma unroll
-    for (int a = 0; a < W; ++a) st[32 + a] = w[a];
-}
-
-// Compact staging (spreading): the W weights of each axis unpadded (z, then
-// x, then y multiplied by ya), then the cell offsets lx | ly << 8; a lane
-// applies the offsets when it reads.  An odd stride keeps the lanes'
-// staging writes in different LDS banks.
+// Staging of one point: the W weights of each axis (z, then x, then y
+// multiplied by ya), then the cell offsets lx | ly << 8; a lane applies the
+// offsets when it reads.  An odd stride keeps the lanes' staging writes in
+// different LDS banks.
 constexpr int kSpreadStride = 37;
 template <int W>
 __device__ __forceinline__ void mfma_stage_compact(const WinPoly<float, W> &hp, float3 r, int lx, int ly,
@@ -1497,12 +1476,6 @@ __device__ __forceinline__ void mfma_stage_compact(const WinPoly<float, W> &hp, 
 #pragma unroll
     for (int a = 0; a < W; ++a) st[2 * W + a] = ya * w[a];
     st[3 * W] = __int_as_float(lx | ly << 8);
-}
-
-__device__ __forceinline__ void mfma_stage_zero(float *st) {
-    float4 *v = reinterpret_cast<float4 *>(st);
-#pragma unroll
-    for (int q = 0; q < kMfmaStride / 4; ++q) v[q] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 // LDS written by one lane of a wave and then read by others: LDS operations
@@ -1531,20 +1504,6 @@ __device__ __forceinline__ void mfma_planes(int zlo, int zhi, F &&f) {
         }
     }
     f(integral_constant<int, 0>{}, integral_constant<int, L>{});
-}
-
-// z weight of plane c for a point of layer lz staged at sp: constant slot
-// when the step's points all start at plane Z0, else looked up and zero
-// outside the support.
-template <int W, int Z0, int NZ>
-__device__ __forceinline__ float mfma_zweight(const float *sp, int c, int lz) {
-    if constexpr (NZ == W) {
-        return sp[32 + c - Z0];
-    } else {
-        const int d = c - lz;
-        const float v = sp[32 + min(max(d, 0), W - 1)];
-        return (unsigned)d < (unsigned)W ? v : 0.0f;
-    }
 }
 
 // The workgroup's tile (origin cell) and its points: a contiguous share of
@@ -1680,15 +1639,19 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(
     }
 }
 
+// Gathering stages each point the same way, with lz << 16 added to the cell
+// offsets and the caller's index after them.
+constexpr int kGatherStride = 39;
+
 template <int W>
-__global__ __launch_bounds__(kMfmaThreads) void gather_mfma_kernel(
+__global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(4))) void gather_mfma_kernel(
     const WinInst *__restrict__ insts, const int32_t *__restrict__ members,
     const int32_t *__restrict__ prefix, int cnt) {
     constexpr int L = MfmaRegion<W>::L, NWV = kMfmaThreads / 64, m = W / 2;
     constexpr int RS = 20, PS = 16 * RS;  // LDS row and plane strides of the region
-    constexpr int STAGE = NWV * kMfmaRound * kMfmaStride, PLANES = L * PS;
+    constexpr int STAGE = NWV * kMfmaRound * kGatherStride, PLANES = L * PS;
+    static_assert(3 * W + 2 <= kGatherStride, "a point's record fits its slot");
     __shared__ __align__(16) float lds[STAGE > PLANES ? STAGE : PLANES];
-    __shared__ int lzs[NWV * kMfmaRound], idx[NWV * kMfmaRound];
     const Located loc = locate(insts, members, prefix, cnt);
     const WinInst &wi = *loc.w;
     const NodeF32 *__restrict__ nodes = static_cast<const NodeF32 *>(wi.nodes);
@@ -1723,53 +1686,72 @@ __global__ __launch_bounds__(kMfmaThreads) void gather_mfma_kernel(
     __syncthreads();  // the region's LDS becomes staging space
     int q0, q1;
     mfma_wave_share(tl, wv, 16, q0, q1);
-    float *wst = lds + wv * (kMfmaRound * kMfmaStride);
-    int *wlz = lzs + wv * kMfmaRound;
-    int *widx = idx + wv * kMfmaRound;
+    float *wst = lds + wv * (kMfmaRound * kGatherStride);
     for (int base = q0; base < q1; base += kMfmaRound) {
         const int kn = min(kMfmaRound, q1 - base);
-        float *st = wst + lane * kMfmaStride;
+        float *st = wst + lane * kGatherStride;
         wave_lds_sync();
         if (lane < kn) {
             const int j = base + lane;
             const float4 nd = *reinterpret_cast<const float4 *>(nodes + j);
             const uint32_t cb = __float_as_uint(nd.w);
             const int lx = (int)(cb & 1023u) - tl.ox, ly = (int)((cb >> 10) & 1023u) - tl.oy;
-            wlz[lane] = (int)((cb >> 20) & 1023u) - tl.oz;
-            widx[lane] = perm[j];
-            mfma_stage(hp, make_float3(nd.x, nd.y, nd.z), lx, ly, 1.0f, st);
+            const int lz = (int)((cb >> 20) & 1023u) - tl.oz;
+            mfma_stage_compact(hp, make_float3(nd.x, nd.y, nd.z), lx, ly | lz << 8, 1.0f, st);
+            st[3 * W + 1] = __int_as_float(perm[j]);
         } else {
-            mfma_stage_zero(st);
+#pragma unroll
+            for (int q = 0; q < 3 * W + 1; ++q) st[q] = 0.0f;  // reads zero weights
         }
         wave_lds_sync();
         for (int kb = 0; kb < kn; kb += 16) {
-            // lane l takes point kb + l % 16 (B column and result column)
+            // lane l takes point kb + l % 16 (B column and result column):
+            // its x weights at x = 4 g + s and y weights at rows 4 g + r,
+            // each at that offset from its cell, zero outside the support
             const int p = kb + col;
-            const float *sp = wst + p * kMfmaStride;
-            const float4 xv = *reinterpret_cast<const float4 *>(sp + 4 * g);
-            const float4 yv = *reinterpret_cast<const float4 *>(sp + 16 + 4 * g);
-            const int lzp = wlz[min(p, kn - 1)];
-            const int zlo = __builtin_amdgcn_readfirstlane(wlz[kb]);
-            const int zhi = __builtin_amdgcn_readfirstlane(wlz[min(kb + 15, kn - 1)]) + W;
+            const float *sp = wst + p * kGatherStride;
+            const int lxyz = __float_as_int(sp[3 * W]);
+            const int lx = lxyz & 255, ly = (lxyz >> 8) & 255, lzp = lxyz >> 16;
+            float xs[4], ys[4];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const int dx = 4 * g + s - lx, dy = 4 * g + s - ly;
+                const float wxv = sp[W + min(max(dx, 0), W - 1)];
+                const float wyv = sp[2 * W + min(max(dy, 0), W - 1)];
+                xs[s] = (unsigned)dx < (unsigned)W ? wxv : 0.0f;
+                ys[s] = (unsigned)dy < (unsigned)W ? wyv : 0.0f;
+            }
+            // the block's planes: its points are sorted by z layer
+            const int zlo = __builtin_amdgcn_readfirstlane(__float_as_int(wst[kb * kGatherStride + 3 * W]) >> 16);
+            const int zhi = __builtin_amdgcn_readfirstlane(
+                                __float_as_int(wst[min(kb + 15, kn - 1) * kGatherStride + 3 * W]) >> 16) + W;
             float part = 0.0f;
             mfma_planes<W>(zlo, zhi, [&](auto z0c, auto nzc) {
                 constexpr int Z0 = decltype(z0c)::value, NZ = decltype(nzc)::value;
 #pragma unroll
                 for (int c = Z0; c < Z0 + NZ; ++c) {
                     mfma_f4 t = {0.0f, 0.0f, 0.0f, 0.0f};
-                    t = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[c].x, xv.x, t, 0, 0, 0);
-                    t = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[c].y, xv.y, t, 0, 0, 0);
-                    t = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[c].z, xv.z, t, 0, 0, 0);
-                    t = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[c].w, xv.w, t, 0, 0, 0);
+                    t = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[c].x, xs[0], t, 0, 0, 0);
+                    t = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[c].y, xs[1], t, 0, 0, 0);
+                    t = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[c].z, xs[2], t, 0, 0, 0);
+                    t = __builtin_amdgcn_mfma_f32_16x16x4f32(gv[c].w, xs[3], t, 0, 0, 0);
                     // rows 4 g + r of the plane, weighted by y, then by z
-                    const float s = fmaf(yv.x, t[0], fmaf(yv.y, t[1], fmaf(yv.z, t[2], yv.w * t[3])));
-                    part = fmaf(mfma_zweight<W, Z0, NZ>(sp, c, lzp), s, part);
+                    const float s = fmaf(ys[0], t[0], fmaf(ys[1], t[1], fmaf(ys[2], t[2], ys[3] * t[3])));
+                    float wz;
+                    if constexpr (NZ == W) {
+                        wz = sp[c - Z0];
+                    } else {
+                        const int d = c - lzp;
+                        const float v = sp[min(max(d, 0), W - 1)];
+                        wz = (unsigned)d < (unsigned)W ? v : 0.0f;
+                    }
+                    part = fmaf(wz, s, part);
                 }
             });
             // the four row groups of the point, in the same order in every lane
             part += __shfl_xor(part, 16, 64);
             part += __shfl_xor(part, 32, 64);
-            if (g == 0 && p < kn) tmp[widx[p]] = part;  // caller order
+            if (g == 0 && p < kn) tmp[__float_as_int(sp[3 * W + 1])] = part;  // caller order
         }
     }
 }
