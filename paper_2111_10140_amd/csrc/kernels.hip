@@ -155,6 +155,31 @@ __device__ __forceinline__ global_ptr<T> as_global(const T *p) {
     return (global_ptr<T>)p;
 }
 
+// A zero in global memory: a lane with nothing to read loads it, so that
+// loads need no condition and all of a batch go out before the first wait.
+template <typename T>
+__device__ const T kZeroValue = T(0);
+template <typename T>
+__device__ __forceinline__ T load_or_zero(global_ptr<T> p, bool ok) {
+    return *(ok ? p : as_global(&kZeroValue<T>));
+}
+
+// Thread-strided fill of count LDS entries from global memory, U loads in
+// flight per thread: load(e) reads entry e through a global view and is
+// called for every e of a round (indices past the end clamped to the last,
+// read again and dropped) before store(e, v) writes the round's entries.
+template <int U, typename T, typename Load, typename Store>
+__device__ __forceinline__ void fill_lds(int count, int nthreads, Load load, Store store) {
+    for (int e0 = (int)threadIdx.x; e0 < count; e0 += U * nthreads) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = load(min(e0 + u * nthreads, count - 1));
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (e0 + u * nthreads < count) store(e0 + u * nthreads, v[u]);
+    }
+}
+
 // Periodic index on a grid of n points: n is a power of two (the plan
 // requires it), so the two's-complement mask also wraps negative g.
 __device__ __forceinline__ int wrap_index(int g, int n) { return g & (n - 1); }
@@ -567,13 +592,16 @@ __global__ __launch_bounds__(kBlock) void gather_cell_kernel(const WinInst *__re
     const int ox = (tile_id % tpd) * TILE;
     const int oy = ((tile_id / tpd) % tpd) * TILE;
     const int oz = (tile_id / (tpd * tpd)) * TILE;
-    for (int e = threadIdx.x; e < VOL; e += kBlock) {
-        const int ex = e % L;
-        size_t g = (size_t)wrap_index(ox - m + 1 + ex, n);
-        if constexpr (DA >= 2) g += (size_t)n * (size_t)wrap_index(oy - m + 1 + (e / L) % L, n);
-        if constexpr (DA == 3) g += (size_t)n * (size_t)n * (size_t)wrap_index(oz - m + 1 + e / L2, n);
-        g_lds[e] = grid[g];
-    }
+    const global_ptr<float> gg = as_global(static_cast<const float *>(grid));
+    fill_lds<4, float>(
+        VOL, kBlock,
+        [&](int e) {
+            size_t g = (size_t)wrap_index(ox - m + 1 + e % L, n);
+            if constexpr (DA >= 2) g += (size_t)n * (size_t)wrap_index(oy - m + 1 + (e / L) % L, n);
+            if constexpr (DA == 3) g += (size_t)n * (size_t)n * (size_t)wrap_index(oz - m + 1 + e / L2, n);
+            return gg[g];
+        },
+        [&](int e, float v) { g_lds[e] = v; });
     __syncthreads();
     const int cell = threadIdx.x / S;
     int pb, pe;
@@ -833,12 +861,16 @@ __global__ __launch_bounds__(kBlock, 2) void gather_cell64_kernel(const WinInst 
     const int ox = (tile_id % tpd) * TILE;
     const int oy = ((tile_id / tpd) % tpd) * TILE;
     const int oz = (tile_id / (tpd * tpd)) * TILE;
-    for (int e = threadIdx.x; e < VOL; e += kBlock) {
-        size_t g = (size_t)wrap_index(ox - m + 1 + e % L, n);
-        g += (size_t)n * (size_t)wrap_index(oy - m + 1 + (e / L) % L, n);
-        g += (size_t)n * (size_t)n * (size_t)wrap_index(oz - m + 1 + e / L2, n);
-        g_lds[e] = grid[g];
-    }
+    const global_ptr<double> gg = as_global(static_cast<const double *>(grid));
+    fill_lds<4, double>(
+        VOL, kBlock,
+        [&](int e) {
+            size_t g = (size_t)wrap_index(ox - m + 1 + e % L, n);
+            g += (size_t)n * (size_t)wrap_index(oy - m + 1 + (e / L) % L, n);
+            g += (size_t)n * (size_t)n * (size_t)wrap_index(oz - m + 1 + e / L2, n);
+            return gg[g];
+        },
+        [&](int e, double v) { g_lds[e] = v; });
     __syncthreads();
     const int cell = threadIdx.x / 4, sub = threadIdx.x % 4;
     const int sz = sub >> 1, sy = sub & 1;
@@ -907,12 +939,11 @@ __global__ __launch_bounds__(kBlock, 2) void gather_cell64_kernel(const WinInst 
 }
 
 // ------------------------------------------------------------------ per-cell, wide supports
-// Supports too wide for one thread's registers (d_A = 3, W = 8 or 12, float
-// 32): SX x SY x SZ adjacent lanes of a cell each own one block of its
-// support (a half, or all, of the offsets along each axis), every lane of
-// the cell walks all of the cell's points, and the z planes of a block may
-// go in several passes over the points so that a pass's sums fit in
-// registers.
+// Supports too wide for one thread's registers (d_A = 3, W = 8, float 32;
+// 12-point supports go to the matrix-core kernels further down): SX x SY
+// adjacent lanes of a cell each own one block of its support (half of the
+// offsets along x and y, all of z), and every lane of the cell walks all of
+// the cell's points.
 //
 // The window is even, so the polynomial of offset W-1-a at z = 2f-1 equals
 // that of offset a at -z.  A lane owning the upper half of an axis indexes
@@ -931,7 +962,6 @@ __global__ __launch_bounds__(kBlock, 2) void gather_cell64_kernel(const WinInst 
 template <int W> struct WideSplit;
 // NPS / NPG: z passes of the spreading / gathering kernel
 template <> struct WideSplit<8> { static constexpr int SX = 2, SY = 2, SZ = 1, NPS = 1, NPG = 1; };
-template <> struct WideSplit<12> { static constexpr int SX = 2, SY = 2, SZ = 2, NPS = 2, NPG = 2; };
 constexpr int kWideTile = 4, kWideCells = 64, kWideThreads = 128;
 
 template <int W>
@@ -1214,7 +1244,8 @@ __global__ __launch_bounds__(kWideThreads, 2) void spread_wide_kernel(
                     ST::half(sxy + k * ST::STRIDE, 0, ln.sx, wx);
                     ST::half(sxy + k * ST::STRIDE, 1, ln.sy, wy);
                     const float zz = sz[k];
-                    if constexpr (SP::SZ == 1 && SP::NPS == 1) {
+                    static_assert(SP::SZ == 1 && SP::NPS == 1, "the whole z axis in one pass");
+                    {
                         // the whole z axis: planes in mirror pairs
                         const float zz2 = zz * zz;
 #pragma unroll
@@ -1232,18 +1263,6 @@ __global__ __launch_bounds__(kWideThreads, 2) void spread_wide_kernel(
                                     for (int i = 0; i < H; ++i)
                                         acc[c][b][i] = fmaf(wbc, wx[i], acc[c][b][i]);
                                 }
-                            }
-                        }
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < PZ; ++c) {
-                            const float wc = AZ::weight(hp, zz, ln.sz, pass * PZ + c);
-#pragma unroll
-                            for (int b = 0; b < H; ++b) {
-                                const float wbc = wc * wy[b];
-#pragma unroll
-                                for (int i = 0; i < H; ++i)
-                                    acc[c][b][i] = fmaf(wbc, wx[i], acc[c][b][i]);
                             }
                         }
                     }
@@ -1281,16 +1300,12 @@ __device__ __forceinline__ float cell_lanes_sum(float v) {
     return v;
 }
 
-// Row and plane strides of the grid tile in the gathering kernel's LDS:
-// the lanes of a cell read their blocks at offsets W/2 (sx + RY sy + RZ sz)
-// floats apart, padded at W = 12 so that these eight offsets fall in eight
-// different LDS banks.
+// Row and plane strides of the grid tile in the gathering kernel's LDS.
 template <int W>
 struct WideGridPad {
     static constexpr int L = kWideTile + W - 1;
-    static constexpr int RY = W == 12 ? L + 3 : L;
-    static constexpr int RZ = W == 12 ? 276 : L * L;
-    static_assert(RY >= L && RZ >= RY * L, "strides cover the tile");
+    static constexpr int RY = L;
+    static constexpr int RZ = L * L;
 };
 
 template <int W>
@@ -1328,12 +1343,16 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
     const int ox = (tile_id % tpd) * T;
     const int oy = ((tile_id / tpd) % tpd) * T;
     const int oz = (tile_id / (tpd * tpd)) * T;
-    for (int e = threadIdx.x; e < VOL; e += NT) {
-        size_t gi = (size_t)wrap_index(ox - m + 1 + e % L, n);
-        gi += (size_t)n * (size_t)wrap_index(oy - m + 1 + (e / L) % L, n);
-        gi += (size_t)n * (size_t)n * (size_t)wrap_index(oz - m + 1 + e / L2, n);
-        g_lds[(e / L2) * RZ + ((e / L) % L) * RY + e % L] = grid[gi];
-    }
+    const global_ptr<float> gg = as_global(grid);
+    fill_lds<4, float>(
+        VOL, NT,
+        [&](int e) {
+            size_t gi = (size_t)wrap_index(ox - m + 1 + e % L, n);
+            gi += (size_t)n * (size_t)wrap_index(oy - m + 1 + (e / L) % L, n);
+            gi += (size_t)n * (size_t)n * (size_t)wrap_index(oz - m + 1 + e / L2, n);
+            return gg[gi];
+        },
+        [&](int e, float v) { g_lds[(e / L2) * RZ + ((e / L) % L) * RY + e % L] = v; });
     wide_cells(wi, tile_id * kWideCells, chunk, K, cs);  // its barriers also order the fill
     const WideLane<W> ln;
     const bool lead = ln.sub == 0;
@@ -1398,8 +1417,8 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
                         }
                         return sc;
                     };
-                    if constexpr (SP::SZ == 1 && SP::NPG == 1) {
-                        // the whole z axis
+                    static_assert(SP::SZ == 1 && SP::NPG == 1, "the whole z axis in one pass");
+                    {
                         float zlo[H], zhi[H];
                         ST::half(ps, 2, 0, zlo);
                         ST::half(ps, 2, 1, zhi);
@@ -1407,12 +1426,6 @@ __global__ __launch_bounds__(kWideThreads, 2) void gather_wide_kernel(
                         for (int c = 0; c < H; ++c) part = fmaf(plane(c), zlo[c], part);
 #pragma unroll
                         for (int c = 0; c < H; ++c) part = fmaf(plane(H + c), zhi[c], part);
-                    } else {
-                        static_assert(SP::SZ == 2, "z split in halves");
-                        float zh[H];
-                        ST::half(ps, 2, ln.sz, zh);
-#pragma unroll
-                        for (int c = 0; c < PZ; ++c) part = fmaf(plane(c), zh[pass * PZ + c], part);
                     }
                     const float v = cell_lanes_sum<TPC>(part);
                     if (lead) cval[k] = pass == 0 ? v : cval[k] + v;
@@ -1553,7 +1566,8 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(
     const int32_t *__restrict__ prefix, int cnt) {
     constexpr int L = MfmaRegion<W>::L, VOL = L * L * L, NWV = kMfmaThreads / 64;
     constexpr int LAYER = kWideTile * kWideTile;  // cells per z layer
-    constexpr int STAGE = NWV * kMfmaRound * kSpreadStride, PLANES = 2 * L * 256;
+    constexpr int FR = 17, FP = 16 * FR;  // row and plane strides of the summed regions
+    constexpr int STAGE = NWV * kMfmaRound * kSpreadStride, PLANES = 2 * L * FP;
     static_assert(NWV == kWideTile, "one wave per cell layer");
     __shared__ __align__(16) float lds[STAGE > PLANES ? STAGE : PLANES];
     const Located loc = locate(insts, members, prefix, cnt);
@@ -1614,28 +1628,30 @@ __global__ __launch_bounds__(kMfmaThreads) void spread_mfma_kernel(
         case 2: run(std::integral_constant<int, 2>{}); break;
         default: run(std::integral_constant<int, 3>{}); break;
     }
-    // the four waves' regions: (0 + 2) + (1 + 3), in the padded layout
+    // the four waves' regions: (0 + 2) + (1 + 3), in a padded layout whose
+    // rows are FR floats apart (a wave's four row groups then write to
+    // different LDS banks)
     __syncthreads();
     if (wv < 2) {
-        float *dst = lds + wv * (L * 256);
+        float *dst = lds + wv * (L * FP);
 #pragma unroll
         for (int c = 0; c < L; ++c)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) dst[c * 256 + (4 * g + r) * 16 + col] = acc[c][r];
+            for (int r = 0; r < 4; ++r) dst[c * FP + (4 * g + r) * FR + col] = acc[c][r];
     }
     __syncthreads();
     if (wv >= 2) {
-        float *dst = lds + (wv - 2) * (L * 256);
+        float *dst = lds + (wv - 2) * (L * FP);
 #pragma unroll
         for (int c = 0; c < L; ++c)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) dst[c * 256 + (4 * g + r) * 16 + col] += acc[c][r];
+            for (int r = 0; r < 4; ++r) dst[c * FP + (4 * g + r) * FR + col] += acc[c][r];
     }
     __syncthreads();
     float *out = static_cast<float *>(wi.priv) + (size_t)loc.lb * VOL;
     for (int e = threadIdx.x; e < VOL; e += kMfmaThreads) {
-        const int i = (e / (L * L)) * 256 + ((e / L) % L) * 16 + e % L;
-        out[e] = lds[i] + lds[L * 256 + i];
+        const int i = (e / (L * L)) * FP + ((e / L) % L) * FR + e % L;
+        out[e] = lds[i] + lds[L * FP + i];
     }
 }
 
@@ -1665,17 +1681,20 @@ __global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(4)
     const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
     const int g = lane >> 4, col = lane & 15;
     // the tile's region of the grid, padded to 16 x 16 planes with zeros
-    // (rows RS apart: the lanes' row reads below then meet fewer LDS banks)
-    for (int e = threadIdx.x; e < L * 256; e += kMfmaThreads) {
-        const int x = e & 15, y = (e >> 4) & 15, z = e >> 8;
-        float v = 0.0f;
-        if (x < L && y < L) {
-            size_t gi = (size_t)wrap_index(tl.ox - m + 1 + x, n);
-            gi += (size_t)n * (size_t)wrap_index(tl.oy - m + 1 + y, n);
-            gi += (size_t)n * (size_t)n * (size_t)wrap_index(tl.oz - m + 1 + z, n);
-            v = grid[gi];
-        }
-        lds[z * PS + y * RS + x] = v;
+    // (rows RS apart: the lanes' row reads below then meet fewer LDS banks):
+    // thread (x, y) loads its column's L planes at once
+    {
+        static_assert(kMfmaThreads == 256, "one thread per (x, y) of a plane");
+        const int x = (int)threadIdx.x & 15, y = (int)threadIdx.x >> 4;
+        const bool in = x < L && y < L;
+        const global_ptr<float> gxy =
+            as_global(grid) + (size_t)wrap_index(tl.ox - m + 1 + min(x, L - 1), n) +
+            (size_t)n * (size_t)wrap_index(tl.oy - m + 1 + min(y, L - 1), n);
+        float v[L];
+#pragma unroll
+        for (int z = 0; z < L; ++z) v[z] = gxy[(size_t)n * (size_t)n * (size_t)wrap_index(tl.oz - m + 1 + z, n)];
+#pragma unroll
+        for (int z = 0; z < L; ++z) lds[z * PS + y * RS + x] = in ? v[z] : 0.0f;
     }
     __syncthreads();
     // A operand of every plane, kept in registers: row col, x = 4 g .. 4 g + 3
@@ -1888,7 +1907,7 @@ __global__ __launch_bounds__(kBlock) void tile_sum_kernel(const WinInst *__restr
     const int k = loc.lb / per;
     const int e = (loc.lb % per) * kBlock + threadIdx.x;
     if (e >= vol) return;
-    const T *__restrict__ priv = static_cast<const T *>(wi.priv);
+    const global_ptr<T> priv = as_global(static_cast<const T *>(wi.priv));
     const int s0 = wi.src_sub[k], s1 = wi.src_sub[k + 1];
     // regions in order, their loads issued eight at a time (a missing one as +0)
     constexpr int B = 8;
@@ -1896,7 +1915,7 @@ __global__ __launch_bounds__(kBlock) void tile_sum_kernel(const WinInst *__restr
     for (int q = s0; q < s1; q += B) {
         T v[B];
 #pragma unroll
-        for (int u = 0; u < B; ++u) v[u] = q + u < s1 ? priv[(size_t)(q + u) * vol + e] : T(0);
+        for (int u = 0; u < B; ++u) v[u] = load_or_zero(priv + ((size_t)(q + u) * vol + e), q + u < s1);
 #pragma unroll
         for (int u = 0; u < B; ++u) s += (double)v[u];
     }
@@ -1911,8 +1930,6 @@ __global__ __launch_bounds__(kBlock) void tile_sum_kernel(const WinInst *__restr
 // congruent to b + c mod n, b the tile origin's offset in the region).
 // Writes every grid point, so no zero fill is needed.
 constexpr int kFoldBatch = 16;  // region reads in flight per thread
-template <typename T>
-__device__ const T kZeroValue = T(0);
 constexpr int kFoldZeroPasses = 4;  // zeroing workgroups: passes of the threads over tiles
 constexpr int kFoldPairsLds = 512;  // a tile's pair list staged in LDS up to this length
 
@@ -2329,8 +2346,9 @@ __global__ __launch_bounds__(kBlock) void convolve_plane_kernel(const WinInst *_
     const WinInst &wi = *loc.w;
     T *__restrict__ plane = static_cast<T *>(wi.grid) + (size_t)loc.lb * NN;
     const T *__restrict__ taps = static_cast<const T *>(wi.ctaps);
-    for (int e = threadIdx.x; e < NN; e += kBlock) a[e] = plane[e];
-    for (int e = threadIdx.x; e < n; e += kBlock) c[e] = taps[e];
+    const global_ptr<T> gp = as_global(plane);
+    fill_lds<(NN + kBlock - 1) / kBlock, T>(NN, kBlock, [&](int e) { return gp[e]; }, [&](int e, T v) { a[e] = v; });
+    if ((int)threadIdx.x < n) c[threadIdx.x] = as_global(taps)[threadIdx.x];
     __syncthreads();
     for (int e = threadIdx.x; e < NN; e += kBlock) {  // along x
         const int x = e & (n - 1), row = e - x;
@@ -2360,8 +2378,11 @@ __global__ __launch_bounds__(kBlock) void convolve_z_kernel(const WinInst *__res
     const WinInst &wi = *loc.w;
     T *__restrict__ col = static_cast<T *>(wi.grid) + (size_t)loc.lb * n;  // y = workgroup
     const T *__restrict__ taps = static_cast<const T *>(wi.ctaps);
-    for (int e = threadIdx.x; e < NN; e += kBlock) a[e] = col[(size_t)(e >> LOGN) * NN + (e & (n - 1))];
-    for (int e = threadIdx.x; e < n; e += kBlock) c[e] = taps[e];
+    const global_ptr<T> gc = as_global(col);
+    fill_lds<(NN + kBlock - 1) / kBlock, T>(
+        NN, kBlock, [&](int e) { return gc[(size_t)(e >> LOGN) * NN + (e & (n - 1))]; },
+        [&](int e, T v) { a[e] = v; });
+    if ((int)threadIdx.x < n) c[threadIdx.x] = as_global(taps)[threadIdx.x];
     __syncthreads();
     for (int e = threadIdx.x; e < NN; e += kBlock) {
         const int x = e & (n - 1), z = e >> LOGN;
@@ -2393,24 +2414,41 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(const CombInst *__restr
     const int q = __builtin_amdgcn_readfirstlane(find_member(prefix, cnt, blockIdx.x));
     const CombInst ci = cis[q];
     const int i0 = (blockIdx.x - prefix[q]) * kCombineSpan + threadIdx.x;
-    double s[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-        const int i = i0 + e * kBlock;
-        s[e] = i < ci.N ? (ci.accumulate ? ci.out[i] : ci.alpha ? ci.beta * ci.alpha[i] : 0.0)
-                        : 0.0;
-    }
-    for (int l = 0; l < ci.P; ++l) {
-        const CombineWin cw = wins[ci.win0 + l];
-        const T *__restrict__ tmp = static_cast<const T *>(cw.tmp);
-        T v[E];
+    double s[E], av[E];  // av: alpha, kept for the CG partial sum below
+    {
+        const global_ptr<double> ga = as_global(ci.alpha), go = as_global(ci.out);
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const int i = i0 + e * kBlock;
-            v[e] = i < ci.N ? tmp[i] : T(0);
+            av[e] = load_or_zero(ga + i, ci.alpha != nullptr && i < ci.N);
+            const double o = load_or_zero(go + i, ci.accumulate && i < ci.N);
+            s[e] = ci.accumulate ? o : ci.beta * av[e];
+        }
+    }
+    // windows four at a time: their values' loads all go out before the
+    // sums, which add the windows in order
+    constexpr int PB = 4;
+    for (int l0 = 0; l0 < ci.P; l0 += PB) {
+        double eta[PB];
+        T v[PB][E];
+#pragma unroll
+        for (int u = 0; u < PB; ++u) {
+            const bool has = l0 + u < ci.P;
+            const CombineWin cw = wins[ci.win0 + min(l0 + u, ci.P - 1)];
+            eta[u] = has ? cw.eta : 0.0;
+            const global_ptr<T> tmp = as_global(static_cast<const T *>(cw.tmp));
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int i = i0 + e * kBlock;
+                v[u][e] = load_or_zero(tmp + i, has && i < ci.N);
+            }
         }
 #pragma unroll
-        for (int e = 0; e < E; ++e) s[e] += cw.eta * (double)v[e];
+        for (int u = 0; u < PB; ++u)
+            if (l0 + u < ci.P) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) s[e] += eta[u] * (double)v[u][e];
+            }
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -2425,7 +2463,7 @@ __global__ __launch_bounds__(kBlock) void combine_kernel(const CombInst *__restr
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         const int i = i0 + e * kBlock;
-        if (i < ci.N) v += ci.alpha[i] * s[e];
+        if (i < ci.N) v += av[e] * s[e];
     }
     v = block_sum_f64(v, red);
     if (threadIdx.x == 0) ci.hook.partial[blockIdx.x - prefix[q]] = v;
