@@ -517,4 +517,25 @@ void timed_launch(anova_plan_s *p, int kind, hipStream_t s, F &&launch) {
     p->timed.push_back({kind, a, b});
 }
 
+// ---------------------------------------------------------------- device loads
+// A device pointer read from an instance record is generic to the compiler,
+// so loads through it are flat loads, which also count against the LDS
+// wait counter: waiting for an LDS read then waits for them too.  Loads
+// through the global view are global loads, waited for on their own.
+template <typename T>
+using global_ptr = const __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ global_ptr<T> as_global(const T *p) {
+    return (global_ptr<T>)p;
+}
+
+// A zero in global memory: a lane with nothing to read loads it, so that
+// loads need no condition and all of a batch go out before the first wait.
+template <typename T>
+__device__ const T kZeroValue = T(0);
+template <typename T>
+__device__ __forceinline__ T load_or_zero(global_ptr<T> p, bool ok) {
+    return *(ok ? p : as_global(&kZeroValue<T>));
+}
+
 }  // namespace anova

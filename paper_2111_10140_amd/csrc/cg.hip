@@ -95,7 +95,7 @@ __device__ double sum_partials(const double *__restrict__ partial, int nblk, dou
     for (int i = threadIdx.x; i < nblk; i += B * kRedBlock) {
         double t[B];
 #pragma unroll
-        for (int u = 0; u < B; ++u) t[u] = i + u * kRedBlock < nblk ? partial[i + u * kRedBlock] : 0.0;
+        for (int u = 0; u < B; ++u) t[u] = load_or_zero(as_global(partial) + (i + u * kRedBlock), i + u * kRedBlock < nblk);
 #pragma unroll
         for (int u = 0; u < B; ++u) v += t[u];
     }

@@ -144,26 +144,6 @@ __device__ __forceinline__ float3 node_offsets(const NodeF32 *__restrict__ p) {
     return *reinterpret_cast<const float3 *>(p);
 }
 
-// A device pointer read from an instance record is generic to the compiler,
-// so loads through it are flat loads, which also count against the LDS
-// wait counter: waiting for an LDS read then waits for them too.  Loads
-// through the global view are global loads, waited for on their own.
-template <typename T>
-using global_ptr = const __attribute__((address_space(1))) T *;
-template <typename T>
-__device__ __forceinline__ global_ptr<T> as_global(const T *p) {
-    return (global_ptr<T>)p;
-}
-
-// A zero in global memory: a lane with nothing to read loads it, so that
-// loads need no condition and all of a batch go out before the first wait.
-template <typename T>
-__device__ const T kZeroValue = T(0);
-template <typename T>
-__device__ __forceinline__ T load_or_zero(global_ptr<T> p, bool ok) {
-    return *(ok ? p : as_global(&kZeroValue<T>));
-}
-
 // Thread-strided fill of count LDS entries from global memory, U loads in
 // flight per thread: load(e) reads entry e through a global view and is
 // called for every e of a round (indices past the end clamped to the last,
@@ -2174,13 +2154,15 @@ __device__ __forceinline__ void dft_reg(typename Cplx<T>::type (&a)[R]) {
     }
 }
 
-// exp(-2 pi i p / n) from the plan's table of the first n/2 powers
-template <typename C>
-__device__ __forceinline__ C twiddle_pow(const C *__restrict__ tw, int p, int n) {
+// exp(-2 pi i p / n) from the plan's table of the first n/2 powers (real
+// and imaginary parts interleaved), read without a branch: the second half
+// is the first negated
+template <typename C, typename T>
+__device__ __forceinline__ C twiddle_pow(global_ptr<T> tw, int p, int n) {
     p &= n - 1;
-    if (p < n / 2) return tw[p];
-    const C w = tw[p - n / 2];
-    return C{-w.x, -w.y};
+    const int i = p & (n / 2 - 1);
+    const T sgn = p < n / 2 ? T(1) : T(-1);
+    return C{sgn * tw[2 * i], sgn * tw[2 * i + 1]};
 }
 
 // Axis pass for n = R1 R2 = 64, 128 or 256 (R1 = 8 or 16, R2 = 8 or 16):
@@ -2210,8 +2192,9 @@ __global__ __launch_bounds__(kBlock) void convolve4_kernel(const WinInst *__rest
     const Located loc = locate(insts, members, prefix, cnt);
     const WinInst &wi = *loc.w;
     T *__restrict__ grid = static_cast<T *>(wi.grid);
-    const T *__restrict__ bconv = static_cast<const T *>(wi.bconv);
-    const C *__restrict__ tw = static_cast<const C *>(wi.twiddle);
+    const global_ptr<T> gg = as_global(static_cast<const T *>(grid));
+    const global_ptr<T> bconv = as_global(static_cast<const T *>(wi.bconv));
+    const global_ptr<T> tw = as_global(static_cast<const T *>(wi.twiddle));
     int nlines = 1;
     for (int d = 1; d < wi.dA; ++d) nlines *= n;
     const int ls = LOGN * axis;  // stride s = n^axis = 2^ls
@@ -2236,12 +2219,12 @@ __global__ __launch_bounds__(kBlock) void convolve4_kernel(const WinInst *__rest
 #pragma unroll
     for (int u2 = 0; u2 < R2; ++u2) {
         const size_t off = (size_t)(t + R1 * u2) * s;
-        a[u2] = C{in0 ? grid[b0 + off] : T(0), in1 ? grid[b1 + off] : T(0)};
+        a[u2] = C{load_or_zero(gg + (b0 + off), in0), load_or_zero(gg + (b1 + off), in1)};
     }
     dft_reg<T, R2, false>(a);
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2) {
-        const C w = twiddle_pow(tw, t * k2, n);
+        const C w = twiddle_pow<C>(tw, t * k2, n);
         const C v = a[k2];
         xq[t * RS + k2] = C{v.x * w.x - v.y * w.y, v.x * w.y + v.y * w.x};
     }
@@ -2261,7 +2244,7 @@ __global__ __launch_bounds__(kBlock) void convolve4_kernel(const WinInst *__rest
         dft_reg<T, R1, true>(b);
 #pragma unroll
         for (int u1 = 0; u1 < R1; ++u1) {
-            const C w = twiddle_pow(tw, u1 * t, n);  // conjugated below
+            const C w = twiddle_pow<C>(tw, u1 * t, n);  // conjugated below
             const C v = b[u1];
             xq[u1 * RS + t] = C{v.x * w.x + v.y * w.y, v.y * w.x - v.x * w.y};
         }

@@ -88,7 +88,7 @@ __device__ double ms_sum_partials(const double *__restrict__ partial, int nblk, 
     for (int i = threadIdx.x; i < nblk; i += B * kMsBlock) {
         double t[B];
 #pragma unroll
-        for (int u = 0; u < B; ++u) t[u] = i + u * kMsBlock < nblk ? partial[i + u * kMsBlock] : 0.0;
+        for (int u = 0; u < B; ++u) t[u] = load_or_zero(as_global(partial) + (i + u * kMsBlock), i + u * kMsBlock < nblk);
 #pragma unroll
         for (int u = 0; u < B; ++u) v += t[u];
     }
