@@ -569,8 +569,19 @@ def serving(args, A):
         "peak_live": st["peak_live"], "budget_gb": args.serve_budget_gb,
         "iters_per_round": args.serve_round,
         "peak_reserved_gb": round(st["peak_reserved_bytes"] / 2**30, 3),
-        "statuses": statuses, "cg_iters_median": int(np.median(iters)) if iters else None,
+        "statuses": statuses, "errors": error_counts(srv),
+        "cg_iters_median": int(np.median(iters)) if iters else None,
     }
+
+
+def error_counts(srv):
+    """Requests that did not end OK, by status and message."""
+    out = {}
+    for r in srv.results.values():
+        if r.status != "OK":
+            key = f"{r.status}: {r.error[:160]}" if r.error else r.status
+            out[key] = out.get(key, 0) + 1
+    return out
 
 
 SWEEP_LOADS = (0.25, 0.5, 0.75, 0.9, 1.0, 1.2)
@@ -600,7 +611,7 @@ def serving_sweep(args, A):
                      "p50_ms": round(st["p50_s"] * 1e3, 2), "p99_ms": round(st["p99_s"] * 1e3, 2),
                      "mean_ms": round(st["mean_s"] * 1e3, 2),
                      "solves_per_s": round(st["solves_per_s"], 3), "peak_live": st["peak_live"],
-                     "ok": ok})
+                     "ok": ok, "not_ok": error_counts(srv)})
         print(f"# serving sweep: {json.dumps(rows[-1])}", file=sys.stderr, flush=True)
     return {"workload": f"{R} KRR solves per rate: N uniform in [1000, {args.sweep_n_hi}], "
                         "d in {6,9,12}, ell uniform in [0.1, 0.4], beta=1, 1-8 RHS, fp32 NFFT + "

@@ -1243,10 +1243,33 @@ static anova_status make_plan(anova_plan_t *out, const Points &X, int32_t d,
                 ANOVA_REQUIRE(prm->reg_q == 0 || c.h > 2.0 * D,
                               "with reg_q, h must exceed twice the extent of the points");
             }
+            // the candidates fit the budget before the window polynomials'
+            // fit error, which building adds: a candidate whose total then
+            // exceeds the window's share of the target is passed over
+            const double share = std::fabs(w.eta) * budget;
+            auto build_choice = [&](WindowPlan &v, const Choice &c, int cap) {
+                v.dA = w.dA; v.eta = w.eta; v.extent = w.extent;
+                v.launch_windows = w.launch_windows;  // chunks as in the full plan
+                v.tile_cap = cap;
+                for (int t = 0; t < 3; ++t) v.feat[t] = w.feat[t];
+                set_centers(v, c, lo, hi, *prm);
+                apply_choice(v, c, *prm);
+                build_for(v, X, prm->precision);
+                return v.err_total <= share;
+            };
+            // first candidate that fits once built (the last one otherwise,
+            // for the plan's final check to report)
+            auto build_first_fit = [&]() {
+                for (size_t k = 0; k < cands.size(); ++k) {
+                    WindowPlan v;
+                    if (build_choice(v, cands[k], 0) || k + 1 == cands.size()) {
+                        w = std::move(v);
+                        return;
+                    }
+                }
+            };
             if (prm->tune == 0 || cands.size() == 1) {
-                set_centers(w, cands.front(), lo, hi, *prm);
-                apply_choice(w, cands.front(), *prm);
-                build_for(w, X, prm->precision);
+                build_first_fit();
                 continue;
             }
             // measured choice: build the cheapest candidates (model cost
@@ -1269,13 +1292,7 @@ static anova_status make_plan(anova_plan_t *out, const Points &X, int32_t d,
                     one.ell = prm->ell; one.device = p->device;
                     one.win.resize(1);
                     WindowPlan &v = one.win[0];
-                    v.dA = w.dA; v.eta = w.eta; v.extent = w.extent;
-                    v.launch_windows = w.launch_windows;  // chunks as in the full plan
-                    v.tile_cap = cap;
-                    for (int t = 0; t < 3; ++t) v.feat[t] = w.feat[t];
-                    set_centers(v, cands[k], lo, hi, *prm);
-                    apply_choice(v, cands[k], *prm);
-                    build_for(v, X, prm->precision);
+                    if (!build_choice(v, cands[k], cap)) break;  // both variants share the estimate
                     const double t =
                         time_window(one, tune_alpha.as<double>(), tune_out.as<double>(), P);
                     const bool halve = !v.dense && v.tile > 2;
@@ -1288,6 +1305,7 @@ static anova_status make_plan(anova_plan_t *out, const Points &X, int32_t d,
                     cap = tile / 2;
                 }
             }
+            if (best_t == std::numeric_limits<double>::infinity()) build_first_fit();
         }
         if (prm->precision == ANOVA_FP32_NFFT && prm->residual == ANOVA_RESIDUAL_FP64) {
             // the same windows and parameters in float64, for CG's residuals

@@ -83,3 +83,26 @@ def test_device_plan_rejects_non_finite_points(A):
             A.anova_fastsum_plan(dev_rows(X), p.windows, A.make_params(p.ell, F32))
         assert ei.value.status == A.ANOVA_E_INVALID
         assert "non-finite" in str(ei.value)
+
+
+def test_served_mix_plans_within_target(A):
+    """Every request of the served mix (300 requests: N up to 5e4, d in
+    {6, 9, 12}, ell in [0.1, 0.4]) plans within its 1e-4 per-entry target.
+    Building a window adds the error of its window polynomials to the
+    estimate that chose its parameters; a candidate that fits the budget
+    before that addition but not after it is passed over for the next one,
+    instead of failing the request."""
+    import torch
+    reqs = workloads.serving_stream(300, rate=1.0, n_hi=50_000)
+    worst = 0.0
+    for r in reqs:
+        p = r.problem
+        X = torch.from_numpy(np.ascontiguousarray(p.X)).cuda()
+        plan = A.anova_fastsum_plan(X, p.windows, A.make_params(p.ell, F32, target_err=1e-4))
+        try:
+            e = plan.err_estimate()
+        finally:
+            plan.destroy()
+        assert e <= 1e-4, (r.rid, e)
+        worst = max(worst, e)
+    print(f"largest estimate over the mix {worst:.6e}")
