@@ -528,6 +528,12 @@ template <typename T>
 __device__ __forceinline__ global_ptr<T> as_global(const T *p) {
     return (global_ptr<T>)p;
 }
+template <typename T>
+using global_mut_ptr = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ global_mut_ptr<T> as_global_mut(T *p) {
+    return (global_mut_ptr<T>)p;
+}
 
 // A zero in global memory: a lane with nothing to read loads it, so that
 // loads need no condition and all of a batch go out before the first wait.

@@ -160,6 +160,12 @@ __device__ __forceinline__ void fill_lds(int count, int nthreads, Load load, Sto
     }
 }
 
+// Offsets of float32 node record k through a global view of the records.
+__device__ __forceinline__ float3 node_offsets(global_ptr<float> nf, int k) {
+    const size_t b = 4 * (size_t)k;
+    return make_float3(nf[b], nf[b + 1], nf[b + 2]);
+}
+
 // Periodic index on a grid of n points: n is a power of two (the plan
 // requires it), so the two's-complement mask also wraps negative g.
 __device__ __forceinline__ int wrap_index(int g, int n) { return g & (n - 1); }
@@ -598,11 +604,18 @@ __global__ __launch_bounds__(kBlock) void gather_cell_kernel(const WinInst *__re
         for (int b = 0; b < WY; ++b)
 #pragma unroll
             for (int i = 0; i < W; ++i) g[c][b][i] = g_lds[((lz + c) * L + ly + b) * L + lx + i];
-    // the next point's offsets load while the current one is interpolated
-    float3 r_n = node_offsets(nodes + c0);
+    // the next point's offsets and caller index load while the current one
+    // is interpolated (no condition: past the end the last point again;
+    // global views, so that nothing waits for them before their use)
+    const global_ptr<float> nf = as_global(reinterpret_cast<const float *>(nodes));
+    const global_ptr<int32_t> perm = as_global(wi.perm);
+    float3 r_n = node_offsets(nf, c0);
+    int q_n = perm[c0];
     for (int j = c0; j < c1; j += S) {
         const float3 r = r_n;
-        if (j + S < c1) r_n = node_offsets(nodes + j + S);
+        const int q = q_n;
+        r_n = node_offsets(nf, min(j + S, c1 - 1));
+        q_n = perm[min(j + S, c1 - 1)];
         float wx[W], wy[W], wz[W];
         wp.eval(r.x, wx);
         if constexpr (DA >= 2) wp.eval(r.y, wy);
@@ -620,7 +633,7 @@ __global__ __launch_bounds__(kBlock) void gather_cell_kernel(const WinInst *__re
             }
             acc = DA == 3 ? fmaf(sc, wz[c], acc) : sc;
         }
-        tmp[wi.perm[j]] = acc;  // caller order
+        as_global_mut(tmp)[q] = acc;  // caller order
     }
 }
 
