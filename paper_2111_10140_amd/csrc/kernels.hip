@@ -2337,20 +2337,24 @@ __global__ __launch_bounds__(kBlock) void convolve_plane_kernel(const WinInst *_
                                                                 const int32_t *__restrict__ prefix,
                                                                 int cnt) {
     constexpr int n = 1 << LOGN, NN = n * n;
-    __shared__ T a[NN], b[NN], c[n];
+    __shared__ T a[NN], b[NN];
     const Located loc = locate(insts, members, prefix, cnt);
     const WinInst &wi = *loc.w;
     T *__restrict__ plane = static_cast<T *>(wi.grid) + (size_t)loc.lb * NN;
     const T *__restrict__ taps = static_cast<const T *>(wi.ctaps);
     const global_ptr<T> gp = as_global(plane);
     fill_lds<(NN + kBlock - 1) / kBlock, T>(NN, kBlock, [&](int e) { return gp[e]; }, [&](int e, T v) { a[e] = v; });
-    if ((int)threadIdx.x < n) c[threadIdx.x] = as_global(taps)[threadIdx.x];
+    // the taps are the same for every lane: scalar registers, so that a
+    // tap costs one LDS read (of the line) instead of two
+    T cr[n];
+#pragma unroll
+    for (int v = 0; v < n; ++v) cr[v] = taps[v];
     __syncthreads();
-    for (int e = threadIdx.x; e < NN; e += kBlock) {  // along x
+    for (int e = threadIdx.x; e < NN; e += kBlock) {  // along x: sum_v c_v a[x - v]
         const int x = e & (n - 1), row = e - x;
         T acc = T(0);
 #pragma unroll
-        for (int u = 0; u < n; ++u) acc += c[(x - u) & (n - 1)] * a[row + u];
+        for (int v = 0; v < n; ++v) acc += cr[v] * a[row + ((x - v) & (n - 1))];
         b[e] = acc;
     }
     __syncthreads();
@@ -2358,7 +2362,7 @@ __global__ __launch_bounds__(kBlock) void convolve_plane_kernel(const WinInst *_
         const int x = e & (n - 1), y = e >> LOGN;
         T acc = T(0);
 #pragma unroll
-        for (int v = 0; v < n; ++v) acc += c[(y - v) & (n - 1)] * b[v * n + x];
+        for (int v = 0; v < n; ++v) acc += cr[v] * b[((y - v) & (n - 1)) * n + x];
         plane[e] = acc;
     }
 }
@@ -2369,7 +2373,7 @@ __global__ __launch_bounds__(kBlock) void convolve_z_kernel(const WinInst *__res
                                                             const int32_t *__restrict__ prefix,
                                                             int cnt) {
     constexpr int n = 1 << LOGN, NN = n * n;
-    __shared__ T a[NN], c[n];  // a[z][x]
+    __shared__ T a[NN];  // a[z][x]
     const Located loc = locate(insts, members, prefix, cnt);
     const WinInst &wi = *loc.w;
     T *__restrict__ col = static_cast<T *>(wi.grid) + (size_t)loc.lb * n;  // y = workgroup
@@ -2378,13 +2382,15 @@ __global__ __launch_bounds__(kBlock) void convolve_z_kernel(const WinInst *__res
     fill_lds<(NN + kBlock - 1) / kBlock, T>(
         NN, kBlock, [&](int e) { return gc[(size_t)(e >> LOGN) * NN + (e & (n - 1))]; },
         [&](int e, T v) { a[e] = v; });
-    if ((int)threadIdx.x < n) c[threadIdx.x] = as_global(taps)[threadIdx.x];
+    T cr[n];  // taps in scalar registers, as in the plane pass
+#pragma unroll
+    for (int v = 0; v < n; ++v) cr[v] = taps[v];
     __syncthreads();
     for (int e = threadIdx.x; e < NN; e += kBlock) {
         const int x = e & (n - 1), z = e >> LOGN;
         T acc = T(0);
 #pragma unroll
-        for (int v = 0; v < n; ++v) acc += c[(z - v) & (n - 1)] * a[v * n + x];
+        for (int v = 0; v < n; ++v) acc += cr[v] * a[((z - v) & (n - 1)) * n + x];
         col[(size_t)z * NN + x] = acc;
     }
 }
