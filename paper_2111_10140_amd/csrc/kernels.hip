@@ -1901,7 +1901,9 @@ __global__ __launch_bounds__(kBlock) void tile_sum_kernel(const WinInst *__restr
     const int e = (loc.lb % per) * kBlock + threadIdx.x;
     if (e >= vol) return;
     const global_ptr<T> priv = as_global(static_cast<const T *>(wi.priv));
-    const int s0 = wi.src_sub[k], s1 = wi.src_sub[k + 1];
+    // the tile's regions (per-cell windows: chunks k K .. k K + K - 1, no load)
+    const int s0 = wi.chunks > 0 ? k * wi.chunks : wi.src_sub[k];
+    const int s1 = wi.chunks > 0 ? s0 + wi.chunks : wi.src_sub[k + 1];
     // regions in order, their loads issued eight at a time (a missing one as +0)
     constexpr int B = 8;
     double s = 0.0;
