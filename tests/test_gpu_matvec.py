@@ -181,7 +181,7 @@ def test_operator_symmetry(A):
 
 @pytest.mark.parametrize("precision,N,tol,per_cell", [
     (F64, 700, 1e-9, 0),      # per-point kernel, float64
-    (F32, 20000, 2e-5, 1),    # wide per-cell kernel (W = 12), tile-blocked regions
+    (F32, 20000, 2e-5, 1),    # matrix-core per-tile kernel (W = 12)
 ])
 def test_stage_spread_matches_adjoint_ndft(A, precision, N, tol, per_cell):
     # the spread grid, transformed by numpy's FFT and divided by the window

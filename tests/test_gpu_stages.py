@@ -123,9 +123,9 @@ def hermitian_coefficients(rng, M, d):
 
 @pytest.mark.parametrize("precision,N,d,M,n,m,h,per_cell", [
     (F64, 700, 3, 16, 32, 6, 1.0, 0),        # per-point kernel, float64
-    (F32, 20000, 3, 16, 32, 6, 1.0, 1),      # wide per-cell kernel (W = 12)
+    (F32, 20000, 3, 16, 32, 6, 1.0, 1),      # matrix-core per-tile kernel (W = 12)
     (F32, 20000, 3, 16, 32, 3, 1.3334, 1),   # the headline's per-cell kernel (W = 6)
-    (F32, 400000, 3, 64, 128, 6, 1.3334, 1),  # the paper's parameters, wide kernel
+    (F32, 400000, 3, 64, 128, 6, 1.3334, 1),  # the paper's parameters, matrix-core kernel
     (F32, 3000, 2, 16, 32, 4, 1.0, None),    # 2-D
     (F64, 500, 1, 24, 64, 5, 1.0, 0),        # 1-D, float64
 ])
