@@ -435,3 +435,31 @@ def test_captured_product_replays_equal_eager(A, kw):
     A.anova_matvec(plan, a, out, p.beta)
     torch.cuda.synchronize()
     assert torch.equal(out, ref)
+
+
+@pytest.mark.parametrize("kw", [dict(M=12, n=16, m=6), dict(M=16, n=32, m=6)])
+def test_matrix_core_kernels_crowded_and_lone_points(A, kw):
+    # 12-point supports (the matrix-core per-tile kernels) on a tight cluster
+    # of 150000 points, whose few tiles hold tens of thousands of points each
+    # (many staging rounds per wave, several chunks per tile), plus 300
+    # points scattered over the box, most alone in their tile (z layers and
+    # steps with no or one point); sampled rows of both kinds against the
+    # oracle, and a repeated product bit for bit
+    rng = np.random.default_rng(51)
+    X = np.concatenate([rng.uniform(0.0, 0.03, size=(150_000, 3)),
+                        rng.uniform(-0.25, 0.25, size=(300, 3))])
+    a = rng.standard_normal(X.shape[0])
+    p = workloads.Problem("cluster_and_scatter", X, [workloads.Window((0, 1, 2), 1.0)], 0.3, 1.0,
+                          np.asfortranarray(a[:, None]), np.asfortranarray(a[:, None]))
+    plan = make_plan(A, p, F32, **kw)
+    assert plan.info(0).per_cell == 1
+    out = gpu_matvec(A, plan, a, p.beta)
+    assert np.array_equal(out, gpu_matvec(A, plan, a, p.beta))
+    rows = np.concatenate([np.random.default_rng(52).choice(150_000, 32, replace=False),
+                           150_000 + np.arange(0, 300, 10)])
+    ref = oracle.direct.anova_matvec(p.X, p.windows, p.ell, p.beta, a, rows=rows)
+    e = float(np.max(np.abs(out[rows] - ref)) / np.abs(a).sum())
+    rel = float(np.max(np.abs(out[rows] - ref)) / np.max(np.abs(ref)))
+    print(f"{kw}: sampled-row E = {e:.3e}, relative {rel:.3e}, estimate {plan.err_estimate():.3e}")
+    assert e <= plan.err_estimate()
+    assert rel <= 1e-4
