@@ -1542,14 +1542,6 @@ __device__ __forceinline__ void mfma_wave_share(const MfmaTile &t, int wv, int S
     q1 = min(t.c1, t.c0 + S * (steps * (wv + 1) / NWV));
 }
 
-template <int B, int E, typename F>
-__device__ __forceinline__ void static_for(F &&f) {
-    if constexpr (B < E) {
-        f(std::integral_constant<int, B>{});
-        static_for<B + 1, E>(f);
-    }
-}
-
 // Spreading: wave wv takes the points of the tile's cell layer wv (cells
 // 16 wv .. 16 wv + 15, their chunk's share), whose z supports all start at
 // plane wv, so its steps touch W planes at constant indices.
