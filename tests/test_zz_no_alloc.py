@@ -82,3 +82,21 @@ def test_noalloc_refuses_oversized_work_space(A):
     o1, r1 = _both(A, plan, p.alpha[:, 0], p.beta)
     assert np.array_equal(o1, r1)
     plan.destroy()
+
+
+def test_noalloc_matrix_core_kernels(A):
+    # 12-point supports (the paper's M = 64, m = 6, n = 128) on clustered
+    # points, so that the windows run the matrix-core per-tile kernels, whose
+    # regions then live in the static work space; two calls, the second on
+    # a smaller problem, each bit for bit equal to the allocating product
+    for N, seed in ((40_000, 61), (12_000, 62)):
+        rng = np.random.default_rng(seed)
+        X = np.ascontiguousarray(rng.uniform(0.0, 0.1, size=(N, 3)))
+        a = rng.standard_normal(N)
+        print(f"noalloc matrix-core: N={N}", flush=True)
+        plan = A.anova_fastsum_plan(dev_rows(X), [workloads.Window((0, 1, 2), 1.0)],
+                                    A.make_params(0.2, F32, M=64, m=6, n=128))
+        assert plan.info(0).per_cell == 1 and plan.info(0).m == 6
+        out, ref = _both(A, plan, a, 1.0)
+        assert np.array_equal(out, ref), float(np.max(np.abs(out - ref)))
+        plan.destroy()
