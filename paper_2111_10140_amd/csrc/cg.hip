@@ -380,6 +380,37 @@ static void record_iteration(StepGraph &G, bool replace, hipStream_t s) {
     ANOVA_HIP_CHECK(hipGetLastError());
 }
 
+static Batch &residual_batch(anova_cg_s *sv);
+
+// An iteration in which only some solves of the list recompute their
+// residual.  The others' columns would discard the product x -> q, so it
+// runs for the due solves alone (each its own batch, as when it runs by
+// itself); the launches are direct, since the due subset changes from one
+// such iteration to the next.  The columns that are not due keep the r.r
+// partials that the x, r update wrote, and the scalar update replaces
+// only where the period is due, so every column takes the same steps as
+// in a list whose members are all due or all not.
+static void record_subset_replace(StepGraph &G, anova_cg_s *const *solves, int count,
+                                  hipStream_t s) {
+    const ColList &L = G.list;
+    const CgCol *dc = L.d_cols.as<CgCol>();
+    const int32_t *dp = L.d_prefix.as<int32_t>();
+    G.pq.run(s);
+    hipLaunchKernelGGL(cg_alpha_kernel, dim3(L.cnt), dim3(kRedBlock), 0, s, dc);
+    hipLaunchKernelGGL(cg_update_xr_kernel, dim3(L.blocks), dim3(kRedBlock), 0, s, dc, dp, L.cnt);
+    for (int i = 0; i < count; ++i) {
+        anova_cg_s *sv = solves[i];
+        if ((sv->it + 1) % sv->period != 0) continue;
+        residual_batch(sv).run(s);
+        hipLaunchKernelGGL(cg_replace_kernel, dim3(sv->own.blocks), dim3(kRedBlock), 0, s,
+                           sv->own.d_cols.as<CgCol>(), sv->own.d_prefix.as<int32_t>(),
+                           sv->own.cnt, 0);
+    }
+    hipLaunchKernelGGL(cg_beta_kernel, dim3(L.cnt), dim3(kRedBlock), 0, s, dc, 1);
+    hipLaunchKernelGGL(cg_update_p_kernel, dim3(L.blocks), dim3(kRedBlock), 0, s, dc, dp, L.cnt);
+    ANOVA_HIP_CHECK(hipGetLastError());
+}
+
 // Iterations replayed by one graph launch when none of them recomputes a
 // residual: consecutive launches of separate graphs leave a gap of several
 // microseconds between them, which a longer graph pays once.
@@ -426,6 +457,20 @@ static BatchProblem product(anova_cg_s *sv, const double *in, bool residual) {
     bp.beta = sv->beta;
     bp.work = sv->work.ptr;  // products of one solve run one after another on its stream
     return bp;
+}
+
+// The product q = (K~ + beta I) x of one solve alone (its residual
+// recomputation), built on first use.
+static Batch &residual_batch(anova_cg_s *sv) {
+    if (!sv->xq) {
+        BatchProblem bp = product(sv, sv->x, true);
+        bp.ld = sv->ld;     // x columns follow the caller's leading dimension
+        bp.ld_out = sv->N;  // q is packed
+        std::unique_ptr<Batch> b(new Batch());
+        b->build({bp});
+        sv->xq = std::move(b);
+    }
+    return *sv->xq;
 }
 
 static StepGraph &step_graph(anova_cg_s *const *solves, int count) {
@@ -615,10 +660,15 @@ extern "C" anova_status krr_cg_iterate(anova_cg_t *solves, int32_t count, int32_
                 k += kGraphIters;
                 continue;
             }
-            bool rep = false;
-            for (int i = 0; i < count; ++i)
-                rep = rep || (solves[i]->it + 1) % solves[i]->period == 0;
-            if (direct)
+            bool rep = false, all_due = true;
+            for (int i = 0; i < count; ++i) {
+                const bool due = (solves[i]->it + 1) % solves[i]->period == 0;
+                rep = rep || due;
+                all_due = all_due && due;
+            }
+            if (rep && !all_due)
+                record_subset_replace(G, solves, count, s);
+            else if (direct)
                 record_iteration(G, rep, s);
             else
                 ANOVA_HIP_CHECK(hipGraphLaunch(graph_for(G, rep, false), s));
@@ -666,21 +716,7 @@ extern "C" anova_status krr_cg_finish(anova_cg_t sv, krr_cg_info *info, void *st
         ANOVA_REQUIRE(sv != nullptr, "NULL solve");
         hipStream_t s = (hipStream_t)stream;
         // true residual r = y - (K~ + beta I) x for every column
-        if (!sv->xq) {
-            sv->xq.reset(new Batch());
-            BatchProblem bp;
-            bp.plan = sv->plan;
-            bp.alpha = sv->x;
-            bp.out = sv->q.as<double>();
-            bp.nrhs = sv->nrhs;
-            bp.ld = sv->ld;
-            bp.ld_out = sv->N;
-            bp.beta = sv->beta;
-            bp.work = sv->work.ptr;
-            bp.residual = true;
-            sv->xq->build({bp});
-        }
-        sv->xq->run(s);
+        residual_batch(sv).run(s);
         hipLaunchKernelGGL(cg_replace_kernel, dim3(sv->own.blocks), dim3(kRedBlock), 0, s,
                            sv->own.d_cols.as<CgCol>(), sv->own.d_prefix.as<int32_t>(),
                            sv->own.cnt, 1);
