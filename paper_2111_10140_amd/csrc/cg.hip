@@ -474,8 +474,8 @@ static Batch &residual_batch(anova_cg_s *sv) {
 }
 
 static StepGraph &step_graph(anova_cg_s *const *solves, int count) {
-    // building and capturing must not overlap other threads' allocations
-    std::lock_guard<std::recursive_mutex> dev_lock(device_mutex());
+    // (the list cache is guarded by the caller's lock on the step mutex; a
+    // hit takes no device lock, which planner threads hold while uploading)
     std::vector<uint64_t> ids(count);
     for (int i = 0; i < count; ++i) ids[i] = solves[i]->id;
     for (size_t k = 0; k < g_steps.size(); ++k)
@@ -485,6 +485,8 @@ static StepGraph &step_graph(anova_cg_s *const *solves, int count) {
             g_steps.push_back(std::move(hit));  // most recently used last
             return *g_steps.back();
         }
+    // building and capturing must not overlap other threads' allocations
+    std::lock_guard<std::recursive_mutex> dev_lock(device_mutex());
     std::unique_ptr<StepGraph> G(new StepGraph());
     G->ids = ids;
     G->solves.assign(solves, solves + count);
