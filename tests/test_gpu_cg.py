@@ -169,7 +169,11 @@ def test_batched_solves_equal_alone_bitwise(A, precision):
 
 def test_solves_join_and_leave_the_batch(A):
     # continuous batching: a solve that starts late joins the running list,
-    # and the result equals the same solve run alone
+    # and the result equals the same solve run alone.  The float32 plans'
+    # columns stop only on a recomputed residual (every 50th iteration), so
+    # each solve runs at least 50 iterations and, joining 5 and 12
+    # iterations apart, the list meets iterations in which only some of its
+    # solves recompute their residual
     import torch
     probs = _batched_problems()
     plans = [A.anova_fastsum_plan(dev_rows(p.X), p.windows, A.make_params(p.ell, F32)) for p in probs]
