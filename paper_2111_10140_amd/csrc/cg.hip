@@ -792,21 +792,27 @@ extern "C" anova_status anova_plan_footprint(anova_plan_t plan, int32_t nrhs,
 
 static anova_status solve_lists(int32_t count, anova_cg_t *svs, int32_t check_every,
                                 void *stream) {
-    // iterate until no column is active, reading the flags every few steps
-    std::vector<anova_cg_t> live(svs, svs + count);
-    while (!live.empty()) {
-        anova_status st = krr_cg_iterate(live.data(), (int32_t)live.size(), check_every, stream);
-        if (st != ANOVA_OK) return st;
-        std::vector<anova_cg_t> still;
-        for (anova_cg_t sv : live) {
-            int32_t a = 0;
-            st = krr_cg_poll(sv, &a, nullptr, stream);
+    // iterate until no column is active, reading every solve's count of
+    // active columns every few steps (one kernel and one copy for the list)
+    return guarded_cg([&]() -> anova_status {
+        std::vector<anova_cg_t> live(svs, svs + count);
+        DevBuf dev_counts;
+        dev_counts.alloc(sizeof(int32_t) * (size_t)count);
+        std::vector<int32_t> act(count);
+        while (!live.empty()) {
+            const int32_t n = (int32_t)live.size();
+            anova_status st = krr_cg_iterate(live.data(), n, check_every, stream);
+            if (st == ANOVA_OK)
+                st = krr_cg_active(live.data(), n, dev_counts.as<int32_t>(), act.data(), stream);
             if (st != ANOVA_OK) return st;
-            if (a > 0) still.push_back(sv);
+            ANOVA_HIP_CHECK(hipStreamSynchronize((hipStream_t)stream));
+            std::vector<anova_cg_t> still;
+            for (int32_t i = 0; i < n; ++i)
+                if (act[i] > 0) still.push_back(live[i]);
+            live.swap(still);
         }
-        live.swap(still);
-    }
-    return ANOVA_OK;
+        return ANOVA_OK;
+    });
 }
 
 extern "C" anova_status krr_cg_solve(anova_plan_t plan, const double *y, double *alpha,
