@@ -793,7 +793,10 @@ extern "C" anova_status anova_plan_footprint(anova_plan_t plan, int32_t nrhs,
 static anova_status solve_lists(int32_t count, anova_cg_t *svs, int32_t check_every,
                                 void *stream) {
     // iterate until no column is active, reading every solve's count of
-    // active columns every few steps (one kernel and one copy for the list)
+    // active columns every few steps (one kernel and one copy for the list).
+    // Columns that stop only on a recomputed residual (one list shares the
+    // residual mode) can stop only at their period or at maxit, so their
+    // counts are read there.
     return guarded_cg([&]() -> anova_status {
         std::vector<anova_cg_t> live(svs, svs + count);
         DevBuf dev_counts;
@@ -801,7 +804,15 @@ static anova_status solve_lists(int32_t count, anova_cg_t *svs, int32_t check_ev
         std::vector<int32_t> act(count);
         while (!live.empty()) {
             const int32_t n = (int32_t)live.size();
-            anova_status st = krr_cg_iterate(live.data(), n, check_every, stream);
+            int64_t iters = check_every;
+            if (live[0]->exact_only) {
+                iters = INT64_MAX;
+                for (anova_cg_t sv : live) {
+                    iters = std::min<int64_t>(iters, sv->period - sv->it % sv->period);
+                    if (sv->maxit > sv->it) iters = std::min<int64_t>(iters, sv->maxit - sv->it);
+                }
+            }
+            anova_status st = krr_cg_iterate(live.data(), n, (int32_t)iters, stream);
             if (st == ANOVA_OK)
                 st = krr_cg_active(live.data(), n, dev_counts.as<int32_t>(), act.data(), stream);
             if (st != ANOVA_OK) return st;
