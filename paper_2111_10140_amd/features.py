@@ -53,9 +53,18 @@ def quantile_bins(x: np.ndarray, n_bins: int) -> np.ndarray:
     feature carries no information about where its rows sit."""
     x = np.asarray(x)
     N = x.shape[0]
-    srt = np.sort(x, kind="stable")
-    ranks = np.searchsorted(srt, x, side="left").astype(np.int64)
-    return (ranks * n_bins) // max(N, 1)
+    if N == 0:
+        return np.zeros(0, dtype=np.int64)
+    order = np.argsort(x, kind="stable")
+    srt = x[order]
+    # a value's rank is the sorted position where its run of equal values starts
+    starts = np.empty(N, dtype=bool)
+    starts[0] = True
+    np.not_equal(srt[1:], srt[:-1], out=starts[1:])
+    run_start = np.maximum.accumulate(np.where(starts, np.arange(N, dtype=np.int64), 0))
+    ranks = np.empty(N, dtype=np.int64)
+    ranks[order] = run_start
+    return (ranks * n_bins) // N
 
 
 def default_bins(N: int) -> int:
@@ -73,6 +82,18 @@ def _labels(y: np.ndarray, n_bins: int) -> np.ndarray:
     return quantile_bins(y, n_bins)
 
 
+def _binned_mi(bx: np.ndarray, cy: np.ndarray, B: int, C: int) -> float:
+    """Plug-in mutual information (nats) of bin indices bx in [0, B) and
+    label indices cy in [0, C) from their joint counts."""
+    N = bx.shape[0]
+    joint = np.bincount(bx * C + cy, minlength=B * C).reshape(B, C).astype(np.float64)
+    pj = joint / N
+    pb = pj.sum(axis=1, keepdims=True)
+    pc = pj.sum(axis=0, keepdims=True)
+    nz = pj > 0
+    return float(np.sum(pj[nz] * np.log(pj[nz] / (pb @ pc)[nz])))
+
+
 def mutual_information(x: np.ndarray, y: np.ndarray, n_bins: int = 0) -> float:
     """Plug-in mutual information (nats) between feature values x and labels
     y after cutting x into n_bins quantile bins (0: default_bins(N))."""
@@ -81,22 +102,21 @@ def mutual_information(x: np.ndarray, y: np.ndarray, n_bins: int = 0) -> float:
     if N == 0:
         return 0.0
     B = n_bins or default_bins(N)
-    bx = quantile_bins(x, B)
     cy = _labels(y, B)
-    C = int(cy.max()) + 1
-    joint = np.zeros((B, C), dtype=np.float64)
-    np.add.at(joint, (bx, cy), 1.0)
-    pj = joint / N
-    pb = pj.sum(axis=1, keepdims=True)
-    pc = pj.sum(axis=0, keepdims=True)
-    nz = pj > 0
-    return float(np.sum(pj[nz] * np.log(pj[nz] / (pb @ pc)[nz])))
+    return _binned_mi(quantile_bins(x, B), cy, B, int(cy.max()) + 1)
 
 
 def mis_scores(X: np.ndarray, y: np.ndarray, n_bins: int = 0) -> np.ndarray:
-    """Mutual information score of every feature (column) of X with y."""
+    """Mutual information score of every feature (column) of X with y (the
+    labels are binned once for all features)."""
     X = np.asarray(X, dtype=np.float64)
-    return np.array([mutual_information(X[:, j], y, n_bins) for j in range(X.shape[1])])
+    N = X.shape[0]
+    if N == 0:
+        return np.zeros(X.shape[1])
+    B = n_bins or default_bins(N)
+    cy = _labels(y, B)
+    C = int(cy.max()) + 1
+    return np.array([_binned_mi(quantile_bins(X[:, j], B), cy, B, C) for j in range(X.shape[1])])
 
 
 def group_windows(scores: Sequence[float], threshold: float = 0.0,
